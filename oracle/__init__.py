@@ -1,0 +1,224 @@
+"""CPU oracle of the per-frame tile-and-depth sort (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+this package never imports the product: the two share no code.  Inputs come
+from ``synth`` (seeded records only).
+
+The arithmetic lives in ``oracle.cpp`` (plain C++, one thread); this module
+builds it with g++ and wraps it with numpy arrays.  ``sort_batch`` composes
+single-frame results into the batched layout (frame-major pairs, global tile
+ids ``tile_base[f] + t``, frame-local values, global ranges).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.cpp")
+
+OK, ERR_INVALID_ARGUMENT, ERR_CAPACITY, ERR_OVERFLOW, ERR_INVALID_INPUT = 0, 1, 3, 4, 5
+
+
+def build(src: str = SRC_PATH, out: str = LIB_PATH, extra=()) -> str:
+    """Compile the oracle into a shared library (g++, C++17)."""
+    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-I", HERE, *extra, src, "-o", out + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("tile_px", ctypes.c_uint32), ("num_gaussians", ctypes.c_uint32),
+                ("gaussians", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        build(out=path)
+    lib = ctypes.CDLL(path)
+    fp = ctypes.POINTER(_Frame)
+    lib.oracle_tile_grid.argtypes = [fp, _P, _P]
+    lib.oracle_count.argtypes = [fp, _P, _P]
+    lib.oracle_scan.argtypes = [_P, ctypes.c_uint32, _P, _P]
+    lib.oracle_duplicate.argtypes = [fp, _P, _U64, _P, _P]
+    lib.oracle_sort.argtypes = [_P, _P, _U64]
+    lib.oracle_ranges.argtypes = [_P, _U64, _U64, _P]
+    lib.oracle_sort_frame.argtypes = [fp, _U64, _P, _P, _P, _P, _P, _P, _P, _P]
+    for f in (lib.oracle_tile_grid, lib.oracle_count, lib.oracle_scan, lib.oracle_duplicate,
+              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame):
+        f.restype = ctypes.c_int
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _frame(width: int, height: int, records: np.ndarray, tile_px: int = 16) -> _Frame:
+    rec = np.ascontiguousarray(records)
+    assert rec.dtype.itemsize == 16
+    return _Frame(width, height, tile_px, len(rec), rec.ctypes.data if len(rec) else None), rec
+
+
+@dataclasses.dataclass
+class FrameResult:
+    status: int
+    tiles_x: int
+    tiles_y: int
+    num_pairs: int
+    tiles_touched: np.ndarray
+    offsets: np.ndarray
+    unsorted_keys: np.ndarray
+    unsorted_values: np.ndarray
+    keys: np.ndarray
+    values: np.ndarray
+    ranges: np.ndarray     # (T, 2) uint32
+
+    @property
+    def num_tiles(self) -> int:
+        return self.tiles_x * self.tiles_y
+
+
+def tile_grid(width: int, height: int, tile_px: int = 16):
+    fr, _ = _frame(width, height, np.zeros(0, dtype=np.dtype((np.void, 16))), tile_px)
+    tx, ty = ctypes.c_uint32(), ctypes.c_uint32()
+    st = lib().oracle_tile_grid(ctypes.byref(fr), ctypes.addressof(tx), ctypes.addressof(ty))
+    if st != OK:
+        raise ValueError(f"invalid frame geometry {width}x{height}/{tile_px}")
+    return tx.value, ty.value
+
+
+def count(width: int, height: int, records: np.ndarray, tile_px: int = 16):
+    """Step a1 alone: (tiles_touched[N], rects[N,4] = x0, x1, y0, y1)."""
+    fr, rec = _frame(width, height, records, tile_px)
+    n = len(rec)
+    cnt = np.zeros(n, np.uint32)
+    rects = np.zeros((n, 4), np.uint32)
+    st = lib().oracle_count(ctypes.byref(fr), _ptr(cnt), _ptr(rects))
+    if st != OK:
+        raise ValueError(f"oracle_count status {st}")
+    return cnt, rects
+
+
+def scan(counts: np.ndarray):
+    """Step a2 alone: (offsets[N] uint64, total)."""
+    c = np.ascontiguousarray(counts, dtype=np.uint32)
+    off = np.zeros(len(c), np.uint64)
+    tot = ctypes.c_uint64()
+    st = lib().oracle_scan(_ptr(c), len(c), _ptr(off), ctypes.addressof(tot))
+    assert st == OK
+    return off, tot.value
+
+
+def sort_pairs(keys: np.ndarray, values: np.ndarray):
+    """Step a4 alone on copies: stable sort by the 64-bit key."""
+    k = np.array(keys, dtype=np.uint64, copy=True)
+    v = np.array(values, dtype=np.uint32, copy=True)
+    assert lib().oracle_sort(_ptr(k), _ptr(v), len(k)) == OK
+    return k, v
+
+
+def ranges(sorted_keys: np.ndarray, num_tiles: int) -> np.ndarray:
+    """Step a5 alone: (T, 2) start/end."""
+    k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    r = np.zeros((num_tiles, 2), np.uint32)
+    st = lib().oracle_ranges(_ptr(k), len(k), num_tiles, _ptr(r))
+    if st != OK:
+        raise ValueError(f"oracle_ranges status {st}")
+    return r
+
+
+def sort_frame(width: int, height: int, records: np.ndarray, tile_px: int = 16,
+               capacity: Optional[int] = None, stages: bool = True) -> FrameResult:
+    """Whole frame, a1..a5.  With ``capacity=None`` the pair buffers are sized
+    to the exact M (a first call counts).  ``stages`` also returns the
+    per-Gaussian counts, offsets and the unsorted a3 order."""
+    fr, rec = _frame(width, height, records, tile_px)
+    n = len(rec)
+    if tile_px != 16 or width < 1 or height < 1:
+        tx = ty = 0
+    else:
+        tx, ty = tile_grid(width, height, tile_px)
+    m_out = ctypes.c_uint64()
+    if capacity is None:
+        cnt = np.zeros(n, np.uint32)
+        st = lib().oracle_count(ctypes.byref(fr), _ptr(cnt), None)
+        if st != OK:
+            return FrameResult(st, tx, ty, 0, *(np.zeros(0),) * 7)
+        capacity = int(cnt.astype(np.uint64).sum())
+        capacity = min(capacity, 0xFFFFFFFF)
+    cap = int(capacity)
+    cnt = np.zeros(n, np.uint32) if stages else None
+    off = np.zeros(n, np.uint64) if stages else None
+    uk = np.zeros(cap, np.uint64) if stages else None
+    uv = np.zeros(cap, np.uint32) if stages else None
+    k = np.zeros(cap, np.uint64)
+    v = np.zeros(cap, np.uint32)
+    r = np.zeros((tx * ty, 2), np.uint32)
+    st = lib().oracle_sort_frame(ctypes.byref(fr), cap, _ptr(cnt), _ptr(off), _ptr(uk), _ptr(uv),
+                                 _ptr(k), _ptr(v), _ptr(r), ctypes.addressof(m_out))
+    m = int(m_out.value)
+    mm = min(m, cap)
+    empty = np.zeros(0)
+    return FrameResult(st, tx, ty, m,
+                       cnt if cnt is not None else empty, off if off is not None else empty,
+                       uk[:mm] if uk is not None else empty, uv[:mm] if uv is not None else empty,
+                       k[:mm], v[:mm], r)
+
+
+@dataclasses.dataclass
+class BatchResult:
+    num_pairs: np.ndarray      # per frame
+    pair_base: np.ndarray      # first pair of each frame
+    tile_base: np.ndarray      # first global tile of each frame
+    keys: np.ndarray           # global tile ids in the high 32 bits
+    values: np.ndarray         # frame-local Gaussian indices
+    ranges: np.ndarray         # (sum T, 2), global pair indices
+
+
+def sort_batch(frames: Sequence[tuple]) -> BatchResult:
+    """Batched layout from single-frame results: frame f's pairs form one
+    contiguous segment starting at the sum of earlier frames' M; its tiles
+    are renumbered tile_base[f] + t with tile_base the exclusive sum of T."""
+    outs: List[FrameResult] = []
+    for (w, h, rec) in frames:
+        res = sort_frame(w, h, rec, stages=False)
+        if res.status != OK:
+            raise ValueError(f"frame status {res.status}")
+        outs.append(res)
+    ms = np.array([o.num_pairs for o in outs], np.uint64)
+    ts = np.array([o.num_tiles for o in outs], np.uint64)
+    pair_base = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.uint64) if outs else np.zeros(0, np.uint64)
+    tile_base = np.concatenate([[0], np.cumsum(ts)[:-1]]).astype(np.uint64) if outs else np.zeros(0, np.uint64)
+    keys, vals, rngs = [], [], []
+    for f, o in enumerate(outs):
+        keys.append(o.keys + (np.uint64(tile_base[f]) << np.uint64(32)))
+        vals.append(o.values)
+        rngs.append(o.ranges.astype(np.uint64) + pair_base[f])
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return BatchResult(ms, pair_base, tile_base, cat(keys, np.uint64), cat(vals, np.uint32),
+                       cat(rngs, np.uint64).reshape(-1, 2).astype(np.uint32))

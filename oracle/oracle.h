@@ -1,0 +1,87 @@
+/* Plain CPU oracle of the per-frame tile-and-depth sort of 3D Gaussian
+ * Splatting.  TEST INFRASTRUCTURE ONLY: the product library never links,
+ * loads or calls it.  Only the tests, the smoke check and the CPU baseline
+ * of the benchmark use it.
+ *
+ * What it computes (paper: Background, "Duplication with Tiles" and
+ * "Sorting"; Design, "Sorting Optimizations in Context of 3DGS"): the list of
+ * all (tile, Gaussian) pairs whose 16x16-pixel tile meets the Gaussian's
+ * axis-aligned bounding box, ordered by tile, then by depth, then by Gaussian
+ * index, as 64-bit keys (tile << 32 | depth bits) with 32-bit index values,
+ * plus each tile's [start, end) range into that list.
+ *
+ * This header defines its own types; it shares nothing with the GPU library.
+ * Status numbers equal the GPU library's status codes so results compare.
+ */
+#ifndef SPLAT_ORACLE_H
+#define SPLAT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORACLE_OK = 0,
+  ORACLE_ERR_INVALID_ARGUMENT = 1,
+  ORACLE_ERR_CAPACITY = 3,
+  ORACLE_ERR_OVERFLOW = 4,
+  ORACLE_ERR_INVALID_INPUT = 5
+};
+
+/* One projected Gaussian: mean in signed 1/16-pixel fixed point, FP32 view
+ * depth, radius in whole pixels (0 = culled).  16 bytes. */
+typedef struct {
+  int32_t mean_x;
+  int32_t mean_y;
+  float depth;
+  uint32_t radius;
+} oracle_gaussian;
+
+typedef struct {
+  uint32_t width;   /* pixels, 1 .. 2^20 */
+  uint32_t height;  /* pixels, 1 .. 2^20 */
+  uint32_t tile_px; /* must be 16 */
+  uint32_t num_gaussians;
+  const oracle_gaussian* gaussians;
+} oracle_frame;
+
+/* a0: tile grid size; partial edge tiles count. */
+int oracle_tile_grid(const oracle_frame* f, uint32_t* tiles_x, uint32_t* tiles_y);
+
+/* a1: per-Gaussian overlap rectangle [x0,x1) x [y0,y1) in tiles and its area.
+ * rects may be NULL; otherwise rects[4g..4g+3] = x0, x1, y0, y1. */
+int oracle_count(const oracle_frame* f, uint32_t* tiles_touched, uint32_t* rects);
+
+/* a2: exclusive prefix sum of the counts, and the total M. */
+int oracle_scan(const uint32_t* counts, uint32_t n, uint64_t* offsets, uint64_t* total);
+
+/* a3: one (key, value) pair per touched tile, Gaussian by Gaussian, tiles of a
+ * Gaussian in row-major order.  keys/values hold m entries. */
+int oracle_duplicate(const oracle_frame* f, const uint64_t* offsets, uint64_t m,
+                     uint64_t* keys, uint32_t* values);
+
+/* a4: stable sort of the pairs by the full 64-bit key, in place. */
+int oracle_sort(uint64_t* keys, uint32_t* values, uint64_t m);
+
+/* a5: ranges[2t], ranges[2t+1] = start, end of tile t in the sorted keys.
+ * Tiles with no pair get start = end = the number of pairs of lower tiles. */
+int oracle_ranges(const uint64_t* keys, uint64_t m, uint64_t num_tiles, uint32_t* ranges);
+
+/* Whole frame: a1..a5.  Any output pointer except num_pairs may be NULL.
+ * keys/values must hold capacity entries; unsorted_* receive the a3 order.
+ * Returns ORACLE_ERR_OVERFLOW if M > 2^32-1, ORACLE_ERR_CAPACITY if
+ * M > capacity (num_pairs is still written), ORACLE_ERR_INVALID_INPUT if a
+ * Gaussian that touches a tile has a depth that is not positive and finite. */
+int oracle_sort_frame(const oracle_frame* f, uint64_t capacity,
+                      uint32_t* tiles_touched, uint64_t* offsets,
+                      uint64_t* unsorted_keys, uint32_t* unsorted_values,
+                      uint64_t* keys, uint32_t* values, uint32_t* ranges,
+                      uint64_t* num_pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,257 @@
+"""Seeded synthetic inputs for the tile-and-depth sort of 3D Gaussian Splatting.
+
+This module only draws input records: projected Gaussians (fixed-point mean,
+FP32 depth, integer radius) for a frame, batches of frames and request
+arrival traces.  It holds none of the sort's arithmetic (no tile overlap, no
+scan, no keys), so both the CPU oracle and the GPU path can take their inputs
+from here without sharing any of the method's code.
+
+The paper's trained scenes (Tanks&Temples Train/Truck, DeepBlending Playroom;
+Evaluation, "Datasets") are not available, so these distributions stand in for
+them.  Image sizes bracket the paper's (980x545 to 1264x832, Evaluation table
+of per-stage latency) and the pair counts span its random key-value sweep
+(0.5M to 17M pairs, Evaluation, "Datasets").
+
+Random numbers
+--------------
+All draws come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based
+generator: element ``i`` of the stream with start state ``s`` is
+``mix64(s + (i + 1) * GOLDEN)``, where ``mix64`` is the published SplitMix64
+output function.  A stream's start state is derived from ``(seed, ids...)`` by
+chaining the same function, so every variable of every frame has its own
+stream and any element can be drawn on its own.  Arithmetic is numpy uint64
+with wrap-around.
+
+Derived variates (documented so the inputs can be reproduced elsewhere):
+
+* uniform double in [0, 1):   ``(x >> 11) * 2**-53``
+* uniform double in (0, 1]:   ``((x >> 11) + 1) * 2**-53``
+* uniform integer in [0, n):  ``((x >> 32) * n) >> 32``  (n < 2**32)
+* standard normal:            Box-Muller, ``sqrt(-2 ln u1) * cos(2 pi u2)`` with
+                              u1 in (0, 1] and u2 in [0, 1)
+* lround(v) for v >= 0:       ``floor(v + 0.5)``
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+
+#: record layout shared by every consumer: 16 bytes, little endian.
+#: mean_x/mean_y: signed 1/16-pixel fixed point; depth: FP32; radius: pixels.
+RECORD_DTYPE = np.dtype([("mean_x", "<i4"), ("mean_y", "<i4"),
+                         ("depth", "<f4"), ("radius", "<u4")])
+assert RECORD_DTYPE.itemsize == 16
+
+#: fixed-point scale of the mean (units per pixel)
+FIXED_POINT = 16
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrap-around arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _mix64_int(z: int) -> int:
+    z &= _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def stream_key(seed: int, *ids: int) -> int:
+    """Start state of the stream named by ``(seed, ids...)``."""
+    k = seed & _MASK64
+    for i in ids:
+        k = _mix64_int(k + ((int(i) + 1) * int(GOLDEN)))
+    return k
+
+
+def raw_u64(key: int, n: int, start: int = 0) -> np.ndarray:
+    """Elements ``start .. start+n-1`` of the SplitMix64 stream ``key``."""
+    idx = np.arange(start + 1, start + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        s = np.uint64(key) + idx * GOLDEN
+    return _mix64(s)
+
+
+def uniform01(key: int, n: int) -> np.ndarray:
+    """Doubles in [0, 1)."""
+    return (raw_u64(key, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform01_open0(key: int, n: int) -> np.ndarray:
+    """Doubles in (0, 1]."""
+    return ((raw_u64(key, n) >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform_int(key: int, n: int, bound: int) -> np.ndarray:
+    """Integers in [0, bound) (Lemire's multiply-shift on the high 32 bits)."""
+    if not 0 < bound < (1 << 32):
+        raise ValueError("bound must be in (0, 2^32)")
+    hi = raw_u64(key, n) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        return ((hi * np.uint64(bound)) >> np.uint64(32)).astype(np.int64)
+
+
+def normal(key: int, n: int) -> np.ndarray:
+    """Standard normals by Box-Muller (cosine branch) from two sub-streams."""
+    u1 = uniform01_open0(stream_key(key, 0), n)
+    u2 = uniform01(stream_key(key, 1), n)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def lround_nonneg(v: np.ndarray) -> np.ndarray:
+    return np.floor(v + 0.5)
+
+
+# ----------------------------------------------------------------------------
+# frame specifications
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class FrameSpec:
+    """Distribution of one frame's projected Gaussians."""
+    width: int
+    height: int
+    n: int
+    radius: str = "lognormal"        # "lognormal" or "pareto"
+    sigma_mu: float = math.log(3.0)  # lognormal sigma: exp(mu + s z)
+    sigma_s: float = 0.6
+    pareto_alpha: float = 1.8        # pareto sigma: u^(-1/alpha), x_m = 1 px
+    radius_cap: int = 64
+    depth_lo: float = 0.2
+    depth_hi: float = 100.0
+    blob_fraction: float = 0.0       # share of means drawn around blob centres
+    n_blobs: int = 8
+    blob_std_px: float = 80.0
+
+
+# stream ids of the per-Gaussian variables
+_V_MX, _V_MY, _V_SEL, _V_BLOB, _V_BX, _V_BY, _V_SIGMA, _V_DEPTH, _V_CENTRES = range(9)
+
+
+def make_frame(spec: FrameSpec, seed: int, frame_index: int = 0) -> np.ndarray:
+    """Draw ``spec.n`` records for frame ``frame_index`` of stream ``seed``.
+
+    Means are integer-uniform over the image in 1/16 px (``[0, 16 W)``); a
+    ``blob_fraction`` share (chosen per Gaussian) is instead placed at
+    ``centre + round_half_even(16 * std * z)`` around one of ``n_blobs``
+    centres, without clamping, so some fall off the image.  Radii are
+    ``clamp(lround(3 sigma), 1, cap)``; depths ``float32(exp(U(ln lo, ln hi)))``.
+    """
+    n = int(spec.n)
+    key = stream_key(seed, frame_index)
+    fw = FIXED_POINT * spec.width
+    fh = FIXED_POINT * spec.height
+    mx = uniform_int(stream_key(key, _V_MX), n, fw)
+    my = uniform_int(stream_key(key, _V_MY), n, fh)
+    if spec.blob_fraction > 0.0 and n > 0:
+        sel = uniform01(stream_key(key, _V_SEL), n) < spec.blob_fraction
+        which = uniform_int(stream_key(key, _V_BLOB), n, spec.n_blobs)
+        ckey = stream_key(key, _V_CENTRES)
+        cx = uniform_int(stream_key(ckey, 0), spec.n_blobs, fw)
+        cy = uniform_int(stream_key(ckey, 1), spec.n_blobs, fh)
+        scale = FIXED_POINT * spec.blob_std_px
+        bx = cx[which] + np.rint(scale * normal(stream_key(key, _V_BX), n)).astype(np.int64)
+        by = cy[which] + np.rint(scale * normal(stream_key(key, _V_BY), n)).astype(np.int64)
+        mx = np.where(sel, bx, mx)
+        my = np.where(sel, by, my)
+    if spec.radius == "lognormal":
+        sigma = np.exp(spec.sigma_mu + spec.sigma_s * normal(stream_key(key, _V_SIGMA), n))
+    elif spec.radius == "pareto":
+        sigma = uniform01_open0(stream_key(key, _V_SIGMA), n) ** (-1.0 / spec.pareto_alpha)
+    else:
+        raise ValueError(spec.radius)
+    radius = np.clip(lround_nonneg(3.0 * sigma), 1, spec.radius_cap)
+    lo, hi = math.log(spec.depth_lo), math.log(spec.depth_hi)
+    depth = np.exp(lo + (hi - lo) * uniform01(stream_key(key, _V_DEPTH), n)).astype(np.float32)
+
+    rec = np.empty(n, dtype=RECORD_DTYPE)
+    rec["mean_x"] = mx.astype(np.int32)
+    rec["mean_y"] = my.astype(np.int32)
+    rec["depth"] = depth
+    rec["radius"] = radius.astype(np.uint32)
+    return rec
+
+
+# ----------------------------------------------------------------------------
+# the benchmark workloads
+# ----------------------------------------------------------------------------
+
+#: base seed of workload k is 1000 + k
+SEED_BASE = 1000
+
+SMALL = FrameSpec(256, 256, 10_000)                                   # 256 tiles
+FULL_HD = FrameSpec(1920, 1080, 1_000_000, sigma_mu=math.log(2.0), sigma_s=0.8,
+                    blob_fraction=0.2)                                 # 8,160 tiles
+LARGE = FrameSpec(1920, 1080, 6_000_000, radius="pareto", radius_cap=256,
+                  depth_lo=0.1, depth_hi=500.0)                        # heavy tail
+
+#: the three single-frame workloads by name
+FRAME_WORKLOADS = {"small-256x256": (SMALL, SEED_BASE + 0),
+                   "fullhd-1m": (FULL_HD, SEED_BASE + 1),
+                   "large-6m": (LARGE, SEED_BASE + 2)}
+
+BATCH_RESOLUTIONS = ((640, 360), (1280, 720), (1920, 1080))
+BATCH_N_RANGE = (50_000, 2_000_000)
+
+
+def scaled(spec: FrameSpec, n: int) -> FrameSpec:
+    """Same distributions with a different Gaussian count."""
+    return dataclasses.replace(spec, n=int(n))
+
+
+def batch_frame_spec(seed: int, frame_index: int,
+                     n_range: Sequence[int] = BATCH_N_RANGE) -> FrameSpec:
+    """Frame ``frame_index`` of a batch: resolution uniform over three sizes,
+    N log-uniform over ``n_range``, other distributions as the full-HD frame."""
+    key = stream_key(seed, frame_index, 1 << 20)
+    r = int(uniform_int(stream_key(key, 0), 1, len(BATCH_RESOLUTIONS))[0])
+    lo, hi = math.log(n_range[0]), math.log(n_range[1])
+    u = float(uniform01(stream_key(key, 1), 1)[0])
+    n = int(math.floor(math.exp(lo + (hi - lo) * u)))
+    w, h = BATCH_RESOLUTIONS[r]
+    return dataclasses.replace(FULL_HD, width=w, height=h, n=n)
+
+
+def make_batch(n_frames: int, seed: int = SEED_BASE + 3,
+               n_range: Sequence[int] = BATCH_N_RANGE) -> List[tuple]:
+    """``n_frames`` uneven frames as ``(width, height, records)`` tuples."""
+    out = []
+    for f in range(n_frames):
+        spec = batch_frame_spec(seed, f, n_range)
+        out.append((spec.width, spec.height, make_frame(spec, seed, f)))
+    return out
+
+
+def poisson_arrivals(rate_per_s: float, duration_s: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process: exponential gaps -ln(u)/rate."""
+    expect = int(rate_per_s * duration_s * 1.5 + 64)
+    gaps = -np.log(uniform01_open0(stream_key(seed, 1 << 21), expect)) / rate_per_s
+    t = np.cumsum(gaps)
+    while t[-1] < duration_s:   # rare: extend the stream
+        more = -np.log(uniform01_open0(stream_key(seed, 1 << 21, len(t)), expect)) / rate_per_s
+        t = np.concatenate([t, t[-1] + np.cumsum(more)])
+    return t[t < duration_s]
+
+
+def sort_sweep_pairs(m: int, key_bits: int, seed: int) -> tuple:
+    """Random pairs for the sort-only sweep: keys uniform over [0, 2^key_bits),
+    values 0..m-1 (the paper's random key-value datasets, Evaluation)."""
+    k = raw_u64(stream_key(seed, 1 << 22), m)
+    if key_bits < 64:
+        k = k >> np.uint64(64 - key_bits)
+    return k, np.arange(m, dtype=np.uint32)

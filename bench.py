@@ -1,0 +1,170 @@
+"""Throughput of the per-frame tile-and-depth sort on one MI355X.
+
+One step = the whole hot path (count, scan, duplicate, radix sort, ranges)
+over one synthetic frame whose records are already resident in HBM.  The
+default workload is the full-HD frame (1920x1080, 8,160 tiles, N = 1,000,000
+Gaussians, about 4.8M pairs).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--workload", default="fullhd-1m", choices=sorted(synth.FRAME_WORKLOADS))
+    p.add_argument("--radix-bits", type=int, default=0)
+    p.add_argument("--items", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="budget of the oracle baseline (whole frames until exceeded)")
+    return p.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sort of one frame runs on one device and "
+              "frames shard across GPUs without communication; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2511_16298_amd as ss
+    from paper_2511_16298_amd import _abi
+
+    spec, seed = synth.FRAME_WORKLOADS[args.workload]
+    rec = synth.make_frame(spec, seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d = ss.records_to_device(rec, dev)
+    _, _, m_t, s_t = ss.count_pairs(d, spec.width, spec.height)
+    assert int(s_t.item()) == 0
+    M = int(m_t.item()) & 0xFFFFFFFF
+    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev)
+    tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
+    rb = args.radix_bits or 8
+    passes = -(-key_bits // rb)
+    stream = torch.cuda.current_stream()
+
+    print(f"# workload {args.workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
+          f"T={tx * ty}, key bits {key_bits}, passes {passes}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        sorter(d, stream)
+    torch.cuda.synchronize()
+    st, m_chk = sorter.out.result()
+    assert st == 0 and m_chk == M, (st, m_chk)
+
+    # ---- timed region: K whole steps, an event between consecutive steps ----
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(K):
+        sorter(d, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+    total_ms = ev[0].elapsed_time(ev[K])
+    ms_per_step = total_ms / K
+    print(f"# timed {K} steps: {ms_per_step * 1e3:.1f} us/step (host wall {wall / K * 1e6:.1f} us/step)",
+          file=sys.stderr, flush=True)
+
+    # ---- per-kernel durations: the same K steps with HIP events around each launch ----
+    timer = ss.Timer(max_launches=K * (passes + 4) + 16)
+    torch.cuda.synchronize()
+    evk0, evk1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evk0.record(stream)
+    for i in range(K):
+        sorter(d, stream, timer=timer)
+    evk1.record(stream)
+    torch.cuda.synchronize()
+    instr_ms_per_step = evk0.elapsed_time(evk1) / K
+    kern = {}
+    for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count_scan_dup", _abi.SS_KERNEL_COUNT_DUP),
+                       ("sort_pass", _abi.SS_KERNEL_SORT_PASS), ("ranges", _abi.SS_KERNEL_RANGES)):
+        ms, n = timer.read(kind)
+        kern[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "us_per_step": 1e3 * ms / K}
+    timer.close()
+    pass_us = kern["sort_pass"]["avg_us"]
+    pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair
+    achieved = pass_bytes / (pass_us * 1e-6) / 1e9
+    # whole-step algorithmic bytes (model): 48 N + (28 + 24 P) M + 8 T
+    N = len(rec)
+    step_bytes = 48.0 * N + (28.0 + 24.0 * passes) * M + 8.0 * tx * ty
+
+    pairs_per_s = M / (ms_per_step * 1e-3)
+    line = {
+        "metric": "sorted key-value pairs/s (HBM-roofline %) + p50/p99 frame-sort latency",
+        "value": pairs_per_s,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {spec.width}x{spec.height} image, 16x16 tiles "
+                               f"({tx}x{ty}={tx * ty}), N={N} projected Gaussians, seed {seed}",
+                   "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "passes": passes,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99), "max": max(step_ms)},
+        "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "bytes_per_launch": pass_bytes, "avg_launch_us": pass_us},
+        "step_model": {"bytes": step_bytes, "GB/s": step_bytes / (ms_per_step * 1e-3) / 1e9,
+                       "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "kernels": kern,
+        "instrumented_ms_per_step": instr_ms_per_step,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        keys_gpu = sorter.out.keys.cpu().numpy().view(np.uint64)[:M]
+        vals_gpu = sorter.out.values.cpu().numpy().view(np.uint32)[:M]
+        rng_gpu = sorter.out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        frames, spent, parity = 0, 0.0, True
+        while spent < args.cpu_seconds or frames == 0:
+            t = time.perf_counter()
+            res = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+            spent += time.perf_counter() - t
+            frames += 1
+            if frames == 1:
+                parity = (res.num_pairs == M and np.array_equal(res.keys, keys_gpu)
+                          and np.array_equal(res.values, vals_gpu) and np.array_equal(res.ranges, rng_gpu))
+        line["cpu_baseline"] = {"value": frames * M / spent, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{frames} whole {args.workload} frames ({spent:.1f} s, "
+                                          f"single-threaded oracle, {os.cpu_count()} host CPUs visible)"}
+        line["parity_vs_oracle"] = bool(parity)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

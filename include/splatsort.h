@@ -1,0 +1,175 @@
+/* splatsort: per-frame tile-and-depth sort of 3D Gaussian Splatting on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Operation (arXiv 2511.16298, Background, "Duplication with Tiles" and
+ * "Sorting"; Design, "Sorting Optimizations in Context of 3DGS"): projected
+ * Gaussians go in; out come all (tile, Gaussian) pairs whose 16x16-pixel tile
+ * meets the Gaussian's axis-aligned bounding box, as 64-bit keys
+ * (tile id << 32 | raw FP32 depth bits) with 32-bit Gaussian-index values,
+ * ordered by tile, then depth, then index, and each tile's [start, end)
+ * range into that list.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named d_* or documented "device" point to device memory on the
+ *    current HIP device; the caller owns them; the library never frees or
+ *    retains them past the call (except the arena given to a server).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls validate their arguments synchronously and return an error before
+ *    enqueuing anything; then they enqueue asynchronously on `stream` and
+ *    return SS_OK.  Outputs are valid once the stream has reached that point.
+ *  - Errors found on the device (capacity, overflow, invalid input) are
+ *    written to a device status word; when it is not SS_OK the contents of
+ *    keys, values and ranges are unspecified.
+ *  - No call blocks on the GPU unless documented.  No exceptions cross the
+ *    ABI.  Calls that share a workspace must not overlap in time.
+ */
+#ifndef SPLATSORT_H
+#define SPLATSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SS_ABI_VERSION 1
+
+typedef enum ss_status {
+  SS_OK = 0,
+  SS_ERR_INVALID_ARGUMENT = 1, /* a NULL pointer, a size out of range, bad alignment */
+  SS_ERR_UNSUPPORTED = 2,      /* an option value this build does not implement */
+  SS_ERR_CAPACITY = 3,         /* device: the frame has more pairs than pair_capacity */
+  SS_ERR_OVERFLOW = 4,         /* device: the frame has 2^32 pairs or more */
+  SS_ERR_INVALID_INPUT = 5,    /* device: a Gaussian that touches a tile has a depth
+                                  that is not positive and finite */
+  SS_ERR_WORKSPACE = 6,        /* the workspace is smaller than required */
+  SS_ERR_HIP = 7,              /* a HIP runtime call failed */
+  SS_ERR_BUDGET = 8,           /* server: the request can never fit the arena */
+  SS_ERR_TIMEOUT = 9           /* device: a bounded inter-workgroup wait gave up */
+} ss_status;
+
+/* One projected Gaussian, the packed output group the duplication step reads
+ * (Design, "Output Data Grouping": 2D mean, depth and radius together).
+ * 16 bytes, 16-byte aligned; one 128-bit load per Gaussian. */
+typedef struct ss_gaussian2d {
+  int32_t mean_x;  /* signed 1/16-pixel fixed point; off-image allowed */
+  int32_t mean_y;
+  float depth;     /* view depth; must be positive and finite if the
+                      Gaussian touches a tile; its raw bits form the key */
+  uint32_t radius; /* pixels; 0 = culled */
+} ss_gaussian2d;
+
+/* Tile overlap rule: with cx = mean_x / 16 px, tile column tx is touched iff
+ * the open interval (cx - radius, cx + radius) meets [16 tx, 16 tx + 16);
+ * rows likewise.  Partial edge tiles count.  Tile id = ty * tiles_x + tx. */
+typedef struct ss_frame {
+  uint32_t width;          /* pixels, 1 .. SS_MAX_IMAGE_PX */
+  uint32_t height;         /* pixels, 1 .. SS_MAX_IMAGE_PX */
+  uint32_t tile_px;        /* must be 16 */
+  uint32_t num_gaussians;  /* N, 0 .. 2^31 - 1 */
+  const ss_gaussian2d* gaussians; /* device [N]; may be NULL when N == 0 */
+} ss_frame;
+
+#define SS_MAX_IMAGE_PX 1048560u        /* 65535 tiles of 16 px per axis */
+#define SS_MAX_PAIR_CAPACITY 1073741823u /* 2^30 - 1 pairs per sort */
+
+typedef struct ss_frame_out {
+  uint32_t pair_capacity;  /* entries of keys/values, 0 .. SS_MAX_PAIR_CAPACITY */
+  uint64_t* keys;          /* device [pair_capacity]: sorted keys */
+  uint32_t* values;        /* device [pair_capacity]: Gaussian indices */
+  uint32_t* tile_ranges;   /* device [2 T]: start, end of tile t at [2t], [2t+1];
+                              the ranges partition [0, M) in tile order; an
+                              empty tile gets [p, p), p = pairs of lower tiles */
+  uint32_t* tiles_touched; /* device [N] or NULL: pairs per Gaussian */
+  uint32_t* offsets;       /* device [N] or NULL: exclusive prefix sum of tiles_touched */
+  uint32_t* num_pairs;     /* device scalar M (min(M, 2^32-1)) or NULL */
+  uint32_t* status;        /* device scalar ss_status or NULL */
+} ss_frame_out;
+
+/* Radix digit width and instrumentation.  Zero-initialise, then set
+ * struct_size = sizeof(ss_options).  A NULL options pointer means defaults. */
+typedef struct ss_timer ss_timer;
+typedef struct ss_options {
+  uint32_t struct_size;
+  uint32_t radix_bits;     /* 0 = default (8); supported: 4, 6, 8 */
+  uint32_t items_per_thread; /* 0 = default; sort-pass tile = 256 * items */
+  uint32_t flags;          /* 0, or SS_FLAG_UNSORTED */
+  ss_timer* timer;         /* optional: record HIP events around every kernel */
+} ss_options;
+
+/* Stop after step a3: keys/values receive the duplicated pairs in
+ * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no
+ * ranges.  For stage-by-stage verification. */
+#define SS_FLAG_UNSORTED 1u
+
+/* Library identification. */
+uint32_t ss_abi_version(void);
+const char* ss_status_string(ss_status s);
+
+/* Tile grid of a frame: T = tiles_x * tiles_y, and the sorted key width
+ * b = ceil(log2 T) + 32 (32 when T == 1).  Host only, no GPU work. */
+ss_status ss_frame_geometry(const ss_frame* frame, uint32_t* tiles_x, uint32_t* tiles_y,
+                            uint32_t* key_bits);
+
+/* Bytes of workspace that ss_sort_frame needs for this frame shape and
+ * capacity (depends on N, T, pair_capacity and the options only).  The
+ * workspace must be 256-byte aligned device memory. */
+ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity,
+                             const ss_options* options, size_t* bytes);
+
+/* Steps a1-a2 only: per-Gaussian tile counts, their exclusive prefix sum and
+ * the total M, so a caller can size the pair buffers (one 4-byte read back).
+ * Any of d_tiles_touched, d_offsets may be NULL; d_num_pairs and d_status
+ * are required.  Uses the same workspace as ss_sort_frame with capacity 0. */
+ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint32_t* d_offsets,
+                         uint32_t* d_num_pairs, uint32_t* d_status,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* The whole hot path a1-a5 for one frame: tile-overlap counting fused with a
+ * single-pass exclusive scan and the duplication into (key, value) pairs;
+ * a stable LSD radix sort of the pairs over key bits [0, b); tile ranges. */
+ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out,
+                        void* workspace, size_t workspace_bytes, void* stream,
+                        const ss_options* options);
+
+/* Step a4 alone on caller data (the paper's random key-value sort benchmark,
+ * Evaluation, "Datasets"): stable sort of n pairs by key bits [0, key_bits);
+ * keys must be < 2^key_bits.  keys_in/values_in are not modified; they may
+ * not alias the outputs.  Workspace: ss_sort_pairs_workspace_bytes. */
+ss_status ss_sort_pairs_workspace_bytes(uint32_t n, uint32_t key_bits, const ss_options* options,
+                                        size_t* bytes);
+ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint32_t n,
+                        uint32_t key_bits, uint64_t* keys_out, uint32_t* values_out,
+                        void* workspace, size_t workspace_bytes, void* stream,
+                        const ss_options* options);
+
+/* Measurement helpers. */
+/* A plain streaming copy of `bytes` (multiple of 16, 16-byte aligned) used to
+ * calibrate memory-traffic counters and to report achievable bandwidth. */
+ss_status ss_copy_bytes(void* d_dst, const void* d_src, size_t bytes, void* stream,
+                        const ss_options* options);
+
+typedef enum ss_kernel_kind {
+  SS_KERNEL_CLEAR = 0,      /* zeroes counters and look-back state */
+  SS_KERNEL_COUNT_DUP = 1,  /* a1+a2+a3 fused */
+  SS_KERNEL_SORT_PASS = 2,  /* one a4 digit pass */
+  SS_KERNEL_RANGES = 3,     /* a5 */
+  SS_KERNEL_COPY = 4,       /* ss_copy_bytes */
+  SS_KERNEL_HIST = 5,       /* digit histograms of caller keys (ss_sort_pairs) */
+  SS_KERNEL_KINDS = 8
+} ss_kernel_kind;
+
+/* Event pool for per-kernel timing.  Create once (host), pass in
+ * ss_options.timer, synchronise the stream, then read the summed time and
+ * launch count per kernel kind.  Reset before reuse.  Not thread-safe. */
+ss_status ss_timer_create(ss_timer** timer, uint32_t max_launches);
+ss_status ss_timer_reset(ss_timer* timer);
+ss_status ss_timer_read(ss_timer* timer, uint32_t kind, double* total_ms, uint32_t* launches);
+void ss_timer_destroy(ss_timer* timer);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLATSORT_H */

@@ -1,0 +1,225 @@
+"""splatsort for MI355X: the per-frame tile-and-depth sort of 3D Gaussian
+Splatting (arXiv 2511.16298, Background, "Duplication with Tiles" and
+"Sorting"), as a HIP library with a C ABI.
+
+This module marshals torch tensors into the C ABI (``_abi``); torch supplies
+device memory and the stream, the HIP kernels do all the work.  Integer
+buffers use signed torch dtypes of the same width (keys int64 = uint64 bits,
+values and ranges int32 = uint32 bits).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+from . import _abi
+from ._abi import (SS_OK, SplatSortError, check, make_options, ss_frame, ss_frame_out)
+
+__all__ = ["FrameSorter", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
+           "records_to_device", "SplatSortError", "geometry"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def records_to_device(records, device="cuda"):
+    """A numpy array of 16-byte records (``synth.RECORD_DTYPE``) as an (N, 4)
+    int32 device tensor."""
+    import numpy as np
+    torch = _torch()
+    a = np.ascontiguousarray(records).view(np.int32).reshape(-1, 4)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+def _frame(records, width: int, height: int, tile_px: int = 16) -> ss_frame:
+    n = 0 if records is None else int(records.shape[0])
+    if records is not None and n > 0:
+        torch = _torch()
+        if records.dtype != torch.int32 or records.dim() != 2 or records.shape[1] != 4 or not records.is_contiguous():
+            raise ValueError("records must be a contiguous (N, 4) int32 tensor")
+    f = ss_frame()
+    f.width, f.height, f.tile_px, f.num_gaussians = width, height, tile_px, n
+    f.gaussians = records.data_ptr() if n > 0 else None
+    return f
+
+
+def geometry(width: int, height: int, tile_px: int = 16):
+    """(tiles_x, tiles_y, key_bits) of a frame."""
+    f = ss_frame()
+    f.width, f.height, f.tile_px, f.num_gaussians, f.gaussians = width, height, tile_px, 0, None
+    st, tx, ty, kb = _abi.ss_frame_geometry(f)
+    check(st, "ss_frame_geometry")
+    return tx, ty, kb
+
+
+class Timer:
+    """Per-kernel HIP-event timing (``ss_timer``)."""
+
+    def __init__(self, max_launches: int = 4096):
+        st, h = _abi.ss_timer_create(max_launches)
+        check(st, "ss_timer_create")
+        self.handle = h
+
+    def reset(self):
+        check(_abi.ss_timer_reset(self.handle), "ss_timer_reset")
+
+    def read(self, kind: int):
+        """(total milliseconds, launches) of one kernel kind; the stream must
+        have been synchronised."""
+        st, ms, n = _abi.ss_timer_read(self.handle, kind)
+        check(st, "ss_timer_read")
+        return ms, n
+
+    def close(self):
+        if self.handle:
+            _abi.ss_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class FrameOutput:
+    keys: "object"            # int64 [capacity] (uint64 bits)
+    values: "object"          # int32 [capacity] (uint32 bits)
+    tile_ranges: "object"     # int32 [T, 2]
+    num_pairs: "object"       # int32 [1] device scalar
+    status: "object"          # int32 [1] device scalar
+    tiles_touched: "object" = None
+    offsets: "object" = None
+
+    def result(self):
+        """Synchronise and return (status, M)."""
+        return int(self.status.item()), int(self.num_pairs.item()) & 0xFFFFFFFF
+
+
+class FrameSorter:
+    """Pre-allocated outputs and workspace for repeated ``ss_sort_frame`` calls
+    on frames of one shape (the device-resident buffers of a serving loop or
+    a benchmark)."""
+
+    def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
+                 radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
+                 device="cuda", unsorted: bool = False):
+        torch = _torch()
+        self.width, self.height = width, height
+        self.num_gaussians = num_gaussians
+        self.capacity = int(pair_capacity)
+        self.tiles_x, self.tiles_y, self.key_bits = geometry(width, height)
+        self.num_tiles = self.tiles_x * self.tiles_y
+        self.options = make_options(radix_bits, items_per_thread,
+                                    flags=_abi.SS_FLAG_UNSORTED if unsorted else 0)
+        probe = ss_frame()
+        probe.width, probe.height, probe.tile_px, probe.num_gaussians = width, height, 16, num_gaussians
+        probe.gaussians = 16 if num_gaussians else None   # only shape matters here
+        st, ws = _abi.ss_workspace_bytes(probe, self.capacity, self.options)
+        check(st, "ss_workspace_bytes")
+        self.workspace_bytes = ws
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        cap = max(self.capacity, 1)
+        n = max(num_gaussians, 1)
+        self.out = FrameOutput(
+            keys=torch.empty(cap, dtype=torch.int64, device=device),
+            values=torch.empty(cap, dtype=torch.int32, device=device),
+            tile_ranges=torch.empty((self.num_tiles, 2), dtype=torch.int32, device=device),
+            num_pairs=torch.zeros(1, dtype=torch.int32, device=device),
+            status=torch.zeros(1, dtype=torch.int32, device=device),
+            tiles_touched=torch.empty(n, dtype=torch.int32, device=device) if stages else None,
+            offsets=torch.empty(n, dtype=torch.int32, device=device) if stages else None)
+        o = ss_frame_out()
+        o.pair_capacity = self.capacity
+        o.keys = self.out.keys.data_ptr()
+        o.values = self.out.values.data_ptr()
+        o.tile_ranges = self.out.tile_ranges.data_ptr()
+        o.tiles_touched = self.out.tiles_touched.data_ptr() if stages else None
+        o.offsets = self.out.offsets.data_ptr() if stages else None
+        o.num_pairs = self.out.num_pairs.data_ptr()
+        o.status = self.out.status.data_ptr()
+        self._cout = o
+
+    def __call__(self, records, stream=None, timer: Optional[Timer] = None) -> FrameOutput:
+        """Enqueue ``ss_sort_frame`` on ``stream`` (default: torch's current
+        stream).  Raises on a synchronous error; device errors land in
+        ``out.status``."""
+        if int(records.shape[0]) != self.num_gaussians:
+            raise ValueError("records do not match the sorter's Gaussian count")
+        f = _frame(records, self.width, self.height)
+        self.options.timer = timer.handle if timer is not None else None
+        st = _abi.ss_sort_frame(f, self._cout, self.workspace.data_ptr(), self.workspace_bytes,
+                                _stream_handle(stream), self.options)
+        check(st, "ss_sort_frame")
+        return self.out
+
+
+def count_pairs(records, width: int, height: int, stream=None):
+    """Steps a1-a2: (tiles_touched, offsets, num_pairs, status) device tensors."""
+    torch = _torch()
+    dev = records.device
+    f = _frame(records, width, height)
+    n = max(int(records.shape[0]), 1)
+    probe = f
+    st, ws = _abi.ss_workspace_bytes(probe, 0, None)
+    check(st, "ss_workspace_bytes")
+    work = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    tt = torch.empty(n, dtype=torch.int32, device=dev)
+    off = torch.empty(n, dtype=torch.int32, device=dev)
+    m = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = torch.zeros(1, dtype=torch.int32, device=dev)
+    st = _abi.ss_count_pairs(f, tt.data_ptr(), off.data_ptr(), m.data_ptr(), s.data_ptr(),
+                             work.data_ptr(), ws, _stream_handle(stream))
+    check(st, "ss_count_pairs")
+    return tt, off, m, s
+
+
+def sort_frame(records, width: int, height: int, capacity: Optional[int] = None, stream=None,
+               radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False):
+    """Whole frame.  With ``capacity=None`` a first call counts the pairs and
+    one 4-byte read-back sizes the buffers exactly.  Returns the sorter's
+    FrameOutput (slice ``[:M]`` after ``result()``)."""
+    if capacity is None:
+        _, _, m, s = count_pairs(records, width, height, stream)
+        st = int(s.item())
+        if st != SS_OK:
+            raise SplatSortError(st, "ss_count_pairs")
+        capacity = int(m.item()) & 0xFFFFFFFF
+    sorter = FrameSorter(width, height, int(records.shape[0]), capacity, radix_bits, items_per_thread,
+                         stages, device=records.device)
+    return sorter(records, stream)
+
+
+def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, items_per_thread: int = 0,
+               timer: Optional[Timer] = None):
+    """Step a4 alone: stable sort of (int64 keys, int32 values) by key bits
+    [0, key_bits).  Returns new (keys, values) tensors."""
+    torch = _torch()
+    n = int(keys.shape[0])
+    opts = make_options(radix_bits, items_per_thread, timer.handle if timer is not None else None)
+    st, ws = _abi.ss_sort_pairs_workspace_bytes(n, key_bits, opts)
+    check(st, "ss_sort_pairs_workspace_bytes")
+    work = torch.empty(max(ws, 256), dtype=torch.uint8, device=keys.device)
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(values)
+    st = _abi.ss_sort_pairs(keys.data_ptr(), values.data_ptr(), n, key_bits, ko.data_ptr(), vo.data_ptr(),
+                            work.data_ptr(), ws, _stream_handle(stream), opts)
+    check(st, "ss_sort_pairs")
+    return ko, vo
+
+
+def copy_bytes(dst, src, nbytes: int, stream=None, timer: Optional[Timer] = None):
+    opts = make_options(timer=timer.handle if timer is not None else None)
+    check(_abi.ss_copy_bytes(dst.data_ptr(), src.data_ptr(), nbytes, _stream_handle(stream), opts),
+          "ss_copy_bytes")

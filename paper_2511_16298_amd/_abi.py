@@ -1,0 +1,199 @@
+"""ctypes declarations of the C ABI in include/splatsort.h (argument
+marshalling only; every step of the sort runs in the HIP library).
+
+Loading fails loudly when libsplatsort.so has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsplatsort.so")
+
+SS_OK = 0
+SS_ERR_INVALID_ARGUMENT = 1
+SS_ERR_UNSUPPORTED = 2
+SS_ERR_CAPACITY = 3
+SS_ERR_OVERFLOW = 4
+SS_ERR_INVALID_INPUT = 5
+SS_ERR_WORKSPACE = 6
+SS_ERR_HIP = 7
+SS_ERR_BUDGET = 8
+SS_ERR_TIMEOUT = 9
+
+SS_KERNEL_CLEAR = 0
+SS_KERNEL_COUNT_DUP = 1
+SS_KERNEL_SORT_PASS = 2
+SS_KERNEL_RANGES = 3
+SS_KERNEL_COPY = 4
+SS_KERNEL_HIST = 5
+
+SS_FLAG_UNSORTED = 1
+
+SS_MAX_IMAGE_PX = 1048560
+SS_MAX_PAIR_CAPACITY = (1 << 30) - 1
+
+
+class ss_frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("tile_px", ctypes.c_uint32), ("num_gaussians", ctypes.c_uint32),
+                ("gaussians", ctypes.c_void_p)]
+
+
+class ss_frame_out(ctypes.Structure):
+    _fields_ = [("pair_capacity", ctypes.c_uint32),
+                ("keys", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("tile_ranges", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("num_pairs", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+class ss_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
+                ("items_per_thread", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("timer", ctypes.c_void_p)]
+
+
+def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, flags: int = 0) -> ss_options:
+    o = ss_options()
+    o.struct_size = ctypes.sizeof(ss_options)
+    o.radix_bits = radix_bits
+    o.items_per_thread = items_per_thread
+    o.flags = flags
+    o.timer = timer
+    return o
+
+
+class SplatSortError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_P = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_SZ = ctypes.c_size_t
+
+_SIGNATURES = {
+    "ss_abi_version": ([], _U32),
+    "ss_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "ss_frame_geometry": ([ctypes.POINTER(ss_frame), _P, _P, _P], ctypes.c_int),
+    "ss_workspace_bytes": ([ctypes.POINTER(ss_frame), _U32, ctypes.POINTER(ss_options),
+                            ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ss_count_pairs": ([ctypes.POINTER(ss_frame), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "ss_sort_frame": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_frame_out), _P, _SZ, _P,
+                       ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_sort_pairs_workspace_bytes": ([_U32, _U32, ctypes.POINTER(ss_options), ctypes.POINTER(_SZ)],
+                                      ctypes.c_int),
+    "ss_sort_pairs": ([_P, _P, _U32, _U32, _P, _P, _P, _SZ, _P, ctypes.POINTER(ss_options)],
+                      ctypes.c_int),
+    "ss_copy_bytes": ([_P, _P, _SZ, _P, ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_timer_create": ([ctypes.POINTER(_P), _U32], ctypes.c_int),
+    "ss_timer_reset": ([_P], ctypes.c_int),
+    "ss_timer_read": ([_P, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)], ctypes.c_int),
+    "ss_timer_destroy": ([_P], None),
+}
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2511_16298_amd.build` (there is no fallback)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = h
+    return _LIB
+
+
+def status_string(status: int) -> str:
+    return lib().ss_status_string(status).decode()
+
+
+def check(status: int, what: str):
+    if status != SS_OK:
+        raise SplatSortError(status, what)
+
+
+def declared_symbols():
+    return sorted(_SIGNATURES)
+
+
+# Thin wrappers with the C names -------------------------------------------------
+
+def ss_abi_version() -> int:
+    return lib().ss_abi_version()
+
+
+def ss_status_string(status: int) -> str:
+    return status_string(status)
+
+
+def ss_frame_geometry(frame: ss_frame):
+    tx, ty, kb = _U32(), _U32(), _U32()
+    st = lib().ss_frame_geometry(ctypes.byref(frame), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(kb))
+    return st, tx.value, ty.value, kb.value
+
+
+def ss_workspace_bytes(frame: ss_frame, pair_capacity: int, options=None):
+    n = _SZ()
+    st = lib().ss_workspace_bytes(ctypes.byref(frame), pair_capacity,
+                                  ctypes.byref(options) if options is not None else None, ctypes.byref(n))
+    return st, n.value
+
+
+def ss_count_pairs(frame: ss_frame, d_tiles_touched, d_offsets, d_num_pairs, d_status, workspace,
+                   workspace_bytes, stream):
+    return lib().ss_count_pairs(ctypes.byref(frame), d_tiles_touched, d_offsets, d_num_pairs, d_status,
+                                workspace, workspace_bytes, stream)
+
+
+def ss_sort_frame(frame: ss_frame, out: ss_frame_out, workspace, workspace_bytes, stream, options=None):
+    return lib().ss_sort_frame(ctypes.byref(frame), ctypes.byref(out), workspace, workspace_bytes, stream,
+                               ctypes.byref(options) if options is not None else None)
+
+
+def ss_sort_pairs_workspace_bytes(n: int, key_bits: int, options=None):
+    b = _SZ()
+    st = lib().ss_sort_pairs_workspace_bytes(n, key_bits, ctypes.byref(options) if options is not None else None,
+                                             ctypes.byref(b))
+    return st, b.value
+
+
+def ss_sort_pairs(keys_in, values_in, n, key_bits, keys_out, values_out, workspace, workspace_bytes, stream,
+                  options=None):
+    return lib().ss_sort_pairs(keys_in, values_in, n, key_bits, keys_out, values_out, workspace, workspace_bytes,
+                               stream, ctypes.byref(options) if options is not None else None)
+
+
+def ss_copy_bytes(dst, src, nbytes, stream, options=None):
+    return lib().ss_copy_bytes(dst, src, nbytes, stream, ctypes.byref(options) if options is not None else None)
+
+
+def ss_timer_create(max_launches: int):
+    h = _P()
+    st = lib().ss_timer_create(ctypes.byref(h), max_launches)
+    return st, h.value
+
+
+def ss_timer_reset(timer) -> int:
+    return lib().ss_timer_reset(timer)
+
+
+def ss_timer_read(timer, kind: int):
+    ms, n = ctypes.c_double(), _U32()
+    st = lib().ss_timer_read(timer, kind, ctypes.byref(ms), ctypes.byref(n))
+    return st, ms.value, n.value
+
+
+def ss_timer_destroy(timer) -> None:
+    lib().ss_timer_destroy(timer)

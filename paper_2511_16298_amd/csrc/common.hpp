@@ -1,0 +1,88 @@
+// Device helpers shared by the splatsort kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+constexpr int kWave = 64;
+
+// Look-back words.  32-bit form (sort passes): bits 30-31 hold the state,
+// bits 0-29 the count.  64-bit form (the Gaussian scan): bits 62-63 state,
+// bit 61 a sticky "invalid input" flag, bits 0-60 the count (saturating).
+constexpr uint32_t kLbAgg32 = 1u << 30;
+constexpr uint32_t kLbInc32 = 2u << 30;
+constexpr uint32_t kLbMask32 = (1u << 30) - 1;
+constexpr uint64_t kLbAgg64 = 1ull << 62;
+constexpr uint64_t kLbInc64 = 2ull << 62;
+constexpr uint64_t kLbBad64 = 1ull << 61;
+constexpr uint64_t kLbMask64 = (1ull << 61) - 1;
+
+// A bounded spin: after this many polls a waiting workgroup gives up, raises
+// SS_ERR_TIMEOUT in the status word and leaves (its output is then invalid,
+// but the grid always drains).  Far above any legitimate wait.
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ uint32_t popc_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Cross-workgroup words are read and written with device-scope atomics so
+// they are coherent across the XCDs' separate L2 caches.
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (lane >= static_cast<uint32_t>(d)) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over a whole workgroup of THREADS threads (one value each).
+// `s_tmp` holds THREADS / 64 values of LDS.  Returns the exclusive prefix and
+// writes the workgroup total.  Contains two barriers.
+template <typename T, int THREADS>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* s_tmp, T& total) {
+  constexpr int kWaves = THREADS / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const T inc = wave_inclusive_scan(v);
+  if (lane == kWave - 1) s_tmp[wave] = inc;
+  __syncthreads();
+  T before = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const T x = s_tmp[w];
+    before += (w < wave) ? x : T(0);
+    sum += x;
+  }
+  __syncthreads();
+  total = sum;
+  return before + inc - v;
+}
+
+}  // namespace ss

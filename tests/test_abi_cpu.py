@@ -1,0 +1,148 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/splatsort.h declares, and rejects bad arguments synchronously (no
+compute calls are made here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "splatsort.h")
+
+from paper_2511_16298_amd import _abi  # noqa: E402
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set()
+    for m in re.finditer(r"^\s*(?!typedef)[A-Za-z_][\w\s\*]*?\b(ss_\w+)\s*\(", text, flags=re.M):
+        names.add(m.group(1))
+    return names
+
+
+def test_header_parsed():
+    names = header_functions()
+    assert {"ss_sort_frame", "ss_count_pairs", "ss_sort_pairs", "ss_workspace_bytes"} <= names
+
+
+def test_every_declared_function_is_exported():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", _abi.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = header_functions() - exported
+    assert not missing, missing
+    lib = _abi.lib()
+    for name in header_functions():
+        assert hasattr(lib, name)
+
+
+def test_binding_declares_exactly_the_header():
+    assert set(_abi.declared_symbols()) == header_functions()
+
+
+def test_abi_version_and_status_strings():
+    assert _abi.ss_abi_version() == 1
+    for s in range(10):
+        assert _abi.ss_status_string(s) and "unknown" not in _abi.ss_status_string(s)
+    assert "unknown" in _abi.ss_status_string(77)
+
+
+def frame(w=1920, h=1080, n=0, ptr=None, tile=16):
+    f = _abi.ss_frame()
+    f.width, f.height, f.tile_px, f.num_gaussians = w, h, tile, n
+    f.gaussians = ptr
+    return f
+
+
+@pytest.mark.parametrize("w,h,tx,ty,kb", [(1920, 1080, 120, 68, 45), (256, 256, 16, 16, 40),
+                                          (16, 16, 1, 1, 32), (17, 16, 2, 1, 33), (1, 1, 1, 1, 32),
+                                          (1048560, 1048560, 65535, 65535, 64)])
+def test_geometry(w, h, tx, ty, kb):
+    st, a, b, c = _abi.ss_frame_geometry(frame(w, h))
+    assert st == _abi.SS_OK and (a, b, c) == (tx, ty, kb)
+
+
+@pytest.mark.parametrize("f", [frame(0, 10), frame(10, 0), frame(1048561, 4), frame(tile=8),
+                               frame(n=5, ptr=None), frame(n=5, ptr=8), frame(n=1 << 31, ptr=256)])
+def test_bad_frames_rejected(f):
+    assert _abi.ss_frame_geometry(f)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_workspace_bytes(f, 10)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+
+
+def fake_out(cap=100):
+    o = _abi.ss_frame_out()
+    o.pair_capacity = cap
+    o.keys, o.values, o.tile_ranges = 1 << 20, 2 << 20, 3 << 20
+    return o
+
+
+def test_sort_frame_argument_errors_are_synchronous():
+    f = frame(n=10, ptr=1 << 12)
+    st, need = _abi.ss_workspace_bytes(f, 100)
+    assert st == _abi.SS_OK and need > 0
+    ws = 4 << 20
+    # workspace too small / misaligned / missing
+    assert _abi.ss_sort_frame(f, fake_out(), ws, need - 1, None) == _abi.SS_ERR_WORKSPACE
+    assert _abi.ss_sort_frame(f, fake_out(), ws + 8, need, None) == _abi.SS_ERR_WORKSPACE
+    assert _abi.ss_sort_frame(f, fake_out(), None, need, None) == _abi.SS_ERR_WORKSPACE
+    # outputs
+    o = fake_out()
+    o.keys = None
+    assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    o = fake_out()
+    o.tile_ranges = None
+    assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    o = fake_out()
+    o.keys = (1 << 20) + 4
+    assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    o = fake_out(cap=_abi.SS_MAX_PAIR_CAPACITY + 1)
+    assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    # options
+    for rb, it, fl in [(5, 0, 0), (9, 0, 0), (0, 7, 0), (0, 0, 2)]:
+        opt = _abi.make_options(rb, it, flags=fl)
+        assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, opt) == _abi.SS_ERR_UNSUPPORTED
+    bad = _abi.make_options()
+    bad.struct_size = 4
+    assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, bad) == _abi.SS_ERR_INVALID_ARGUMENT
+    # count-only entry point
+    assert _abi.ss_count_pairs(f, None, None, None, 1 << 10, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_count_pairs(f, None, None, 1 << 10, 1 << 11, ws, 16, None) == _abi.SS_ERR_WORKSPACE
+
+
+def test_sort_pairs_argument_errors():
+    st, need = _abi.ss_sort_pairs_workspace_bytes(1000, 45)
+    assert st == _abi.SS_OK
+    for kb in (0, 65):
+        assert _abi.ss_sort_pairs_workspace_bytes(10, kb)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    a, b, c, d = 1 << 20, 2 << 20, 3 << 20, 4 << 20
+    assert _abi.ss_sort_pairs(a, b, 1000, 45, a, d, 8 << 20, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_sort_pairs(a, b, 1000, 45, c, d, 8 << 20, need - 1, None) == _abi.SS_ERR_WORKSPACE
+    assert _abi.ss_sort_pairs(a + 4, b, 1000, 45, c, d, 8 << 20, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_copy_bytes(a, b, 15, None) == _abi.SS_ERR_INVALID_ARGUMENT
+
+
+def test_workspace_grows_with_capacity_and_gaussians():
+    f = frame(n=10_000, ptr=256)
+    w1 = _abi.ss_workspace_bytes(f, 1000)[1]
+    w2 = _abi.ss_workspace_bytes(f, 2_000_000)[1]
+    assert w2 > w1 + 2_000_000 * 12
+    assert _abi.ss_workspace_bytes(frame(n=10_000_000, ptr=256), 1000)[1] > w1
+    assert _abi.ss_workspace_bytes(f, 1000, _abi.make_options(4))[1] != w1
+
+
+def test_product_and_oracle_share_no_code():
+    pkg = os.path.join(ROOT, "paper_2511_16298_amd")
+    orc = os.path.join(ROOT, "oracle")
+    for d, other in ((pkg, "oracle"), (orc, "paper_2511_16298_amd")):
+        for dirpath, _, files in os.walk(d):
+            for fn in files:
+                if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                    txt = open(os.path.join(dirpath, fn)).read()
+                    assert not re.search(rf"\bimport\s+{other}\b|\bfrom\s+{other}\b|{other}/", txt), (fn, other)
+    # the product never includes the oracle header and vice versa
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".hip", ".hpp")):
+                assert "oracle.h" not in open(os.path.join(dirpath, fn)).read()

@@ -1,0 +1,219 @@
+"""GPU path against the CPU oracle, bit for bit (integer work: tolerance 0).
+
+Every case runs the HIP library through its C ABI (via the thin binding) and
+the oracle on the same seeded records.  Sizes span several workgroup tiles
+and ragged tails; the full-size workloads run in the launch configuration
+the benchmark times.
+"""
+import hashlib
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_16298_amd as ss  # noqa: E402
+from paper_2511_16298_amd import _abi  # noqa: E402
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False):
+    d = ss.records_to_device(rec)
+    if capacity is None:
+        _, _, m, s = ss.count_pairs(d, W, H)
+        assert int(s.item()) == 0
+        capacity = int(m.item()) & 0xFFFFFFFF
+    sorter = ss.FrameSorter(W, H, len(rec), capacity, radix_bits, items, stages=stages, unsorted=unsorted)
+    out = sorter(d)
+    st, m = out.result()
+    res = {"status": st, "M": m}
+    if st == 0:
+        res["keys"] = u64(out.keys)[:m]
+        res["values"] = u32(out.values)[:m]
+        res["ranges"] = u32(out.tile_ranges).reshape(-1, 2)
+    if stages and len(rec):
+        res["tiles_touched"] = u32(out.tiles_touched)[:len(rec)]
+        res["offsets"] = u32(out.offsets)[:len(rec)]
+    return res
+
+
+def assert_same(W, H, rec, g, stages=True):
+    o = oracle.sort_frame(W, H, rec)
+    assert o.status == 0
+    assert g["status"] == 0, _abi.status_string(g["status"])
+    assert g["M"] == o.num_pairs
+    assert np.array_equal(g["keys"], o.keys)
+    assert np.array_equal(g["values"], o.values)
+    assert np.array_equal(g["ranges"], o.ranges)
+    if stages and len(rec):
+        assert np.array_equal(g["tiles_touched"], o.tiles_touched)
+        assert np.array_equal(g["offsets"], o.offsets.astype(np.uint32))
+    return o
+
+
+def test_tiny_frames():
+    rs = np.random.default_rng(2024)
+    for case in range(60):
+        W, H, rec = pins.random_tiny_frame(rs)
+        print(f"tiny case {case}: {W}x{H} n={len(rec)}", flush=True)
+        assert_same(W, H, rec, gpu_frame(W, H, rec))
+
+
+@pytest.mark.parametrize("name", ["small-256x256", "fullhd-1m"])
+def test_workload_frames(name):
+    spec, seed = synth.FRAME_WORKLOADS[name]
+    rec = synth.make_frame(spec, seed)
+    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec))
+
+
+def test_large_frame_full_size():
+    spec, seed = synth.FRAME_WORKLOADS["large-6m"]
+    rec = synth.make_frame(spec, seed)
+    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec, stages=False),
+                stages=False)
+
+
+@pytest.mark.parametrize("rb,items", [(8, 8), (8, 12), (6, 16), (4, 16), (4, 8)])
+def test_radix_widths_and_tiles(rb, items):
+    spec, seed = synth.FRAME_WORKLOADS["fullhd-1m"]
+    spec = synth.scaled(spec, 150_000)
+    rec = synth.make_frame(spec, seed)
+    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec, radix_bits=rb, items=items))
+
+
+def test_unsorted_stage_matches_duplication_order():
+    spec, seed = synth.FRAME_WORKLOADS["fullhd-1m"]
+    spec = synth.scaled(spec, 100_000)
+    rec = synth.make_frame(spec, seed)
+    o = oracle.sort_frame(spec.width, spec.height, rec)
+    g = gpu_frame(spec.width, spec.height, rec, capacity=o.num_pairs, unsorted=True)
+    assert g["M"] == o.num_pairs
+    assert np.array_equal(g["keys"], o.unsorted_keys)
+    assert np.array_equal(g["values"], o.unsorted_values)
+
+
+def test_count_pairs_stage():
+    spec, seed = synth.FRAME_WORKLOADS["large-6m"]
+    spec = synth.scaled(spec, 300_001)
+    rec = synth.make_frame(spec, seed)
+    tt, off, m, s = ss.count_pairs(ss.records_to_device(rec), spec.width, spec.height)
+    cnt, _ = oracle.count(spec.width, spec.height, rec)
+    offs, tot = oracle.scan(cnt)
+    assert int(s.item()) == 0 and int(m.item()) == tot
+    assert np.array_equal(u32(tt), cnt) and np.array_equal(u32(off), offs.astype(np.uint32))
+
+
+def blank(n):
+    return np.zeros(n, dtype=synth.RECORD_DTYPE)
+
+
+def test_empty_and_degenerate_frames():
+    # no Gaussians
+    assert_same(100, 70, blank(0), gpu_frame(100, 70, blank(0), capacity=0))
+    # every radius 0: M = 0, all ranges empty
+    rec = synth.make_frame(synth.scaled(synth.SMALL, 5000), 5)
+    rec["radius"] = 0
+    g = gpu_frame(256, 256, rec, capacity=0)
+    assert g["M"] == 0 and not g["ranges"].any()
+    # one tile (T = 1, 32-bit keys)
+    rec = synth.make_frame(synth.FrameSpec(16, 9, 20_000), 6)
+    assert_same(16, 9, rec, gpu_frame(16, 9, rec))
+    # every pair in one tile of a large grid, equal depths (pure index order)
+    rec = blank(70_001)
+    rec["mean_x"], rec["mean_y"], rec["radius"], rec["depth"] = 16 * 700 + 8, 16 * 300 + 8, 1, 2.5
+    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec))
+    # every Gaussian covers the whole grid
+    rec = synth.make_frame(synth.FrameSpec(200, 120, 900), 8)
+    rec["radius"] = 5000
+    assert_same(200, 120, rec, gpu_frame(200, 120, rec))
+
+
+@pytest.mark.parametrize("m", [4095, 4096, 4097, 3 * 4096 - 1, 3 * 4096 + 1, 1023, 1025])
+def test_pair_counts_around_tile_sizes(m):
+    # m Gaussians of one tile each: M = m, spread over the grid
+    rs = np.random.default_rng(m)
+    rec = blank(m)
+    rec["mean_x"] = 16 * (16 * rs.integers(0, 120, m) + 8)
+    rec["mean_y"] = 16 * (16 * rs.integers(0, 68, m) + 8)
+    rec["radius"] = 1
+    rec["depth"] = rs.choice(np.float32([1.0, 2.0, 3.0]), m)
+    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec))
+
+
+def test_device_errors():
+    spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
+    rec = synth.make_frame(spec, seed)
+    o = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+    # capacity one short
+    g = gpu_frame(256, 256, rec, capacity=o.num_pairs - 1)
+    assert g["status"] == _abi.SS_ERR_CAPACITY and g["M"] == o.num_pairs
+    # a NaN or negative depth on a Gaussian that touches a tile
+    for bad in (np.nan, -1.0, np.inf, 0.0):
+        r2 = rec.copy()
+        r2["depth"][1234] = bad
+        assert gpu_frame(256, 256, r2, capacity=o.num_pairs)["status"] == _abi.SS_ERR_INVALID_INPUT
+    # ... but not on a culled one
+    r2 = rec.copy()
+    r2["depth"][1234], r2["radius"][1234] = np.nan, 0
+    g = gpu_frame(256, 256, r2, capacity=o.num_pairs)
+    assert g["status"] == 0
+    assert_same(256, 256, r2, g)
+    # 2^32 pairs or more: 300 Gaussians covering 4096 x 4096 tiles
+    rec = blank(300)
+    rec["mean_x"] = rec["mean_y"] = 16 * 32768
+    rec["radius"], rec["depth"] = 40000, 1.0
+    g = gpu_frame(65536, 65536, rec, capacity=1000, stages=False)
+    assert g["status"] == _abi.SS_ERR_OVERFLOW and g["M"] == 0xFFFFFFFF
+    # a frame status is reset by the next call on the same buffers
+    spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
+    rec = synth.make_frame(spec, seed)
+    d = ss.records_to_device(rec)
+    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs - 1)
+    assert sorter(d).result()[0] == _abi.SS_ERR_CAPACITY
+    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs)
+    r2 = rec.copy()
+    r2["depth"][7] = np.nan
+    assert sorter(ss.records_to_device(r2)).result()[0] == _abi.SS_ERR_INVALID_INPUT
+    assert sorter(d).result()[0] == 0
+
+
+@pytest.mark.parametrize("n,key_bits", [(1, 45), (4095, 13), (4097, 45), (100_003, 45), (65_536, 64),
+                                        (50_000, 1), (300_000, 32)])
+def test_sort_pairs_against_stable_argsort(n, key_bits):
+    keys, vals = synth.sort_sweep_pairs(n, key_bits, seed=n + key_bits)
+    if n > 10:  # force many ties
+        keys[::3] = keys[0]
+    vals = np.random.default_rng(n).permutation(n).astype(np.uint32)
+    ko, vo = ss.sort_pairs(torch.from_numpy(keys.view(np.int64)).cuda(),
+                           torch.from_numpy(vals.view(np.int32)).cuda(), key_bits)
+    ok, ov = oracle.sort_pairs(keys, vals)
+    assert np.array_equal(u64(ko), ok) and np.array_equal(u32(vo), ov)
+
+
+def test_repeated_runs_are_identical():
+    spec, seed = synth.FRAME_WORKLOADS["fullhd-1m"]
+    rec = synth.make_frame(spec, seed)
+    d = ss.records_to_device(rec)
+    _, _, m, _ = ss.count_pairs(d, spec.width, spec.height)
+    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), int(m.item()))
+    digests = set()
+    for _ in range(10):
+        out = sorter(d)
+        torch.cuda.synchronize()
+        h = hashlib.sha256()
+        for t in (out.keys, out.values, out.tile_ranges, out.status):
+            h.update(t.cpu().numpy().tobytes())
+        digests.add(h.hexdigest())
+    assert len(digests) == 1

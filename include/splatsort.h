@@ -157,6 +157,7 @@ typedef enum ss_kernel_kind {
   SS_KERNEL_RANGES = 3,     /* a5 */
   SS_KERNEL_COPY = 4,       /* ss_copy_bytes */
   SS_KERNEL_HIST = 5,       /* digit histograms of caller keys (ss_sort_pairs) */
+  SS_KERNEL_DIGIT_BASES = 6, /* exclusive prefix of the digit totals */
   SS_KERNEL_KINDS = 8
 } ss_kernel_kind;
 

@@ -29,6 +29,7 @@ SS_KERNEL_SORT_PASS = 2
 SS_KERNEL_RANGES = 3
 SS_KERNEL_COPY = 4
 SS_KERNEL_HIST = 5
+SS_KERNEL_DIGIT_BASES = 6
 
 SS_FLAG_UNSORTED = 1
 

@@ -17,6 +17,10 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
+// Counter words at the start of the workspace.
+constexpr uint32_t kCounterTicket = 0;   // count / duplicate workgroup tickets
+constexpr uint32_t kCounterPass = 16;    // + p: tickets of sort pass p (p < 48)
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 struct Options {
@@ -65,7 +69,7 @@ ss_status frame_geometry(const ss_frame* f, Geometry* g) {
 // is zeroed at the start of every call; the alternate pair buffers follow.
 struct Layout {
   uint32_t npasses = 0, bins = 0, count_blocks = 0, pass_blocks = 0, tile = 0;
-  size_t counters = 0, scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, clear_end = 0;
+  size_t counters = 0, scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, bases = 0, clear_end = 0;
   size_t alt_keys = 0, alt_vals = 0, total = 0;
 };
 
@@ -79,6 +83,7 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
   size_t off = 0;
   L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
   L.scalars = off;   off = align_up(off + 4 * sizeof(uint32_t));
+  L.bases = off;     off = align_up(off + static_cast<size_t>(L.npasses) * L.bins * sizeof(uint32_t));
   L.scan_lb = off;   off = align_up(off + static_cast<size_t>(L.count_blocks) * sizeof(uint64_t));
   L.hist = off;      off = align_up(off + static_cast<size_t>(kHistCopies) * L.npasses * L.bins * sizeof(uint32_t));
   L.pass_lb = off;   off = align_up(off + static_cast<size_t>(L.npasses) * L.pass_blocks * L.bins * sizeof(uint32_t));
@@ -142,7 +147,6 @@ ss_status run_passes(Launcher& L, const Layout& lay, const Options& o, void* ws,
                      uint32_t* const* vdst, const uint32_t* d_num_pairs, uint32_t n_fixed,
                      uint32_t* d_status, hipStream_t s) {
   uint32_t* counters = at<uint32_t>(ws, lay.counters);
-  uint32_t* hist = at<uint32_t>(ws, lay.hist);
   uint32_t* plb = at<uint32_t>(ws, lay.pass_lb);
   for (uint32_t p = 0; p < lay.npasses; ++p) {
     PassArgs a{};
@@ -154,12 +158,11 @@ ss_status run_passes(Launcher& L, const Layout& lay, const Options& o, void* ws,
     a.n_fixed = n_fixed;
     a.status = d_status;
     a.shift = p * o.radix_bits;
-    a.hist = hist + static_cast<size_t>(p) * lay.bins;
-    a.hist_stride = lay.npasses * lay.bins;
-    a.ticket = counters + 1 + p;
+    a.bases = at<uint32_t>(ws, lay.bases) + static_cast<size_t>(p) * lay.bins;
+    a.ticket = counters + kCounterPass + p;
     a.lookback = plb + static_cast<size_t>(p) * lay.pass_blocks * lay.bins;
     SS_TRY(L.run(SS_KERNEL_SORT_PASS, [&] {
-      return launch_pass(a, static_cast<int>(o.radix_bits), static_cast<int>(o.items), lay.pass_blocks, s);
+      return launch_pass(a, 8, static_cast<int>(o.radix_bits), static_cast<int>(o.items), lay.pass_blocks, s);
     }));
   }
   return SS_OK;
@@ -236,7 +239,7 @@ ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint3
   a.npasses = 0;
   a.tiles_touched = d_tiles_touched;
   a.offsets = d_offsets;
-  a.ticket = at<uint32_t>(workspace, lay.counters);
+  a.ticket = at<uint32_t>(workspace, lay.counters) + kCounterTicket;
   a.lookback = at<uint64_t>(workspace, lay.scan_lb);
   a.hist = at<uint32_t>(workspace, lay.hist);
   a.num_pairs = d_num_pairs;
@@ -295,7 +298,7 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   a.offsets = out->offsets;
   a.keys = bk[0];
   a.values = bv[0];
-  a.ticket = at<uint32_t>(workspace, lay.counters);
+  a.ticket = at<uint32_t>(workspace, lay.counters) + kCounterTicket;
   a.lookback = at<uint64_t>(workspace, lay.scan_lb);
   a.hist = at<uint32_t>(workspace, lay.hist);
   a.num_pairs = d_num_pairs;
@@ -303,6 +306,10 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   a.nblocks = lay.count_blocks;
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
   if (unsorted) return SS_OK;
+  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
+    return launch_digit_bases(a.hist, lay.npasses, at<uint32_t>(workspace, lay.bases),
+                              static_cast<int>(o.radix_bits), s);
+  }));
 
   std::vector<const uint64_t*> ks(lay.npasses);
   std::vector<const uint32_t*> vs(lay.npasses);
@@ -353,6 +360,10 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, nullptr, s); }));
   HistArgs h{keys_in, n, lay.npasses, at<uint32_t>(workspace, lay.hist)};
   SS_TRY(L.run(SS_KERNEL_HIST, [&] { return launch_hist(h, static_cast<int>(o.radix_bits), s); }));
+  SS_TRY(L.run(SS_KERNEL_HIST, [&] {
+    return launch_digit_bases(h.hist, lay.npasses, at<uint32_t>(workspace, lay.bases),
+                              static_cast<int>(o.radix_bits), s);
+  }));
   uint64_t* alt_k = at<uint64_t>(workspace, lay.alt_keys);
   uint32_t* alt_v = at<uint32_t>(workspace, lay.alt_vals);
   const uint32_t P = lay.npasses;

@@ -22,7 +22,7 @@ constexpr uint64_t kLbMask64 = (1ull << 61) - 1;
 // A bounded spin: after this many polls a waiting workgroup gives up, raises
 // SS_ERR_TIMEOUT in the status word and leaves (its output is then invalid,
 // but the grid always drains).  Far above any legitimate wait.
-constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

@@ -34,16 +34,15 @@ struct CountDupArgs {
 };
 
 struct PassArgs {
-  const uint64_t* kin;
+  const void* kin;            // uint64_t or uint32_t keys
   const uint32_t* vin;
-  uint64_t* kout;
+  void* kout;
   uint32_t* vout;
   const uint32_t* num_pairs;  // device M; NULL means n_fixed
   uint32_t n_fixed;
   uint32_t* status;           // device status word or NULL
   uint32_t shift;             // first key bit of this digit
-  const uint32_t* hist;       // this pass's counters in histogram copy 0
-  uint32_t hist_stride;       // words between copies
+  const uint32_t* bases;      // [bins] exclusive prefix of this pass's digit totals
   uint32_t* ticket;           // zeroed counter
   uint32_t* lookback;         // zeroed [nblocks][bins]
 };
@@ -62,7 +61,11 @@ hipError_t launch_ranges(const uint64_t* keys, const uint32_t* num_pairs, const 
                          uint32_t capacity, uint32_t num_tiles, uint32_t* ranges, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
-hipError_t launch_pass(const PassArgs& a, int radix_bits, int items, uint32_t nblocks, hipStream_t s);
+// bases[p][d] = sum over histogram copies and digits d' < d of hist[c][p][d'].
+hipError_t launch_digit_bases(const uint32_t* hist, uint32_t npasses, uint32_t* bases, int radix_bits,
+                              hipStream_t s);
+hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, uint32_t nblocks,
+                       hipStream_t s);
 
 // Sort-pass tile sizes available for each radix width.
 bool pass_config_supported(int radix_bits, int items);

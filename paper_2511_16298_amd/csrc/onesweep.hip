@@ -1,10 +1,10 @@
-// One digit pass of the stable LSD radix sort of (64-bit key, 32-bit value)
-// pairs (paper: Background, "Sorting" -- by tile, then by depth; Design,
-// "Sorting Optimizations in Context of 3DGS" -- the original method sorts a
-// 64-bit integer key).  Single-pass ("onesweep") scatter: the global digit
-// counts are known beforehand (gathered while the pairs were produced), so a
-// workgroup needs only the counts of its digit in earlier workgroups, which it
-// gets by a decoupled look-back, and then scatters its tile straight to the
+// One digit pass of the stable LSD radix sort of (key, 32-bit value) pairs
+// (paper: Background, "Sorting" -- by tile, then by depth; Design, "Sorting
+// Optimizations in Context of 3DGS" -- the original method sorts a 64-bit
+// integer key).  Single-pass ("onesweep") scatter: the global digit totals
+// are known beforehand (gathered while the pairs were produced), so a
+// workgroup needs only the counts of its digits in earlier workgroups, which
+// it gets by a decoupled look-back, and then scatters its tile straight to the
 // output.  One read and one write of every pair per pass.
 #include "common.hpp"
 #include "internal.hpp"
@@ -24,63 +24,46 @@ namespace {
 // digit group).  Slots are visited in order j = 0, 1, ..., so ranks follow
 // the input order inside the wave; waves are then offset by the counts of
 // earlier waves, and digits by a workgroup scan.  The tile is permuted into
-// digit order in LDS and written out so that runs of one digit land on
-// consecutive addresses.
-template <int RB, int ITEMS>
-__global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
+// digit order in LDS -- keys first, then values through the same buffer, to
+// keep LDS small enough for four workgroups per CU -- and written out so that
+// runs of one digit land on consecutive addresses.
+template <typename K, int RB, int ITEMS>
+struct PassSmem {
+  K buf[kPassThreads * ITEMS];  // keys, then values (as uint32)
+  uint32_t wcnt[(kPassThreads / kWave) << RB];
+  uint32_t dstart[1 << RB];
+  uint32_t gofs[1 << RB];
+  uint32_t tmp[kPassThreads / kWave];
+  uint32_t ticket;
+  uint32_t timeout;
+};
+
+// The tile body.  FULL: every one of the TILE slots holds a pair (all tiles
+// but the last), so no per-item bounds tests are needed.
+template <typename K, int RB, int ITEMS, bool FULL>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS>& sm, uint32_t t,
+                                          uint32_t base, uint32_t n) {
   constexpr int THREADS = kPassThreads;
   constexpr int WAVES = THREADS / kWave;
   constexpr int BINS = 1 << RB;
   constexpr uint32_t DMASK = BINS - 1;
   constexpr int TILE = THREADS * ITEMS;
-  constexpr int DPT = (BINS + THREADS - 1) / THREADS;  // digits per thread
-  static_assert(BINS <= THREADS * DPT, "digit ownership");
-
-  __shared__ uint64_t s_keys[TILE];
-  __shared__ uint32_t s_vals[TILE];
-  __shared__ uint32_t s_wcnt[WAVES * BINS];
-  __shared__ uint32_t s_dstart[BINS];
-  __shared__ uint32_t s_gofs[BINS];
-  __shared__ uint32_t s_tmp[WAVES];
-  __shared__ uint32_t s_ticket;
-  __shared__ uint32_t s_timeout;
-
-  if (a.status && *a.status != SS_OK) return;
-  const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_ticket = atomicAdd(a.ticket, 1u);
-    s_timeout = 0;
-  }
-  for (int i = tid; i < WAVES * BINS; i += THREADS) s_wcnt[i] = 0;
-  __syncthreads();
-  const uint32_t t = s_ticket;
-  const uint32_t base = t * TILE;
-  if (base >= n) return;  // uniform over the workgroup
-
-  // ---- global digit totals (sum of the histogram copies) ----
-  uint32_t gcnt[DPT];
-#pragma unroll
-  for (int i = 0; i < DPT; ++i) {
-    const int d = tid * DPT + i;
-    uint32_t s = 0;
-    if (d < BINS)
-      for (uint32_t c = 0; c < kHistCopies; ++c) s += a.hist[c * a.hist_stride + d];
-    gcnt[i] = s;
-  }
+  const uint32_t gbase = tid < BINS ? a.bases[tid] : 0u;
 
   // ---- load (wave-striped) ----
+  const K* __restrict__ kin = static_cast<const K*>(a.kin);
   const uint32_t lane = lane_id();
   const uint32_t wave = tid / kWave;
   const uint32_t seg = base + wave * (kWave * ITEMS);
-  uint64_t k[ITEMS];
+  K k[ITEMS];
   uint32_t v[ITEMS];
   uint32_t dg[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t idx = seg + j * kWave + lane;
-    if (idx < n) {
-      k[j] = a.kin[idx];
+    if (FULL || idx < n) {
+      k[j] = kin[idx];
       v[j] = a.vin[idx];
       dg[j] = static_cast<uint32_t>(k[j] >> a.shift) & DMASK;
     } else {
@@ -91,18 +74,28 @@ __global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
   }
 
   // ---- stable rank inside the wave ----
-  uint32_t* wc = s_wcnt + wave * BINS;
-  uint32_t rank[ITEMS];
+  // peers = lanes whose digit equals this lane's: for every digit bit b,
+  // keep the ballot of b where this lane's bit is set, its complement
+  // elsewhere (t = 0 or ~0 from a signed one-bit field extract).
+  uint32_t* wc = sm.wcnt + wave * BINS;
+  uint32_t pos[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const bool valid = dg[j] < BINS;
-    uint64_t peers = ballot(valid);
+    const bool valid = FULL || dg[j] < BINS;
+    uint32_t plo = ~0u, phi = ~0u;
+    if (!FULL) {
+      const uint64_t vm = ballot(valid);
+      plo = static_cast<uint32_t>(vm);
+      phi = static_cast<uint32_t>(vm >> 32);
+    }
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      const bool bit = (dg[j] >> b) & 1u;
-      const uint64_t m = ballot(bit);
-      peers &= bit ? m : ~m;
+      const uint32_t tb = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(dg[j]), b, 1));
+      const uint64_t m = ballot(tb != 0);
+      plo &= ~(static_cast<uint32_t>(m) ^ tb);
+      phi &= ~(static_cast<uint32_t>(m >> 32) ^ tb);
     }
+    const uint64_t peers = (static_cast<uint64_t>(phi) << 32) | plo;
     uint32_t r = 0;
     if (valid) {
       const uint32_t old = wc[dg[j]];
@@ -112,106 +105,120 @@ __global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
       if (below == 0) wc[dg[j]] = old + static_cast<uint32_t>(__popcll(peers));
     }
     __builtin_amdgcn_wave_barrier();
-    rank[j] = r;
+    pos[j] = r;
   }
   __syncthreads();
 
   // ---- per digit: offsets of the waves, workgroup count, publish ----
-  uint32_t bcnt[DPT];
-  uint32_t tsum = 0, gsum = 0;
+  uint32_t bcnt = 0;
+  if (tid < BINS) {
 #pragma unroll
-  for (int i = 0; i < DPT; ++i) {
-    const int d = tid * DPT + i;
-    uint32_t s = 0;
-    if (d < BINS) {
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        const uint32_t c = s_wcnt[w * BINS + d];
-        s_wcnt[w * BINS + d] = s;
-        s += c;
-      }
-      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + d], (t == 0 ? kLbInc32 : kLbAgg32) | s);
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = sm.wcnt[w * BINS + tid];
+      sm.wcnt[w * BINS + tid] = bcnt;
+      bcnt += c;
     }
-    bcnt[i] = s;
-    tsum += s;
-    gsum += gcnt[i];
+    st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
   }
   uint32_t total;
-  const uint32_t lexcl = block_exclusive_scan<uint32_t, THREADS>(tsum, s_tmp, total);
-  const uint32_t gexcl = block_exclusive_scan<uint32_t, THREADS>(gsum, s_tmp, total);
-  {
-    uint32_t run = lexcl;
-#pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      const int d = tid * DPT + i;
-      if (d < BINS) s_dstart[d] = run;
-      run += bcnt[i];
-    }
-  }
+  const uint32_t lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, sm.tmp, total);
+  if (tid < BINS) sm.dstart[tid] = lexcl;
   __syncthreads();
 
-  // ---- permute the tile into digit order in LDS ----
+  // ---- permute the keys into digit order in LDS ----
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    if (dg[j] < BINS) {
-      const uint32_t pos = s_dstart[dg[j]] + wc[dg[j]] + rank[j];
-      s_keys[pos] = k[j];
-      s_vals[pos] = v[j];
+    if (FULL || dg[j] < BINS) {
+      pos[j] += sm.dstart[dg[j]] + wc[dg[j]];
+      sm.buf[pos[j]] = k[j];
     }
   }
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
-  {
-    uint32_t grun = gexcl;
-#pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      const int d = tid * DPT + i;
-      if (d < BINS) {
-        uint32_t excl = 0;
-        if (t > 0) {
-          int32_t kb = static_cast<int32_t>(t) - 1;
-          uint32_t spins = 0;
-          while (true) {
-            const uint32_t w = ld_agent(&a.lookback[static_cast<size_t>(kb) * BINS + d]);
-            if ((w & ~kLbMask32) == 0) {
-              if (++spins > kSpinLimit) {
-                s_timeout = 1;
-                if (a.status) st_agent(a.status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
-                break;
-              }
-              __builtin_amdgcn_s_sleep(1);
-              continue;
-            }
-            excl += w & kLbMask32;
-            if (w & kLbInc32) break;
-            --kb;
+  if (tid < BINS) {
+    uint32_t excl = 0;
+    if (t > 0) {
+      int32_t kb = static_cast<int32_t>(t) - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const uint32_t w = ld_agent(&a.lookback[static_cast<size_t>(kb) * BINS + tid]);
+        if ((w & ~kLbMask32) == 0) {
+          if (++spins > kSpinLimit) {
+            sm.timeout = 1;
+            if (a.status) st_agent(a.status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
+            break;
           }
-          st_agent(&a.lookback[static_cast<size_t>(t) * BINS + d], kLbInc32 | (excl + bcnt[i]));
+          __builtin_amdgcn_s_sleep(1);
+          continue;
         }
-        s_gofs[d] = grun + excl - s_dstart[d];
+        excl += w & kLbMask32;
+        if (w & kLbInc32) break;
+        --kb;
       }
-      grun += gcnt[i];
+      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], kLbInc32 | (excl + bcnt));
+    }
+    sm.gofs[tid] = gbase + excl - lexcl;
+  }
+  __syncthreads();
+  if (sm.timeout) return;
+
+  // ---- write keys: LDS slot i goes to global position gofs[digit] + i ----
+  K* __restrict__ kout = static_cast<K*>(a.kout);
+  const uint32_t valid_n = FULL ? TILE : ((n - base) < static_cast<uint32_t>(TILE) ? (n - base) : TILE);
+  uint32_t dst[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = j * THREADS + tid;
+    dst[j] = 0xFFFFFFFFu;
+    if (FULL || i < valid_n) {
+      const K key = sm.buf[i];
+      const uint32_t o = sm.gofs[static_cast<uint32_t>(key >> a.shift) & DMASK] + i;
+      if (o < n) {
+        kout[o] = key;
+        dst[j] = o;
+      }
     }
   }
   __syncthreads();
-  if (s_timeout) return;
 
-  // ---- write out: LDS slot i goes to global position gofs[digit] + i ----
-  const uint32_t valid_n = (n - base) < static_cast<uint32_t>(TILE) ? (n - base) : TILE;
-  for (uint32_t i = tid; i < valid_n; i += THREADS) {
-    const uint64_t key = s_keys[i];
-    const uint32_t d = static_cast<uint32_t>(key >> a.shift) & DMASK;
-    const uint32_t o = s_gofs[d] + i;
-    if (o < n) {
-      a.kout[o] = key;
-      a.vout[o] = s_vals[i];
-    }
+  // ---- values through the same buffer ----
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(sm.buf);
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (FULL || dg[j] < BINS) s_val[pos[j]] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t i = j * THREADS + tid;
+    if (dst[j] != 0xFFFFFFFFu) a.vout[dst[j]] = s_val[i];
   }
 }
 
-template <int RB, int ITEMS>
+template <typename K, int RB, int ITEMS>
+__global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
+  constexpr int TILE = kPassThreads * ITEMS;
+  __shared__ PassSmem<K, RB, ITEMS> sm;
+  if (a.status && *a.status != SS_OK) return;
+  const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    sm.ticket = atomicAdd(a.ticket, 1u);
+    sm.timeout = 0;
+  }
+  for (int i = tid; i < (kPassThreads / kWave) << RB; i += kPassThreads) sm.wcnt[i] = 0;
+  __syncthreads();
+  const uint32_t t = sm.ticket;
+  const uint32_t base = t * TILE;
+  if (base >= n) return;  // uniform over the workgroup
+  if (n - base >= static_cast<uint32_t>(TILE))
+    pass_tile<K, RB, ITEMS, true>(a, sm, t, base, n);
+  else
+    pass_tile<K, RB, ITEMS, false>(a, sm, t, base, n);
+}
+
+template <typename K, int RB, int ITEMS>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_onesweep<RB, ITEMS>), dim3(nblocks), dim3(kPassThreads), 0, s, a);
+  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS>), dim3(nblocks), dim3(kPassThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -223,13 +230,15 @@ bool pass_config_supported(int radix_bits, int items) {
   return rb_ok && it_ok;
 }
 
-hipError_t launch_pass(const PassArgs& a, int radix_bits, int items, uint32_t nblocks, hipStream_t s) {
+hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, uint32_t nblocks,
+                       hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-#define SS_PASS_CASE(RB, IT) \
-  if (radix_bits == RB && items == IT) return pass_launch<RB, IT>(a, nblocks, s);
-  SS_PASS_CASE(8, 16) SS_PASS_CASE(8, 12) SS_PASS_CASE(8, 8)
-  SS_PASS_CASE(6, 16) SS_PASS_CASE(6, 12) SS_PASS_CASE(6, 8)
-  SS_PASS_CASE(4, 16) SS_PASS_CASE(4, 12) SS_PASS_CASE(4, 8)
+#define SS_PASS_CASE(K, RB, IT) \
+  if (key_bytes == sizeof(K) && radix_bits == RB && items == IT) return pass_launch<K, RB, IT>(a, nblocks, s);
+  SS_PASS_CASE(uint64_t, 8, 16) SS_PASS_CASE(uint64_t, 8, 12) SS_PASS_CASE(uint64_t, 8, 8)
+  SS_PASS_CASE(uint64_t, 6, 16) SS_PASS_CASE(uint64_t, 6, 12) SS_PASS_CASE(uint64_t, 6, 8)
+  SS_PASS_CASE(uint64_t, 4, 16) SS_PASS_CASE(uint64_t, 4, 12) SS_PASS_CASE(uint64_t, 4, 8)
+  SS_PASS_CASE(uint32_t, 8, 16) SS_PASS_CASE(uint32_t, 8, 12) SS_PASS_CASE(uint32_t, 8, 8)
 #undef SS_PASS_CASE
   return hipErrorInvalidValue;
 }

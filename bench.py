@@ -6,10 +6,23 @@ default workload is the full-HD frame (1920x1080, 8,160 tiles, N = 1,000,000
 Gaussians, about 4.8M pairs).  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Profiles (run under rocprofv3, then summarised into profiles/ with
+``--summarize-profiles DIR``; the exact commands are written into each summary):
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- \
+        python3 bench.py --steps 20 --warmup 5 --no-cpu-baseline
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- \
+        python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-mib 512
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- \
+        python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-mib 512
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +36,9 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
+PASS_SOURCE = os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "onesweep.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+PASS_KERNEL = "k_onesweep"
 
 
 def parse():
@@ -33,10 +49,86 @@ def parse():
     p.add_argument("--workload", default="fullhd-1m", choices=sorted(synth.FRAME_WORKLOADS))
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
+    p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle baseline (whole frames until exceeded)")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="run one streaming copy of this size first (traffic-counter calibration)")
+    p.add_argument("--summarize-profiles", metavar="DIR",
+                   help="summarise rocprofv3 output under DIR/{stats,fetch,write} into profiles/ and exit")
     return p.parse_args()
+
+
+def source_hash(path: str = PASS_SOURCE) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _rows(pattern: str):
+    files = sorted(glob.glob(pattern))
+    if not files:
+        raise SystemExit(f"no rocprofv3 csv matches {pattern}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
+    """Write the kernel-time and HBM-traffic summaries of the pass kernel."""
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = _rows(os.path.join(d, "stats", "*kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel statistics, workload {workload}",
+             "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
+             "python3 bench.py --steps 20 --warmup 5 --no-cpu-baseline",
+             f"pass-kernel source sha256[:16]: {source_hash()}", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        short = name.replace("ss::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        if short.startswith("at::") or "rocclr" in short:
+            continue
+        lines.append(f"| {short} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    with open(os.path.join(PROFILES, f"kernel_stats_{workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_kernel(kind):
+        rows = _rows(os.path.join(d, kind, "*counter_collection.csv"))
+        copy = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
+        passes = [float(r["Counter_Value"]) for r in rows if PASS_KERNEL in r["Kernel_Name"]]
+        return copy, passes
+    fc, fp = per_kernel("fetch")
+    wc, wp = per_kernel("write")
+    kib = copy_mib * 1024.0
+    f_scale, w_scale = kib / (sum(fc) / len(fc)), kib / (sum(wc) / len(wc))
+    fetch = sum(fp) / len(fp) * f_scale * 1024.0
+    write = sum(wp) / len(wp) * w_scale * 1024.0
+    rec = {"kernel": PASS_KERNEL, "workload": workload, "source_sha256_16": source_hash(),
+           "copy_calibration_mib": copy_mib, "fetch_scale": f_scale, "write_scale": w_scale,
+           "dispatches": len(fp), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "traffic_bytes_per_launch": fetch + write,
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py "
+                        f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py "
+                        f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}"]}
+    with open(os.path.join(PROFILES, f"{PASS_KERNEL}_{workload}_traffic.txt"), "w") as f:
+        f.write("# HBM traffic of one sort pass (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
+                "# the scales make a plain copy of copy_calibration_mib MiB read and write exactly that)\n")
+        f.write(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec))
+
+
+def profiled_traffic(workload: str):
+    """Traffic per pass launch from the committed profile, if it was taken on
+    the current pass-kernel source; else None."""
+    path = os.path.join(PROFILES, f"{PASS_KERNEL}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    rec = json.loads(text[text.index("{"):])
+    if rec.get("source_sha256_16") != source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def pct(a, q):
@@ -45,6 +137,9 @@ def pct(a, q):
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "
               "frames shard across GPUs without communication; run it with --gpus 1", file=sys.stderr)
@@ -62,11 +157,19 @@ def main():
     _, _, m_t, s_t = ss.count_pairs(d, spec.width, spec.height)
     assert int(s_t.item()) == 0
     M = int(m_t.item()) & 0xFFFFFFFF
-    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev)
+    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev,
+                            workgroup_size=args.wg)
     tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
     rb = args.radix_bits or 8
     passes = -(-key_bits // rb)
     stream = torch.cuda.current_stream()
+    if args.copy_mib:
+        nb = args.copy_mib << 20
+        a = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        ss.copy_bytes(b, a, nb, stream)
+        torch.cuda.synchronize()
+        del a, b
 
     print(f"# workload {args.workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
           f"T={tx * ty}, key bits {key_bits}, passes {passes}", file=sys.stderr, flush=True)
@@ -137,7 +240,7 @@ def main():
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99), "max": max(step_ms)},
         "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": profiled_traffic(args.workload),
                      "bytes_per_launch": pass_bytes, "avg_launch_us": pass_us},
         "step_model": {"bytes": step_bytes, "GB/s": step_bytes / (ms_per_step * 1e-3) / 1e9,
                        "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS},

@@ -93,9 +93,14 @@ typedef struct ss_timer ss_timer;
 typedef struct ss_options {
   uint32_t struct_size;
   uint32_t radix_bits;     /* 0 = default (8); supported: 4, 6, 8 */
-  uint32_t items_per_thread; /* 0 = default; sort-pass tile = 256 * items */
+  uint32_t items_per_thread; /* 0 = default (16); supported: 8, 12, 16 */
   uint32_t flags;          /* 0, or SS_FLAG_UNSORTED */
   ss_timer* timer;         /* optional: record HIP events around every kernel */
+  uint32_t workgroup_size; /* sort-pass threads: 0 = default (512 where
+                              supported, else 256); 512 needs radix_bits 8
+                              and items 8 or 16.  A pass tile holds
+                              workgroup_size * items_per_thread pairs. */
+  uint32_t reserved;
 } ss_options;
 
 /* Stop after step a3: keys/values receive the duplicated pairs in
@@ -163,7 +168,10 @@ typedef enum ss_kernel_kind {
 
 /* Event pool for per-kernel timing.  Create once (host), pass in
  * ss_options.timer, synchronise the stream, then read the summed time and
- * launch count per kernel kind.  Reset before reuse.  Not thread-safe. */
+ * launch count per kernel kind.  The sort passes of one call are timed as
+ * one group (no events between them); their launch count is the number of
+ * passes.  max_launches bounds the number of event pairs.  Reset before
+ * reuse.  Not thread-safe. */
 ss_status ss_timer_create(ss_timer** timer, uint32_t max_launches);
 ss_status ss_timer_reset(ss_timer* timer);
 ss_status ss_timer_read(ss_timer* timer, uint32_t kind, double* total_ms, uint32_t* launches);

@@ -114,7 +114,7 @@ class FrameSorter:
 
     def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
                  radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
-                 device="cuda", unsorted: bool = False):
+                 device="cuda", unsorted: bool = False, workgroup_size: int = 0):
         torch = _torch()
         self.width, self.height = width, height
         self.num_gaussians = num_gaussians
@@ -122,7 +122,8 @@ class FrameSorter:
         self.tiles_x, self.tiles_y, self.key_bits = geometry(width, height)
         self.num_tiles = self.tiles_x * self.tiles_y
         self.options = make_options(radix_bits, items_per_thread,
-                                    flags=_abi.SS_FLAG_UNSORTED if unsorted else 0)
+                                    flags=_abi.SS_FLAG_UNSORTED if unsorted else 0,
+                                    workgroup_size=workgroup_size)
         probe = ss_frame()
         probe.width, probe.height, probe.tile_px, probe.num_gaussians = width, height, 16, num_gaussians
         probe.gaussians = 16 if num_gaussians else None   # only shape matters here
@@ -202,12 +203,13 @@ def sort_frame(records, width: int, height: int, capacity: Optional[int] = None,
 
 
 def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, items_per_thread: int = 0,
-               timer: Optional[Timer] = None):
+               timer: Optional[Timer] = None, workgroup_size: int = 0):
     """Step a4 alone: stable sort of (int64 keys, int32 values) by key bits
     [0, key_bits).  Returns new (keys, values) tensors."""
     torch = _torch()
     n = int(keys.shape[0])
-    opts = make_options(radix_bits, items_per_thread, timer.handle if timer is not None else None)
+    opts = make_options(radix_bits, items_per_thread, timer.handle if timer is not None else None,
+                        workgroup_size=workgroup_size)
     st, ws = _abi.ss_sort_pairs_workspace_bytes(n, key_bits, opts)
     check(st, "ss_sort_pairs_workspace_bytes")
     work = torch.empty(max(ws, 256), dtype=torch.uint8, device=keys.device)

@@ -54,16 +54,20 @@ class ss_frame_out(ctypes.Structure):
 class ss_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
                 ("items_per_thread", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("timer", ctypes.c_void_p)]
+                ("timer", ctypes.c_void_p), ("workgroup_size", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
-def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, flags: int = 0) -> ss_options:
+def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, flags: int = 0,
+                 workgroup_size: int = 0) -> ss_options:
     o = ss_options()
     o.struct_size = ctypes.sizeof(ss_options)
     o.radix_bits = radix_bits
     o.items_per_thread = items_per_thread
     o.flags = flags
     o.timer = timer
+    o.workgroup_size = workgroup_size
+    o.reserved = 0
     return o
 
 

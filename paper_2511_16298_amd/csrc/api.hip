@@ -13,6 +13,7 @@ namespace {
 
 constexpr uint32_t kDefaultRadix = 8;
 constexpr uint32_t kDefaultItems = 16;
+constexpr uint32_t kDefaultThreads = 512;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -26,6 +27,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) &
 struct Options {
   uint32_t radix_bits = kDefaultRadix;
   uint32_t items = kDefaultItems;
+  uint32_t threads = kDefaultThreads;
   uint32_t flags = 0;
   ss_timer* timer = nullptr;
 };
@@ -38,7 +40,12 @@ ss_status parse_options(const ss_options* o, Options* out) {
   out->flags = o->flags;
   if (o->radix_bits != 0) out->radix_bits = o->radix_bits;
   if (o->items_per_thread != 0) out->items = o->items_per_thread;
-  if (!pass_config_supported(static_cast<int>(out->radix_bits), static_cast<int>(out->items)))
+  // default workgroup: 512 where that configuration exists, else 256
+  out->threads = pass_config_supported(static_cast<int>(out->radix_bits), static_cast<int>(out->items), 512)
+                     ? 512u : 256u;
+  if (o->workgroup_size != 0) out->threads = o->workgroup_size;
+  if (!pass_config_supported(static_cast<int>(out->radix_bits), static_cast<int>(out->items),
+                             static_cast<int>(out->threads)))
     return SS_ERR_UNSUPPORTED;
   out->timer = o->timer;
   return SS_OK;
@@ -78,7 +85,7 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
   L.bins = 1u << o.radix_bits;
   L.npasses = (key_bits + o.radix_bits - 1) / o.radix_bits;
   L.count_blocks = n_gauss == 0 ? 1u : (n_gauss + kCountTile - 1) / kCountTile;
-  L.tile = kPassThreads * o.items;
+  L.tile = o.threads * o.items;
   L.pass_blocks = (capacity + L.tile - 1) / L.tile;
   size_t off = 0;
   L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
@@ -103,8 +110,9 @@ T* at(void* ws, size_t off) {
 }  // namespace ss
 
 struct ss_timer {
-  std::vector<hipEvent_t> events;  // two per launch
+  std::vector<hipEvent_t> events;  // two per record
   std::vector<uint32_t> kinds;
+  std::vector<uint32_t> launches;  // kernels covered by each record
   uint32_t used = 0;
 };
 
@@ -117,13 +125,21 @@ class Launcher {
   Launcher(hipStream_t s, ss_timer* t) : s_(s), t_(t) {}
   template <typename F>
   ss_status run(uint32_t kind, F&& launch) {
+    return run_group(kind, 1, [&] { return launch() == hipSuccess ? SS_OK : SS_ERR_HIP; });
+  }
+  // Several consecutive launches of one kind under a single pair of events
+  // (no event between them, so their own durations are not inflated).
+  template <typename F>
+  ss_status run_group(uint32_t kind, uint32_t count, F&& launches) {
     int slot = -1;
     if (t_ != nullptr && t_->used < t_->kinds.size()) {
       slot = static_cast<int>(t_->used++);
       t_->kinds[slot] = kind;
+      t_->launches[slot] = count;
       if (hipEventRecord(t_->events[2 * slot], s_) != hipSuccess) return SS_ERR_HIP;
     }
-    if (launch() != hipSuccess) return SS_ERR_HIP;
+    const ss_status st = launches();
+    if (st != SS_OK) return st;
     if (slot >= 0 && hipEventRecord(t_->events[2 * slot + 1], s_) != hipSuccess) return SS_ERR_HIP;
     return SS_OK;
   }
@@ -148,6 +164,7 @@ ss_status run_passes(Launcher& L, const Layout& lay, const Options& o, void* ws,
                      uint32_t* d_status, hipStream_t s) {
   uint32_t* counters = at<uint32_t>(ws, lay.counters);
   uint32_t* plb = at<uint32_t>(ws, lay.pass_lb);
+  return L.run_group(SS_KERNEL_SORT_PASS, lay.npasses, [&]() -> ss_status {
   for (uint32_t p = 0; p < lay.npasses; ++p) {
     PassArgs a{};
     a.kin = ksrc[p];
@@ -161,11 +178,12 @@ ss_status run_passes(Launcher& L, const Layout& lay, const Options& o, void* ws,
     a.bases = at<uint32_t>(ws, lay.bases) + static_cast<size_t>(p) * lay.bins;
     a.ticket = counters + kCounterPass + p;
     a.lookback = plb + static_cast<size_t>(p) * lay.pass_blocks * lay.bins;
-    SS_TRY(L.run(SS_KERNEL_SORT_PASS, [&] {
-      return launch_pass(a, 8, static_cast<int>(o.radix_bits), static_cast<int>(o.items), lay.pass_blocks, s);
-    }));
+    if (launch_pass(a, 8, static_cast<int>(o.radix_bits), static_cast<int>(o.items), static_cast<int>(o.threads),
+                    lay.pass_blocks, s) != hipSuccess)
+      return SS_ERR_HIP;
   }
   return SS_OK;
+  });
 }
 
 }  // namespace
@@ -398,6 +416,7 @@ ss_status ss_timer_create(ss_timer** timer, uint32_t max_launches) {
   if (t == nullptr) return SS_ERR_HIP;
   t->events.resize(2 * static_cast<size_t>(max_launches));
   t->kinds.resize(max_launches);
+  t->launches.resize(max_launches);
   for (size_t i = 0; i < t->events.size(); ++i) {
     if (hipEventCreate(&t->events[i]) != hipSuccess) {
       for (size_t j = 0; j < i; ++j) (void)hipEventDestroy(t->events[j]);
@@ -424,7 +443,7 @@ ss_status ss_timer_read(ss_timer* timer, uint32_t kind, double* total_ms, uint32
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, timer->events[2 * i], timer->events[2 * i + 1]) != hipSuccess) return SS_ERR_HIP;
     sum += ms;
-    ++cnt;
+    cnt += timer->launches[i];
   }
   *total_ms = sum;
   *launches = cnt;

@@ -10,7 +10,6 @@ namespace ss {
 
 // Gaussians per workgroup of the fused count / scan / duplicate kernel.
 constexpr uint32_t kCountTile = 1024;
-constexpr uint32_t kPassThreads = 256;
 // Histogram copies: workgroups spread their global atomics over this many
 // copies to cut same-address contention; passes sum the copies.
 constexpr uint32_t kHistCopies = 8;
@@ -64,10 +63,11 @@ hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
 // bases[p][d] = sum over histogram copies and digits d' < d of hist[c][p][d'].
 hipError_t launch_digit_bases(const uint32_t* hist, uint32_t npasses, uint32_t* bases, int radix_bits,
                               hipStream_t s);
-hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, uint32_t nblocks,
+hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s);
 
-// Sort-pass tile sizes available for each radix width.
-bool pass_config_supported(int radix_bits, int items);
+// Sort-pass configurations (radix width, items per thread, workgroup size)
+// compiled into the library.
+bool pass_config_supported(int radix_bits, int items, int threads);
 
 }  // namespace ss

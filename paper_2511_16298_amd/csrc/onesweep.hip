@@ -27,23 +27,22 @@ namespace {
 // digit order in LDS -- keys first, then values through the same buffer, to
 // keep LDS small enough for four workgroups per CU -- and written out so that
 // runs of one digit land on consecutive addresses.
-template <typename K, int RB, int ITEMS>
+template <typename K, int RB, int ITEMS, int THREADS>
 struct PassSmem {
-  K buf[kPassThreads * ITEMS];  // keys, then values (as uint32)
-  uint32_t wcnt[(kPassThreads / kWave) << RB];
+  K buf[THREADS * ITEMS];  // keys, then values (as uint32)
+  uint32_t wcnt[(THREADS / kWave) << RB];
   uint32_t dstart[1 << RB];
   uint32_t gofs[1 << RB];
-  uint32_t tmp[kPassThreads / kWave];
+  uint32_t tmp[THREADS / kWave];
   uint32_t ticket;
   uint32_t timeout;
 };
 
 // The tile body.  FULL: every one of the TILE slots holds a pair (all tiles
 // but the last), so no per-item bounds tests are needed.
-template <typename K, int RB, int ITEMS, bool FULL>
-__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS>& sm, uint32_t t,
+template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
                                           uint32_t base, uint32_t n) {
-  constexpr int THREADS = kPassThreads;
   constexpr int WAVES = THREADS / kWave;
   constexpr int BINS = 1 << RB;
   constexpr uint32_t DMASK = BINS - 1;
@@ -194,10 +193,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   }
 }
 
-template <typename K, int RB, int ITEMS>
-__global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
-  constexpr int TILE = kPassThreads * ITEMS;
-  __shared__ PassSmem<K, RB, ITEMS> sm;
+template <typename K, int RB, int ITEMS, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
+  constexpr int TILE = THREADS * ITEMS;
+  __shared__ PassSmem<K, RB, ITEMS, THREADS> sm;
   if (a.status && *a.status != SS_OK) return;
   const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
   const int tid = threadIdx.x;
@@ -205,40 +204,44 @@ __global__ __launch_bounds__(kPassThreads) void k_onesweep(PassArgs a) {
     sm.ticket = atomicAdd(a.ticket, 1u);
     sm.timeout = 0;
   }
-  for (int i = tid; i < (kPassThreads / kWave) << RB; i += kPassThreads) sm.wcnt[i] = 0;
+  for (int i = tid; i < (THREADS / kWave) << RB; i += THREADS) sm.wcnt[i] = 0;
   __syncthreads();
   const uint32_t t = sm.ticket;
   const uint32_t base = t * TILE;
   if (base >= n) return;  // uniform over the workgroup
   if (n - base >= static_cast<uint32_t>(TILE))
-    pass_tile<K, RB, ITEMS, true>(a, sm, t, base, n);
+    pass_tile<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n);
   else
-    pass_tile<K, RB, ITEMS, false>(a, sm, t, base, n);
+    pass_tile<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n);
 }
 
-template <typename K, int RB, int ITEMS>
+template <typename K, int RB, int ITEMS, int THREADS>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS>), dim3(nblocks), dim3(kPassThreads), 0, s, a);
+  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS>), dim3(nblocks), dim3(THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-bool pass_config_supported(int radix_bits, int items) {
+bool pass_config_supported(int radix_bits, int items, int threads) {
   const bool rb_ok = radix_bits == 4 || radix_bits == 6 || radix_bits == 8;
   const bool it_ok = items == 8 || items == 12 || items == 16;
-  return rb_ok && it_ok;
+  const bool th_ok = threads == 256 || (threads == 512 && radix_bits == 8 && (items == 8 || items == 16));
+  return rb_ok && it_ok && th_ok;
 }
 
-hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, uint32_t nblocks,
+hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-#define SS_PASS_CASE(K, RB, IT) \
-  if (key_bytes == sizeof(K) && radix_bits == RB && items == IT) return pass_launch<K, RB, IT>(a, nblocks, s);
-  SS_PASS_CASE(uint64_t, 8, 16) SS_PASS_CASE(uint64_t, 8, 12) SS_PASS_CASE(uint64_t, 8, 8)
-  SS_PASS_CASE(uint64_t, 6, 16) SS_PASS_CASE(uint64_t, 6, 12) SS_PASS_CASE(uint64_t, 6, 8)
-  SS_PASS_CASE(uint64_t, 4, 16) SS_PASS_CASE(uint64_t, 4, 12) SS_PASS_CASE(uint64_t, 4, 8)
-  SS_PASS_CASE(uint32_t, 8, 16) SS_PASS_CASE(uint32_t, 8, 12) SS_PASS_CASE(uint32_t, 8, 8)
+#define SS_PASS_CASE(K, RB, IT, TH)                                                        \
+  if (key_bytes == sizeof(K) && radix_bits == RB && items == IT && threads == TH) \
+    return pass_launch<K, RB, IT, TH>(a, nblocks, s);
+  SS_PASS_CASE(uint64_t, 8, 16, 256) SS_PASS_CASE(uint64_t, 8, 12, 256) SS_PASS_CASE(uint64_t, 8, 8, 256)
+  SS_PASS_CASE(uint64_t, 6, 16, 256) SS_PASS_CASE(uint64_t, 6, 12, 256) SS_PASS_CASE(uint64_t, 6, 8, 256)
+  SS_PASS_CASE(uint64_t, 4, 16, 256) SS_PASS_CASE(uint64_t, 4, 12, 256) SS_PASS_CASE(uint64_t, 4, 8, 256)
+  SS_PASS_CASE(uint64_t, 8, 16, 512) SS_PASS_CASE(uint64_t, 8, 8, 512)
+  SS_PASS_CASE(uint32_t, 8, 16, 256) SS_PASS_CASE(uint32_t, 8, 12, 256) SS_PASS_CASE(uint32_t, 8, 8, 256)
+  SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512)
 #undef SS_PASS_CASE
   return hipErrorInvalidValue;
 }

@@ -208,8 +208,10 @@ def main():
     torch.cuda.synchronize()
     instr_ms_per_step = evk0.elapsed_time(evk1) / K
     kern = {}
-    for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count_scan_dup", _abi.SS_KERNEL_COUNT_DUP),
-                       ("sort_pass", _abi.SS_KERNEL_SORT_PASS), ("ranges", _abi.SS_KERNEL_RANGES)):
+    for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count", _abi.SS_KERNEL_COUNT_DUP),
+                       ("digit_bases", _abi.SS_KERNEL_DIGIT_BASES), ("depth_pass", _abi.SS_KERNEL_DEPTH_PASS),
+                       ("expand", _abi.SS_KERNEL_EXPAND), ("sort_pass", _abi.SS_KERNEL_SORT_PASS),
+                       ("ranges", _abi.SS_KERNEL_RANGES)):
         ms, n = timer.read(kind)
         kern[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "us_per_step": 1e3 * ms / K}
     timer.close()

@@ -100,8 +100,20 @@ typedef struct ss_options {
                               supported, else 256); 512 needs radix_bits 8
                               and items 8 or 16.  A pass tile holds
                               workgroup_size * items_per_thread pairs. */
-  uint32_t reserved;
+  uint32_t algorithm;      /* SS_ALGO_*; both give bit-identical results */
 } ss_options;
+
+/* SS_ALGO_DIRECT: duplicate in index order, then ceil((ceil(log2 T) + 32) /
+ * radix_bits) passes over all M pairs.  SS_ALGO_DEPTH_FIRST: sort the N
+ * Gaussians by depth first (four 8-bit passes over N), duplicate in depth
+ * order, then sort the pairs by tile id alone (ceil(log2 T) bits, 8-bit
+ * digits); a Gaussian adds at most one pair per tile, so the stable tile
+ * sort leaves each tile in (depth, index) order.  radix_bits, items and
+ * workgroup_size apply to the passes over the pairs.  AUTO = DEPTH_FIRST,
+ * except that SS_FLAG_UNSORTED implies DIRECT. */
+#define SS_ALGO_AUTO 0u
+#define SS_ALGO_DEPTH_FIRST 1u
+#define SS_ALGO_DIRECT 2u
 
 /* Stop after step a3: keys/values receive the duplicated pairs in
  * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no
@@ -138,6 +150,30 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out,
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
 
+/* Many frames in one segmented sort (up to SS_MAX_BATCH_FRAMES).  Frame f's
+ * tiles are renumbered tile_base[f] + t, tile_base the exclusive prefix sum
+ * of the frames' tile counts; keys hold global tile ids, values frame-local
+ * Gaussian indices.  Frame f's pairs are one contiguous segment, equal to
+ * what ss_sort_frame gives for frame f alone (with its keys' tile part
+ * offset by tile_base[f]).  Always the depth-first algorithm. */
+#define SS_MAX_BATCH_FRAMES 256u
+typedef struct ss_batch_out {
+  uint32_t pair_capacity;   /* entries of keys/values for all frames together */
+  uint64_t* keys;           /* device [pair_capacity] */
+  uint32_t* values;         /* device [pair_capacity] */
+  uint32_t* tile_ranges;    /* device [2 * sum of T]: global pair indices */
+  uint32_t* frame_pairs;    /* device [n_frames]: pairs of each frame, or NULL */
+  uint32_t* frame_pair_base;/* device [n_frames]: first pair of each frame, or NULL */
+  uint32_t* num_pairs;      /* device scalar: all pairs, or NULL */
+  uint32_t* status;         /* device scalar ss_status, or NULL */
+} ss_batch_out;
+
+ss_status ss_batch_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uint32_t pair_capacity,
+                                   const ss_options* options, size_t* bytes);
+ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batch_out* out,
+                        void* workspace, size_t workspace_bytes, void* stream,
+                        const ss_options* options);
+
 /* Step a4 alone on caller data (the paper's random key-value sort benchmark,
  * Evaluation, "Datasets"): stable sort of n pairs by key bits [0, key_bits);
  * keys must be < 2^key_bits.  keys_in/values_in are not modified; they may
@@ -157,13 +193,15 @@ ss_status ss_copy_bytes(void* d_dst, const void* d_src, size_t bytes, void* stre
 
 typedef enum ss_kernel_kind {
   SS_KERNEL_CLEAR = 0,      /* zeroes counters and look-back state */
-  SS_KERNEL_COUNT_DUP = 1,  /* a1+a2+a3 fused */
+  SS_KERNEL_COUNT_DUP = 1,  /* direct: a1+a2+a3 fused; depth-first: a1 (counts, keys) */
   SS_KERNEL_SORT_PASS = 2,  /* one a4 digit pass */
   SS_KERNEL_RANGES = 3,     /* a5 */
   SS_KERNEL_COPY = 4,       /* ss_copy_bytes */
   SS_KERNEL_HIST = 5,       /* digit histograms of caller keys (ss_sort_pairs) */
   SS_KERNEL_DIGIT_BASES = 6, /* exclusive prefix of the digit totals */
-  SS_KERNEL_KINDS = 8
+  SS_KERNEL_DEPTH_PASS = 7, /* depth-first: one pass of the Gaussian depth sort */
+  SS_KERNEL_EXPAND = 8,     /* depth-first: pairs in depth order */
+  SS_KERNEL_KINDS = 9
 } ss_kernel_kind;
 
 /* Event pool for per-kernel timing.  Create once (host), pass in

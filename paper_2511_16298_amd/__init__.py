@@ -14,10 +14,12 @@ import dataclasses
 from typing import Optional
 
 from . import _abi
-from ._abi import (SS_OK, SplatSortError, check, make_options, ss_frame, ss_frame_out)
+from ._abi import (SS_ALGO_AUTO, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
+                   make_options, ss_batch_out, ss_frame, ss_frame_out)
 
-__all__ = ["FrameSorter", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
-           "records_to_device", "SplatSortError", "geometry"]
+__all__ = ["FrameSorter", "BatchSorter", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
+           "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
+           "SS_ALGO_DIRECT"]
 
 
 def _torch():
@@ -114,7 +116,7 @@ class FrameSorter:
 
     def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
                  radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
-                 device="cuda", unsorted: bool = False, workgroup_size: int = 0):
+                 device="cuda", unsorted: bool = False, workgroup_size: int = 0, algorithm: int = 0):
         torch = _torch()
         self.width, self.height = width, height
         self.num_gaussians = num_gaussians
@@ -123,7 +125,7 @@ class FrameSorter:
         self.num_tiles = self.tiles_x * self.tiles_y
         self.options = make_options(radix_bits, items_per_thread,
                                     flags=_abi.SS_FLAG_UNSORTED if unsorted else 0,
-                                    workgroup_size=workgroup_size)
+                                    workgroup_size=workgroup_size, algorithm=algorithm)
         probe = ss_frame()
         probe.width, probe.height, probe.tile_px, probe.num_gaussians = width, height, 16, num_gaussians
         probe.gaussians = 16 if num_gaussians else None   # only shape matters here
@@ -164,6 +166,66 @@ class FrameSorter:
                                 _stream_handle(stream), self.options)
         check(st, "ss_sort_frame")
         return self.out
+
+
+class BatchSorter:
+    """Pre-allocated buffers for ``ss_sort_batch`` over frames of fixed shapes
+    ``[(width, height, num_gaussians), ...]`` (one segmented sort)."""
+
+    def __init__(self, shapes, pair_capacity: int, radix_bits: int = 0, items_per_thread: int = 0,
+                 workgroup_size: int = 0, device="cuda"):
+        import numpy as np
+        torch = _torch()
+        self.shapes = [tuple(int(x) for x in s) for s in shapes]
+        self.capacity = int(pair_capacity)
+        self.options = make_options(radix_bits, items_per_thread, workgroup_size=workgroup_size)
+        tiles = [geometry(w, h)[0] * geometry(w, h)[1] for (w, h, _) in self.shapes]
+        self.tile_base = np.concatenate([[0], np.cumsum(tiles)[:-1]]).astype(np.int64)
+        self.num_tiles = int(sum(tiles))
+        probe = []
+        for (w, h, n) in self.shapes:
+            f = ss_frame()
+            f.width, f.height, f.tile_px, f.num_gaussians = w, h, 16, n
+            f.gaussians = 16 if n else None
+            probe.append(f)
+        st, ws = _abi.ss_batch_workspace_bytes(probe, self.capacity, self.options)
+        check(st, "ss_batch_workspace_bytes")
+        self.workspace_bytes = ws
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        cap = max(self.capacity, 1)
+        nf = len(self.shapes)
+        self.keys = torch.empty(cap, dtype=torch.int64, device=device)
+        self.values = torch.empty(cap, dtype=torch.int32, device=device)
+        self.tile_ranges = torch.empty((self.num_tiles, 2), dtype=torch.int32, device=device)
+        self.frame_pairs = torch.zeros(nf, dtype=torch.int32, device=device)
+        self.frame_pair_base = torch.zeros(nf, dtype=torch.int32, device=device)
+        self.num_pairs = torch.zeros(1, dtype=torch.int32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        o = ss_batch_out()
+        o.pair_capacity = self.capacity
+        o.keys, o.values = self.keys.data_ptr(), self.values.data_ptr()
+        o.tile_ranges = self.tile_ranges.data_ptr()
+        o.frame_pairs, o.frame_pair_base = self.frame_pairs.data_ptr(), self.frame_pair_base.data_ptr()
+        o.num_pairs, o.status = self.num_pairs.data_ptr(), self.status.data_ptr()
+        self._cout = o
+
+    def __call__(self, records_list, stream=None, timer: Optional[Timer] = None):
+        if len(records_list) != len(self.shapes):
+            raise ValueError("one records tensor per frame")
+        frames = []
+        for rec, (w, h, n) in zip(records_list, self.shapes):
+            if int(rec.shape[0]) != n:
+                raise ValueError("records do not match the frame shape")
+            frames.append(_frame(rec, w, h))
+        self.options.timer = timer.handle if timer is not None else None
+        st = _abi.ss_sort_batch(frames, self._cout, self.workspace.data_ptr(), self.workspace_bytes,
+                                _stream_handle(stream), self.options)
+        check(st, "ss_sort_batch")
+        return self
+
+    def result(self):
+        """Synchronise and return (status, total pairs)."""
+        return int(self.status.item()), int(self.num_pairs.item()) & 0xFFFFFFFF
 
 
 def count_pairs(records, width: int, height: int, stream=None):

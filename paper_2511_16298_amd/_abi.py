@@ -30,6 +30,13 @@ SS_KERNEL_RANGES = 3
 SS_KERNEL_COPY = 4
 SS_KERNEL_HIST = 5
 SS_KERNEL_DIGIT_BASES = 6
+SS_KERNEL_DEPTH_PASS = 7
+SS_KERNEL_EXPAND = 8
+
+SS_ALGO_AUTO = 0
+SS_ALGO_DEPTH_FIRST = 1
+SS_ALGO_DIRECT = 2
+SS_MAX_BATCH_FRAMES = 256
 
 SS_FLAG_UNSORTED = 1
 
@@ -55,11 +62,19 @@ class ss_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
                 ("items_per_thread", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("timer", ctypes.c_void_p), ("workgroup_size", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("algorithm", ctypes.c_uint32)]
+
+
+class ss_batch_out(ctypes.Structure):
+    _fields_ = [("pair_capacity", ctypes.c_uint32),
+                ("keys", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("tile_ranges", ctypes.c_void_p), ("frame_pairs", ctypes.c_void_p),
+                ("frame_pair_base", ctypes.c_void_p), ("num_pairs", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
 
 
 def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, flags: int = 0,
-                 workgroup_size: int = 0) -> ss_options:
+                 workgroup_size: int = 0, algorithm: int = 0) -> ss_options:
     o = ss_options()
     o.struct_size = ctypes.sizeof(ss_options)
     o.radix_bits = radix_bits
@@ -67,7 +82,7 @@ def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, fla
     o.flags = flags
     o.timer = timer
     o.workgroup_size = workgroup_size
-    o.reserved = 0
+    o.algorithm = algorithm
     return o
 
 
@@ -89,6 +104,10 @@ _SIGNATURES = {
                             ctypes.POINTER(_SZ)], ctypes.c_int),
     "ss_count_pairs": ([ctypes.POINTER(ss_frame), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "ss_sort_frame": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_frame_out), _P, _SZ, _P,
+                       ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_batch_workspace_bytes": ([ctypes.POINTER(ss_frame), _U32, _U32, ctypes.POINTER(ss_options),
+                                  ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ss_sort_batch": ([ctypes.POINTER(ss_frame), _U32, ctypes.POINTER(ss_batch_out), _P, _SZ, _P,
                        ctypes.POINTER(ss_options)], ctypes.c_int),
     "ss_sort_pairs_workspace_bytes": ([_U32, _U32, ctypes.POINTER(ss_options), ctypes.POINTER(_SZ)],
                                       ctypes.c_int),
@@ -164,6 +183,27 @@ def ss_count_pairs(frame: ss_frame, d_tiles_touched, d_offsets, d_num_pairs, d_s
 
 def ss_sort_frame(frame: ss_frame, out: ss_frame_out, workspace, workspace_bytes, stream, options=None):
     return lib().ss_sort_frame(ctypes.byref(frame), ctypes.byref(out), workspace, workspace_bytes, stream,
+                               ctypes.byref(options) if options is not None else None)
+
+
+def _frames_array(frames):
+    arr = (ss_frame * len(frames))()
+    for i, f in enumerate(frames):
+        arr[i] = f
+    return arr
+
+
+def ss_batch_workspace_bytes(frames, pair_capacity: int, options=None):
+    arr = _frames_array(frames)
+    b = _SZ()
+    st = lib().ss_batch_workspace_bytes(arr, len(frames), pair_capacity,
+                                        ctypes.byref(options) if options is not None else None, ctypes.byref(b))
+    return st, b.value
+
+
+def ss_sort_batch(frames, out: ss_batch_out, workspace, workspace_bytes, stream, options=None):
+    arr = _frames_array(frames)
+    return lib().ss_sort_batch(arr, len(frames), ctypes.byref(out), workspace, workspace_bytes, stream,
                                ctypes.byref(options) if options is not None else None)
 
 

@@ -1,5 +1,5 @@
 // Host side of the C ABI declared in splatsort.h: argument validation,
-// workspace layout and the launch sequence of the hot path.
+// workspace layout and the launch sequences of the hot path.
 #include <stdint.h>
 
 #include <new>
@@ -17,18 +17,19 @@ constexpr uint32_t kDefaultThreads = 512;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 // Counter words at the start of the workspace.
-constexpr uint32_t kCounterTicket = 0;   // count / duplicate workgroup tickets
+constexpr uint32_t kCounterTicket = 0;   // direct path: count / duplicate tickets
+constexpr uint32_t kCounterExpand = 1;   // depth-first: expand tickets
 constexpr uint32_t kCounterPass = 16;    // + p: tickets of sort pass p (p < 48)
-
-bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 struct Options {
   uint32_t radix_bits = kDefaultRadix;
   uint32_t items = kDefaultItems;
   uint32_t threads = kDefaultThreads;
   uint32_t flags = 0;
+  uint32_t algorithm = SS_ALGO_AUTO;
   ss_timer* timer = nullptr;
 };
 
@@ -37,7 +38,9 @@ ss_status parse_options(const ss_options* o, Options* out) {
   if (o == nullptr) return SS_OK;
   if (o->struct_size < sizeof(ss_options)) return SS_ERR_INVALID_ARGUMENT;
   if ((o->flags & ~SS_FLAG_UNSORTED) != 0) return SS_ERR_UNSUPPORTED;
+  if (o->algorithm > SS_ALGO_DIRECT) return SS_ERR_UNSUPPORTED;
   out->flags = o->flags;
+  out->algorithm = o->algorithm;
   if (o->radix_bits != 0) out->radix_bits = o->radix_bits;
   if (o->items_per_thread != 0) out->items = o->items_per_thread;
   // default workgroup: 512 where that configuration exists, else 256
@@ -49,6 +52,12 @@ ss_status parse_options(const ss_options* o, Options* out) {
     return SS_ERR_UNSUPPORTED;
   out->timer = o->timer;
   return SS_OK;
+}
+
+uint32_t ceil_log2(uint64_t t) {
+  uint32_t b = 0;
+  while ((uint64_t{1} << b) < t) ++b;
+  return b;
 }
 
 struct Geometry {
@@ -67,13 +76,20 @@ ss_status frame_geometry(const ss_frame* f, Geometry* g) {
   g->tiles_y = (f->height + 15) / 16;
   const uint64_t t = static_cast<uint64_t>(g->tiles_x) * g->tiles_y;  // < 2^32 by the size limit
   g->num_tiles = static_cast<uint32_t>(t);
-  const uint32_t tile_bits = t <= 1 ? 0u : 32u - static_cast<uint32_t>(__builtin_clz(g->num_tiles - 1));
-  g->key_bits = 32 + tile_bits;
+  g->key_bits = 32 + ceil_log2(t);
   return SS_OK;
 }
 
-// Workspace: [counters | scan look-back | histograms | pass look-back | scalars]
-// is zeroed at the start of every call; the alternate pair buffers follow.
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// Direct path: count/scan/duplicate in index order, then P passes over the
+// full key.  Workspace: [counters | scalars | bases | scan look-back |
+// histograms | pass look-back] zeroed per call, then the alternate buffers.
+// ---------------------------------------------------------------------------
 struct Layout {
   uint32_t npasses = 0, bins = 0, count_blocks = 0, pass_blocks = 0, tile = 0;
   size_t counters = 0, scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, bases = 0, clear_end = 0;
@@ -101,9 +117,77 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
   return L;
 }
 
-template <typename T>
-T* at(void* ws, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+// ---------------------------------------------------------------------------
+// Depth-first path (one frame or a batch).  Zeroed part: counters, scalars,
+// bad flag, totals, count-only scan look-back, expand look-back, histograms
+// and look-back words of the depth and tile passes; then the frame table,
+// digit bases, rectangles, the Gaussian sort buffers and the alternate pair
+// buffers.
+// ---------------------------------------------------------------------------
+struct PassCfg {
+  uint32_t items = 16, threads = 512;
+  uint32_t tile() const { return items * threads; }
+};
+
+// Depth-sort passes run over N Gaussians (8-byte items): smaller tiles keep
+// the chip busy when N is small.
+PassCfg depth_cfg(uint32_t n) {
+  if (n < (1u << 21)) return PassCfg{8, 256};
+  return PassCfg{16, 512};
+}
+
+struct DfLayout {
+  uint32_t n = 0, n_frames = 0, capacity = 0, total_tiles = 0, tile_bits = 0, tpasses = 0, tbins = 256;
+  PassCfg dcfg, tcfg;
+  uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
+  size_t block_total = 0, block_frame = 0;
+  size_t counters = 0, scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
+         lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_d = 0, bases_t = 0, rect = 0, key = 0, val = 0,
+         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, total = 0;
+};
+
+DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64_t total_tiles, const Options& o) {
+  DfLayout L;
+  L.n = n;
+  L.n_frames = n_frames;
+  L.capacity = capacity;
+  L.total_tiles = static_cast<uint32_t>(total_tiles);
+  L.tile_bits = ceil_log2(total_tiles);
+  L.tpasses = (L.tile_bits + o.radix_bits - 1) / o.radix_bits;
+  L.tbins = 1u << o.radix_bits;
+  L.dcfg = depth_cfg(n);
+  L.tcfg = PassCfg{o.items, o.threads};
+  L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
+  L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile();
+  L.eblocks = (n + kExpandTile - 1) / kExpandTile;
+  L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
+  size_t off = 0;
+  L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
+  L.scalars = off;   off = align_up(off + 4 * sizeof(uint32_t));
+  L.bad = off;       off = align_up(off + sizeof(uint32_t));
+  L.totals = off;    off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
+  L.ck_blocks = (n + kCountKeysTile - 1) / kCountKeysTile;
+  L.block_total = off; off = align_up(off + static_cast<size_t>(L.ck_blocks) * sizeof(uint64_t));
+  L.block_frame = off; off = align_up(off + static_cast<size_t>(L.ck_blocks) * sizeof(uint32_t));
+  L.scan_lb = off;   off = align_up(off + static_cast<size_t>(L.count_blocks) * sizeof(uint64_t));
+  L.expand_lb = off; off = align_up(off + static_cast<size_t>(L.eblocks) * sizeof(uint64_t));
+  L.hist_d = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * 4 * 256 * sizeof(uint32_t));
+  L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * L.tpasses * L.tbins * sizeof(uint32_t));
+  L.lb_d = off;      off = align_up(off + static_cast<size_t>(4) * L.dblocks * 256 * sizeof(uint32_t));
+  L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses) * L.tblocks * L.tbins * sizeof(uint32_t));
+  L.clear_end = off;
+  L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
+  L.bases_d = off;   off = align_up(off + 4 * 256 * sizeof(uint32_t));
+  L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
+  L.rect = off;      off = align_up(off + static_cast<size_t>(n) * sizeof(uint64_t));
+  L.key = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
+  L.val = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
+  L.key_alt = off;   off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
+  L.val_alt = off;   off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
+  L.alt_keys = off;  off = align_up(off + static_cast<size_t>(capacity) * sizeof(uint64_t));
+  L.alt_vals = off;  off = align_up(off + static_cast<size_t>(capacity) * sizeof(uint32_t));
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -119,7 +203,7 @@ struct ss_timer {
 namespace ss {
 namespace {
 
-// Runs one launch, bracketed by timer events when a timer is attached.
+// Runs launches, bracketed by timer events when a timer is attached.
 class Launcher {
  public:
   Launcher(hipStream_t s, ss_timer* t) : s_(s), t_(t) {}
@@ -155,35 +239,279 @@ class Launcher {
     if (st_ != SS_OK) return st_;     \
   } while (0)
 
-// Sort passes p = 0 .. P-1 over key bits [p * RB, (p + 1) * RB).  Pass p
-// reads src[p] and writes dst[p]; the caller arranges the buffers so the last
-// pass lands in the output.
-ss_status run_passes(Launcher& L, const Layout& lay, const Options& o, void* ws,
-                     const uint64_t* const* ksrc, const uint32_t* const* vsrc, uint64_t* const* kdst,
-                     uint32_t* const* vdst, const uint32_t* d_num_pairs, uint32_t n_fixed,
-                     uint32_t* d_status, hipStream_t s) {
+// A chain of P digit passes.  Pass p reads src[p], writes dst[p], sorts on
+// bits [shift0 + RB p, shift0 + RB (p + 1)).
+struct PassChain {
+  uint32_t npasses;
+  uint32_t key_bytes;
+  uint32_t shift0;
+  uint32_t radix_bits;
+  PassCfg cfg;
+  uint32_t nblocks;
+  const void* const* ksrc;
+  const uint32_t* const* vsrc;
+  void* const* kdst;
+  uint32_t* const* vdst;
+  const uint32_t* num_pairs;  // device M or NULL (then n_fixed)
+  uint32_t n_fixed;
+  uint32_t* status;
+  const uint32_t* bases;      // [npasses][bins]
+  uint32_t* tickets;          // [npasses]
+  uint32_t* lookback;         // [npasses][nblocks][bins]
+};
+
+ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
+  if (c.npasses == 0) return SS_OK;
+  const uint32_t bins = 1u << c.radix_bits;
+  return L.run_group(kind, c.npasses, [&]() -> ss_status {
+    for (uint32_t p = 0; p < c.npasses; ++p) {
+      PassArgs a{};
+      a.kin = c.ksrc[p];
+      a.vin = c.vsrc[p];
+      a.kout = c.kdst[p];
+      a.vout = c.vdst[p];
+      a.num_pairs = c.num_pairs;
+      a.n_fixed = c.n_fixed;
+      a.status = c.status;
+      a.shift = c.shift0 + p * c.radix_bits;
+      a.bases = c.bases + static_cast<size_t>(p) * bins;
+      a.ticket = c.tickets + p;
+      a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
+      if (launch_pass(a, static_cast<int>(c.key_bytes), static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
+                      static_cast<int>(c.cfg.threads), c.nblocks, s) != hipSuccess)
+        return SS_ERR_HIP;
+    }
+    return SS_OK;
+  });
+}
+
+// ----------------------------- direct path ---------------------------------
+ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, const ss_frame_out* out,
+                     const Options& o, void* ws, hipStream_t s) {
+  const uint32_t cap = out->pair_capacity;
+  const Layout lay = make_layout(frame->num_gaussians, cap, g.key_bits, o);
+  uint32_t* scal = at<uint32_t>(ws, lay.scalars);
+  uint32_t* d_status = out->status ? out->status : scal + 0;
+  uint32_t* d_num_pairs = out->num_pairs ? out->num_pairs : scal + 1;
+  const bool unsorted = (o.flags & SS_FLAG_UNSORTED) != 0;
+  const uint32_t P = unsorted ? 0 : lay.npasses;
+  // dup writes buf[0]; pass p reads buf[p % 2] and writes buf[(p + 1) % 2];
+  // the data ends in buf[P % 2], which must be the caller's output.
+  uint64_t* bk[2];
+  uint32_t* bv[2];
+  bk[P % 2] = out->keys;
+  bv[P % 2] = out->values;
+  bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
+  bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
+
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, s); }));
+  CountDupArgs a{};
+  a.gaussians = frame->gaussians;
+  a.n = frame->num_gaussians;
+  a.tiles_x = g.tiles_x;
+  a.tiles_y = g.tiles_y;
+  a.capacity = cap;
+  a.npasses = lay.npasses;
+  a.tiles_touched = out->tiles_touched;
+  a.offsets = out->offsets;
+  a.keys = bk[0];
+  a.values = bv[0];
+  a.ticket = at<uint32_t>(ws, lay.counters) + kCounterTicket;
+  a.lookback = at<uint64_t>(ws, lay.scan_lb);
+  a.hist = at<uint32_t>(ws, lay.hist);
+  a.num_pairs = d_num_pairs;
+  a.status = d_status;
+  a.nblocks = lay.count_blocks;
+  SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
+  if (unsorted) return SS_OK;
+  uint32_t* bases = at<uint32_t>(ws, lay.bases);
+  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
+    return launch_digit_bases(a.hist, lay.npasses, bases, static_cast<int>(o.radix_bits), s);
+  }));
+  std::vector<const void*> ks(P);
+  std::vector<const uint32_t*> vs(P);
+  std::vector<void*> kd(P);
+  std::vector<uint32_t*> vd(P);
+  for (uint32_t p = 0; p < P; ++p) {
+    ks[p] = bk[p % 2];
+    vs[p] = bv[p % 2];
+    kd[p] = bk[(p + 1) % 2];
+    vd[p] = bv[(p + 1) % 2];
+  }
+  PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
+              kd.data(), vd.data(), d_num_pairs, 0, d_status, bases,
+              at<uint32_t>(ws, lay.counters) + kCounterPass, at<uint32_t>(ws, lay.pass_lb)};
+  SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
+  return L.run(SS_KERNEL_RANGES, [&] {
+    return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
+  });
+}
+
+// --------------------------- depth-first path ------------------------------
+struct DfIO {
+  const FrameInfo* host_table;  // [n_frames], gaussians pointers are device pointers
+  const ss_frame* frames;       // for the optional index-order offsets (one frame)
+  uint64_t* keys;
+  uint32_t* values;
+  uint32_t* ranges;
+  uint32_t* tiles_touched;      // single frame only, may be NULL
+  uint32_t* offsets;            // single frame only, may be NULL
+  uint32_t* num_pairs;          // may be NULL
+  uint32_t* status;             // may be NULL
+  uint32_t* frame_pairs;        // batch only, may be NULL
+  uint32_t* frame_pair_base;    // batch only, may be NULL
+};
+
+ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, const DfIO& io, void* ws,
+                          hipStream_t s) {
+  uint32_t* scal = at<uint32_t>(ws, lay.scalars);
+  uint32_t* d_status = io.status ? io.status : scal + 0;
+  uint32_t* d_num_pairs = io.num_pairs ? io.num_pairs : scal + 1;
   uint32_t* counters = at<uint32_t>(ws, lay.counters);
-  uint32_t* plb = at<uint32_t>(ws, lay.pass_lb);
-  return L.run_group(SS_KERNEL_SORT_PASS, lay.npasses, [&]() -> ss_status {
-  for (uint32_t p = 0; p < lay.npasses; ++p) {
-    PassArgs a{};
-    a.kin = ksrc[p];
-    a.vin = vsrc[p];
-    a.kout = kdst[p];
-    a.vout = vdst[p];
-    a.num_pairs = d_num_pairs;
-    a.n_fixed = n_fixed;
-    a.status = d_status;
-    a.shift = p * o.radix_bits;
-    a.bases = at<uint32_t>(ws, lay.bases) + static_cast<size_t>(p) * lay.bins;
-    a.ticket = counters + kCounterPass + p;
-    a.lookback = plb + static_cast<size_t>(p) * lay.pass_blocks * lay.bins;
-    if (launch_pass(a, 8, static_cast<int>(o.radix_bits), static_cast<int>(o.items), static_cast<int>(o.threads),
-                    lay.pass_blocks, s) != hipSuccess)
-      return SS_ERR_HIP;
+  FrameInfo* table = at<FrameInfo>(ws, lay.table);
+
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, s); }));
+  for (uint32_t first = 0; first < lay.n_frames; first += kArgFrames) {
+    TableChunk c{};
+    c.first = first;
+    c.count = lay.n_frames - first < kArgFrames ? lay.n_frames - first : kArgFrames;
+    for (uint32_t i = 0; i < c.count; ++i) c.f[i] = io.host_table[first + i];
+    SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_put_table(c, table, s); }));
+  }
+  if (io.offsets != nullptr) {
+    // the index-order scan exists only for this optional output
+    CountDupArgs a{};
+    a.gaussians = io.frames->gaussians;
+    a.n = io.frames->num_gaussians;
+    a.tiles_x = io.host_table[0].tiles_x;
+    a.tiles_y = io.host_table[0].tiles_y;
+    a.offsets = io.offsets;
+    a.ticket = counters + kCounterTicket;
+    a.lookback = at<uint64_t>(ws, lay.scan_lb);
+    a.num_pairs = scal + 2;
+    a.status = scal + 3;
+    a.nblocks = lay.count_blocks;
+    SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, 8, false, s); }));
+  }
+
+  uint32_t* key = at<uint32_t>(ws, lay.key);
+  uint32_t* val = at<uint32_t>(ws, lay.val);
+  uint32_t* key_alt = at<uint32_t>(ws, lay.key_alt);
+  uint32_t* val_alt = at<uint32_t>(ws, lay.val_alt);
+  CountKeysArgs ck{};
+  ck.table = table;
+  ck.n_frames = lay.n_frames;
+  ck.n = lay.n;
+  ck.rect = at<uint64_t>(ws, lay.rect);
+  ck.key = key;
+  ck.val = val;
+  ck.tiles_touched = io.tiles_touched;
+  ck.hist = at<uint32_t>(ws, lay.hist_d);
+  ck.totals = at<unsigned long long>(ws, lay.totals);
+  ck.block_total = at<unsigned long long>(ws, lay.block_total);
+  ck.block_frame = at<uint32_t>(ws, lay.block_frame);
+  ck.bad = at<uint32_t>(ws, lay.bad);
+  SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
+  DepthBasesArgs db{ck.hist, at<uint32_t>(ws, lay.bases_d), ck.totals, ck.block_total, ck.block_frame,
+                    lay.ck_blocks, ck.bad, lay.n_frames, lay.capacity, d_num_pairs, d_status,
+                    io.frame_pairs, io.frame_pair_base};
+  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] { return launch_depth_bases(db, s); }));
+
+  // stable sort of the N Gaussians by depth: key -> alt -> key -> alt -> key
+  {
+    const void* ks[4] = {key, key_alt, key, key_alt};
+    const uint32_t* vs[4] = {val, val_alt, val, val_alt};
+    void* kd[4] = {key_alt, key, key_alt, key};
+    uint32_t* vd[4] = {val_alt, val, val_alt, val};
+    PassChain c{4, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
+                at<uint32_t>(ws, lay.bases_d), counters + kCounterPass, at<uint32_t>(ws, lay.lb_d)};
+    SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
+  }
+
+  // expand into pairs, then sort them by tile id alone
+  const uint32_t P = lay.tpasses;
+  uint64_t* bk[2];
+  uint32_t* bv[2];
+  bk[P % 2] = io.keys;
+  bv[P % 2] = io.values;
+  bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
+  bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
+  ExpandArgs e{};
+  e.table = table;
+  e.n_frames = lay.n_frames;
+  e.n = lay.n;
+  e.key = key;
+  e.val = val;
+  e.rect = ck.rect;
+  e.capacity = lay.capacity;
+  e.keys = bk[0];
+  e.values = bv[0];
+  e.npasses = P;
+  e.radix_bits = o.radix_bits;
+  e.hist = at<uint32_t>(ws, lay.hist_t);
+  e.ticket = counters + kCounterExpand;
+  e.lookback = at<uint64_t>(ws, lay.expand_lb);
+  e.status = d_status;
+  e.nblocks = lay.eblocks;
+  SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
+  if (P > 0) {
+    uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
+    SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
+      return launch_digit_bases(e.hist, P, bases_t, static_cast<int>(o.radix_bits), s);
+    }));
+    std::vector<const void*> ks(P);
+    std::vector<const uint32_t*> vs(P);
+    std::vector<void*> kd(P);
+    std::vector<uint32_t*> vd(P);
+    for (uint32_t p = 0; p < P; ++p) {
+      ks[p] = bk[p % 2];
+      vs[p] = bv[p % 2];
+      kd[p] = bk[(p + 1) % 2];
+      vd[p] = bv[(p + 1) % 2];
+    }
+    PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
+                d_status, bases_t, counters + kCounterPass + 4, at<uint32_t>(ws, lay.lb_t)};
+    SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
+  }
+  return L.run(SS_KERNEL_RANGES, [&] {
+    return launch_ranges(io.keys, d_num_pairs, d_status, lay.capacity, lay.total_tiles, io.ranges, s);
+  });
+}
+
+bool use_direct(const Options& o) {
+  return o.algorithm == SS_ALGO_DIRECT || (o.flags & SS_FLAG_UNSORTED) != 0;
+}
+
+FrameInfo frame_info(const ss_frame* f, const Geometry& g, uint32_t gauss_base, uint32_t tile_base) {
+  FrameInfo fi{};
+  fi.gauss_base = gauss_base;
+  fi.n = f->num_gaussians;
+  fi.tiles_x = g.tiles_x;
+  fi.tiles_y = g.tiles_y;
+  fi.tile_base = tile_base;
+  fi.gaussians = f->gaussians;
+  return fi;
+}
+
+struct BatchShape {
+  std::vector<FrameInfo> table;
+  uint64_t n = 0, tiles = 0;
+};
+
+ss_status batch_shape(const ss_frame* frames, uint32_t n_frames, BatchShape* b) {
+  if (frames == nullptr || n_frames == 0 || n_frames > kMaxFrames) return SS_ERR_INVALID_ARGUMENT;
+  b->table.resize(n_frames);
+  b->n = 0;
+  b->tiles = 0;
+  for (uint32_t f = 0; f < n_frames; ++f) {
+    Geometry g;
+    SS_TRY(frame_geometry(&frames[f], &g));
+    b->table[f] = frame_info(&frames[f], g, static_cast<uint32_t>(b->n), static_cast<uint32_t>(b->tiles));
+    b->n += frames[f].num_gaussians;
+    b->tiles += g.num_tiles;
+    if (b->n > 0x7FFFFFFFull || b->tiles > 0xFFFFFFFFull) return SS_ERR_INVALID_ARGUMENT;
   }
   return SS_OK;
-  });
 }
 
 }  // namespace
@@ -229,7 +557,8 @@ ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity, cons
   Options o;
   SS_TRY(parse_options(options, &o));
   if (pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
-  *bytes = make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total;
+  *bytes = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
+                         : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o).total;
   return SS_OK;
 }
 
@@ -245,16 +574,12 @@ ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint3
     return SS_ERR_WORKSPACE;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, nullptr);
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] {
-    return launch_clear(workspace, lay.clear_end, d_status, s);
-  }));
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, d_status, s); }));
   CountDupArgs a{};
   a.gaussians = frame->gaussians;
   a.n = frame->num_gaussians;
   a.tiles_x = g.tiles_x;
   a.tiles_y = g.tiles_y;
-  a.capacity = 0;
-  a.npasses = 0;
   a.tiles_touched = d_tiles_touched;
   a.offsets = d_offsets;
   a.ticket = at<uint32_t>(workspace, lay.counters) + kCounterTicket;
@@ -278,73 +603,51 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   if (cap > 0 && (out->keys == nullptr || out->values == nullptr)) return SS_ERR_INVALID_ARGUMENT;
   if (!aligned(out->keys, 8) || !aligned(out->values, 4) || !aligned(out->tile_ranges, 4))
     return SS_ERR_INVALID_ARGUMENT;
-  const Layout lay = make_layout(frame->num_gaussians, cap, g.key_bits, o);
-  if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total)
-    return SS_ERR_WORKSPACE;
-
+  size_t need = 0;
+  SS_TRY(ss_workspace_bytes(frame, cap, options, &need));
+  if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < need) return SS_ERR_WORKSPACE;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);
-  uint32_t* scal = at<uint32_t>(workspace, lay.scalars);
-  uint32_t* d_status = out->status ? out->status : scal + 0;
-  uint32_t* d_num_pairs = out->num_pairs ? out->num_pairs : scal + 1;
+  if (use_direct(o)) return run_direct(L, frame, g, out, o, workspace, s);
+  const FrameInfo fi = frame_info(frame, g, 0, 0);
+  const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o);
+  DfIO io{&fi, frame, out->keys, out->values, out->tile_ranges, out->tiles_touched, out->offsets,
+          out->num_pairs, out->status, nullptr, nullptr};
+  return run_depth_first(L, lay, o, io, workspace, s);
+}
 
-  // dup writes buf[0]; pass p reads buf[p % 2] and writes buf[(p + 1) % 2];
-  // the data ends in buf[P % 2], which must be the caller's output.
-  uint64_t* alt_k = at<uint64_t>(workspace, lay.alt_keys);
-  uint32_t* alt_v = at<uint32_t>(workspace, lay.alt_vals);
-  const bool unsorted = (o.flags & SS_FLAG_UNSORTED) != 0;
-  const uint32_t P = unsorted ? 0 : lay.npasses;
-  uint64_t* bk[2];
-  uint32_t* bv[2];
-  bk[P % 2] = out->keys;
-  bv[P % 2] = out->values;
-  bk[(P + 1) % 2] = alt_k;
-  bv[(P + 1) % 2] = alt_v;
+ss_status ss_batch_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uint32_t pair_capacity,
+                                   const ss_options* options, size_t* bytes) {
+  if (bytes == nullptr || pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
+  BatchShape b;
+  SS_TRY(batch_shape(frames, n_frames, &b));
+  Options o;
+  SS_TRY(parse_options(options, &o));
+  if (use_direct(o)) return SS_ERR_UNSUPPORTED;
+  *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o).total;
+  return SS_OK;
+}
 
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] {
-    return launch_clear(workspace, lay.clear_end, d_status, s);
-  }));
-
-  CountDupArgs a{};
-  a.gaussians = frame->gaussians;
-  a.n = frame->num_gaussians;
-  a.tiles_x = g.tiles_x;
-  a.tiles_y = g.tiles_y;
-  a.capacity = cap;
-  a.npasses = lay.npasses;
-  a.tiles_touched = out->tiles_touched;
-  a.offsets = out->offsets;
-  a.keys = bk[0];
-  a.values = bv[0];
-  a.ticket = at<uint32_t>(workspace, lay.counters) + kCounterTicket;
-  a.lookback = at<uint64_t>(workspace, lay.scan_lb);
-  a.hist = at<uint32_t>(workspace, lay.hist);
-  a.num_pairs = d_num_pairs;
-  a.status = d_status;
-  a.nblocks = lay.count_blocks;
-  SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
-  if (unsorted) return SS_OK;
-  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
-    return launch_digit_bases(a.hist, lay.npasses, at<uint32_t>(workspace, lay.bases),
-                              static_cast<int>(o.radix_bits), s);
-  }));
-
-  std::vector<const uint64_t*> ks(lay.npasses);
-  std::vector<const uint32_t*> vs(lay.npasses);
-  std::vector<uint64_t*> kd(lay.npasses);
-  std::vector<uint32_t*> vd(lay.npasses);
-  for (uint32_t p = 0; p < lay.npasses; ++p) {
-    ks[p] = bk[p % 2];
-    vs[p] = bv[p % 2];
-    kd[p] = bk[(p + 1) % 2];
-    vd[p] = bv[(p + 1) % 2];
-  }
-  SS_TRY(run_passes(L, lay, o, workspace, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                    d_status, s));
-
-  return L.run(SS_KERNEL_RANGES, [&] {
-    return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
-  });
+ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batch_out* out, void* workspace,
+                        size_t workspace_bytes, void* stream, const ss_options* options) {
+  BatchShape b;
+  SS_TRY(batch_shape(frames, n_frames, &b));
+  Options o;
+  SS_TRY(parse_options(options, &o));
+  if (use_direct(o)) return SS_ERR_UNSUPPORTED;
+  if (out == nullptr || out->tile_ranges == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  const uint32_t cap = out->pair_capacity;
+  if (cap > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
+  if (cap > 0 && (out->keys == nullptr || out->values == nullptr)) return SS_ERR_INVALID_ARGUMENT;
+  if (!aligned(out->keys, 8) || !aligned(out->values, 4) || !aligned(out->tile_ranges, 4))
+    return SS_ERR_INVALID_ARGUMENT;
+  const DfLayout lay = make_df_layout(static_cast<uint32_t>(b.n), n_frames, cap, b.tiles, o);
+  if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total) return SS_ERR_WORKSPACE;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Launcher L(s, o.timer);
+  DfIO io{b.table.data(), frames, out->keys, out->values, out->tile_ranges, nullptr, nullptr,
+          out->num_pairs, out->status, out->frame_pairs, out->frame_pair_base};
+  return run_depth_first(L, lay, o, io, workspace, s);
 }
 
 ss_status ss_sort_pairs_workspace_bytes(uint32_t n, uint32_t key_bits, const ss_options* options,
@@ -378,25 +681,28 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, nullptr, s); }));
   HistArgs h{keys_in, n, lay.npasses, at<uint32_t>(workspace, lay.hist)};
   SS_TRY(L.run(SS_KERNEL_HIST, [&] { return launch_hist(h, static_cast<int>(o.radix_bits), s); }));
+  uint32_t* bases = at<uint32_t>(workspace, lay.bases);
   SS_TRY(L.run(SS_KERNEL_HIST, [&] {
-    return launch_digit_bases(h.hist, lay.npasses, at<uint32_t>(workspace, lay.bases),
-                              static_cast<int>(o.radix_bits), s);
+    return launch_digit_bases(h.hist, lay.npasses, bases, static_cast<int>(o.radix_bits), s);
   }));
   uint64_t* alt_k = at<uint64_t>(workspace, lay.alt_keys);
   uint32_t* alt_v = at<uint32_t>(workspace, lay.alt_vals);
   const uint32_t P = lay.npasses;
-  std::vector<const uint64_t*> ks(P);
+  std::vector<const void*> ks(P);
   std::vector<const uint32_t*> vs(P);
-  std::vector<uint64_t*> kd(P);
+  std::vector<void*> kd(P);
   std::vector<uint32_t*> vd(P);
   for (uint32_t p = 0; p < P; ++p) {
     const bool to_out = ((P - 1 - p) % 2) == 0;
-    kd[p] = to_out ? keys_out : alt_k;
+    kd[p] = to_out ? static_cast<void*>(keys_out) : static_cast<void*>(alt_k);
     vd[p] = to_out ? values_out : alt_v;
-    ks[p] = p == 0 ? keys_in : kd[p - 1];
+    ks[p] = p == 0 ? static_cast<const void*>(keys_in) : kd[p - 1];
     vs[p] = p == 0 ? values_in : vd[p - 1];
   }
-  return run_passes(L, lay, o, workspace, ks.data(), vs.data(), kd.data(), vd.data(), nullptr, n, nullptr, s);
+  PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
+              kd.data(), vd.data(), nullptr, n, nullptr, bases,
+              at<uint32_t>(workspace, lay.counters) + kCounterPass, at<uint32_t>(workspace, lay.pass_lb)};
+  return run_chain(L, SS_KERNEL_SORT_PASS, c, s);
 }
 
 ss_status ss_copy_bytes(void* d_dst, const void* d_src, size_t bytes, void* stream, const ss_options* options) {

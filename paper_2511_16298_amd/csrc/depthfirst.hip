@@ -1,0 +1,415 @@
+// Depth-first form of the tile-and-depth sort, for one frame or a batch of
+// frames.  The result is identical to sorting all (tile, Gaussian) pairs by
+// (tile, depth, index) (paper: Background, "Duplication with Tiles" and
+// "Sorting"), reached with fewer passes over the pairs:
+//   1. count:  per Gaussian, its tile rectangle and pair count; its depth key
+//              (culled Gaussians get 0xFFFFFFFF and sort last);
+//   2. sort the N Gaussians stably by depth (four 8-bit passes over N);
+//   3. expand: walk the Gaussians in depth order and write their pairs, tile
+//              by tile in row-major order, with global tile ids;
+//   4. sort the pairs stably by tile id alone (ceil(log2 T) bits, two 8-bit
+//              passes for 8,160 tiles; none for one tile).
+// After step 3 the pairs of any one tile already appear in (depth, index)
+// order, because a Gaussian contributes at most one pair per tile; a stable
+// sort by tile keeps that order.  A batch renumbers frame f's tiles
+// tile_base[f] + t and keeps frame-local Gaussian indices as values.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ss {
+namespace {
+
+constexpr uint32_t kCountKeysThreads = 256;
+constexpr uint32_t kCountKeysItems = kCountKeysTile / kCountKeysThreads;
+constexpr uint32_t kExpandThreads = 512;
+constexpr uint32_t kExpandPer = kExpandTile / kExpandThreads;  // Gaussians per thread
+constexpr uint32_t kChunk = 4096;                             // pairs per expansion round
+constexpr uint32_t kChunkPer = kChunk / kExpandThreads;
+constexpr uint64_t kSat = 1ull << 40;
+
+__device__ __forceinline__ uint32_t clamp_tile(int64_t v, uint32_t n) {
+  return v < 0 ? 0u : (v > static_cast<int64_t>(n) ? n : static_cast<uint32_t>(v));
+}
+
+// Largest f with table[f].gauss_base <= g (frames are in order).
+__device__ __forceinline__ uint32_t frame_of(const FrameInfo* tab, uint32_t n_frames, uint32_t g) {
+  uint32_t lo = 0, hi = n_frames;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tab[mid].gauss_base <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_put_table(TableChunk c, FrameInfo* __restrict__ table) {
+  if (threadIdx.x < c.count) table[c.first + threadIdx.x] = c.f[threadIdx.x];
+}
+
+// Step 1.  2048 Gaussians per workgroup, loaded striped (coalesced 16-byte
+// loads).  No scan here: only totals (all pairs and per frame) by atomics,
+// and the four depth-digit histograms of the Gaussian sort.
+__global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs a) {
+  __shared__ FrameInfo s_tab[kMaxFrames];
+  __shared__ uint32_t s_hist[4 * 256];
+  __shared__ unsigned long long s_fm[kMaxFrames];
+  __shared__ unsigned long long s_tmp[kCountKeysThreads / kWave];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < a.n_frames; i += kCountKeysThreads) {
+    s_tab[i] = a.table[i];
+    s_fm[i] = 0;
+  }
+  for (uint32_t i = tid; i < 4 * 256; i += kCountKeysThreads) s_hist[i] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kCountKeysTile;
+  const uint32_t last = min(base + kCountKeysTile, a.n) - 1;
+  const bool one_frame = a.n_frames == 1 || frame_of(s_tab, a.n_frames, base) == frame_of(s_tab, a.n_frames, last);
+
+  bool bad = false;
+  uint64_t tsum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kCountKeysItems; ++j) {
+    const uint32_t g = base + j * kCountKeysThreads + tid;
+    if (g >= a.n) continue;
+    const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
+    const FrameInfo& F = s_tab[f];
+    const int4 r = reinterpret_cast<const int4*>(F.gaussians)[g - F.gauss_base];
+    const uint32_t radius = static_cast<uint32_t>(r.w);
+    const uint32_t dbits = static_cast<uint32_t>(r.z);
+    uint32_t cnt = 0;
+    uint64_t rect = 0;
+    if (radius != 0) {
+      const int64_t R = static_cast<int64_t>(radius) << 4;
+      const int64_t X = r.x, Y = r.y;
+      const uint32_t x0 = clamp_tile((X - R) >> 8, F.tiles_x);
+      const uint32_t x1 = clamp_tile((X + R + 255) >> 8, F.tiles_x);
+      const uint32_t y0 = clamp_tile((Y - R) >> 8, F.tiles_y);
+      const uint32_t y1 = clamp_tile((Y + R + 255) >> 8, F.tiles_y);
+      if (x1 > x0 && y1 > y0) {
+        cnt = (x1 - x0) * (y1 - y0);
+        rect = static_cast<uint64_t>(x0) | (static_cast<uint64_t>(y0) << 16) |
+               (static_cast<uint64_t>(x1 - x0) << 32) | (static_cast<uint64_t>(y1 - y0) << 48);
+      }
+    }
+    if (cnt != 0 && dbits - 1u >= 0x7F7FFFFFu) bad = true;
+    const uint32_t key = cnt != 0 ? dbits : 0xFFFFFFFFu;
+    a.rect[g] = rect;
+    a.key[g] = key;
+    a.val[g] = g;
+    if (a.tiles_touched) a.tiles_touched[g] = cnt;
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) atomicAdd(&s_hist[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+    if (!one_frame && cnt) atomicAdd(&s_fm[f], static_cast<unsigned long long>(cnt));
+    tsum += cnt;
+  }
+  const bool any_bad = __syncthreads_or(bad);
+  unsigned long long btotal;
+  block_exclusive_scan<unsigned long long, kCountKeysThreads>(tsum, s_tmp, btotal);
+  if (tid == 0) {
+    a.block_total[blockIdx.x] = one_frame ? btotal : 0ull;
+    a.block_frame[blockIdx.x] = frame_of(s_tab, a.n_frames, base);
+    if (any_bad) atomicOr(a.bad, 1u);
+  }
+  if (!one_frame)
+    for (uint32_t f = tid; f < a.n_frames; f += kCountKeysThreads)
+      if (s_fm[f]) atomicAdd(&a.totals[1 + f], s_fm[f]);
+  uint32_t* gh = a.hist + static_cast<size_t>(blockIdx.x % kHistCopies) * 4 * 256;
+  for (uint32_t i = tid; i < 4 * 256; i += kCountKeysThreads) {
+    const uint32_t v = s_hist[i];
+    if (v) atomicAdd(&gh[i], v);
+  }
+}
+
+// Digit bases of the four depth passes (workgroups 0-3); workgroup 4 sums
+// the count workgroups' totals per frame, then writes num_pairs, status and
+// the per-frame pair counts and first pairs.
+__global__ __launch_bounds__(256) void k_depth_bases(DepthBasesArgs a) {
+  __shared__ uint32_t s_tmp[4];
+  __shared__ unsigned long long s_fm[kMaxFrames];
+  __shared__ unsigned long long s_tmp64[4];
+  const uint32_t d = threadIdx.x;
+  if (blockIdx.x < 4) {
+    const uint32_t p = blockIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kHistCopies; ++c) tot += a.hist[(static_cast<size_t>(c) * 4 + p) * 256 + d];
+    uint32_t all;
+    const uint32_t ex = block_exclusive_scan<uint32_t, 256>(tot, s_tmp, all);
+    a.bases[p * 256 + d] = ex;
+    return;
+  }
+  for (uint32_t f = d; f < a.n_frames; f += 256) s_fm[f] = a.totals[1 + f];
+  __syncthreads();
+  for (uint32_t b = d; b < a.count_blocks; b += 256) {
+    const unsigned long long t = a.block_total[b];
+    if (t) atomicAdd(&s_fm[a.block_frame[b]], t);
+  }
+  __syncthreads();
+  const unsigned long long fm = d < a.n_frames ? s_fm[d] : 0ull;
+  unsigned long long m;
+  block_exclusive_scan<unsigned long long, 256>(fm, s_tmp64, m);
+  if (d == 0) {
+    uint32_t st = SS_OK;
+    if (*a.bad) st = SS_ERR_INVALID_INPUT;
+    else if (m > 0xFFFFFFFFull) st = SS_ERR_OVERFLOW;
+    else if (m > a.capacity) st = SS_ERR_CAPACITY;
+    *a.num_pairs = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(m);
+    *a.status = st;
+  }
+  if (a.frame_pairs == nullptr) return;
+  const uint32_t f32 = fm > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fm);
+  uint32_t all;
+  const uint32_t ex = block_exclusive_scan<uint32_t, 256>(f32, s_tmp, all);
+  if (d < a.n_frames) {
+    a.frame_pairs[d] = f32;
+    if (a.frame_pair_base) a.frame_pair_base[d] = ex;
+  }
+}
+
+template <typename T, int THREADS>
+__device__ __forceinline__ T block_reduce_sum(T v, T* s_tmp) {
+  T total;
+  block_exclusive_scan<T, THREADS>(v, s_tmp, total);
+  return total;
+}
+
+// Inclusive max-scan over the workgroup (one value per thread).
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_tmp) {
+  constexpr int kWaves = THREADS / kWave;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= static_cast<uint32_t>(d)) v = max(v, o);
+  }
+  if (lane == kWave - 1) s_tmp[wave] = v;
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w)
+    if (static_cast<uint32_t>(w) < wave) before = max(before, s_tmp[w]);
+  __syncthreads();
+  return max(before, v);
+}
+
+// Step 3.  2048 Gaussians (in depth order) per workgroup of 512 threads.
+// Counts come from the rectangles; a workgroup scan plus a decoupled
+// look-back whose window is the whole workgroup (512 earlier workgroups per
+// round trip) gives the first pair of the workgroup.  The pairs are then
+// written in rounds of 4096: an owner map marks, for every Gaussian starting
+// inside the round, its first slot; a max-scan spreads the owners over the
+// round; thread t writes slots t, t + 512, ... (coalesced).
+__global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
+  __shared__ FrameInfo s_tab[kMaxFrames];
+  __shared__ uint32_t s_off[kExpandTile];
+  __shared__ uint32_t s_org[kExpandTile];   // global tile of (x0, y0)
+  __shared__ uint32_t s_wt[kExpandTile];    // w | tiles_x << 16
+  __shared__ uint32_t s_dep[kExpandTile];
+  __shared__ uint32_t s_loc[kExpandTile];
+  __shared__ uint16_t s_map[kChunk];
+  __shared__ uint32_t s_incl[kExpandThreads];
+  __shared__ uint32_t s_hist[8 * 256];   // tile digits: up to 32 bits at 4 bits per pass
+  __shared__ unsigned long long s_tmp64[kExpandThreads / kWave];
+  __shared__ uint32_t s_tmp[kExpandThreads / kWave];
+  __shared__ uint32_t s_ticket, s_first, s_retry, s_timeout;
+  __shared__ unsigned long long s_prefix;
+
+  if (*a.status != SS_OK) return;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) {
+    s_ticket = atomicAdd(a.ticket, 1u);
+    s_timeout = 0;
+  }
+  for (uint32_t i = tid; i < a.n_frames; i += kExpandThreads) s_tab[i] = a.table[i];
+  const uint32_t rb = a.radix_bits;
+  const uint32_t bins = 1u << rb;
+  for (uint32_t i = tid; i < a.npasses * bins; i += kExpandThreads) s_hist[i] = 0;
+  __syncthreads();
+  const uint32_t ticket = s_ticket;
+  const uint32_t base = ticket * kExpandTile;
+
+  // ---- Gaussians of this workgroup: striped loads, per-Gaussian info ----
+#pragma unroll
+  for (uint32_t j = 0; j < kExpandPer; ++j) {
+    const uint32_t i = j * kExpandThreads + tid;
+    const uint32_t pos = base + i;
+    uint32_t cnt = 0;
+    const uint32_t g = pos < a.n ? a.val[pos] : 0xFFFFFFFFu;
+    if (g < a.n) {  // a sorted index is always < n; the test only keeps reads in bounds
+      const uint64_t r = a.rect[g];
+      const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
+      const uint32_t w = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
+      const uint32_t h = static_cast<uint32_t>(r >> 48);
+      const uint32_t x0 = static_cast<uint32_t>(r) & 0xFFFFu;
+      const uint32_t y0 = static_cast<uint32_t>(r >> 16) & 0xFFFFu;
+      const uint32_t tx = s_tab[f].tiles_x;
+      cnt = w * h;
+      s_org[i] = s_tab[f].tile_base + y0 * tx + x0;
+      s_wt[i] = w | (tx << 16);
+      s_dep[i] = a.key[pos];
+      s_loc[i] = g - s_tab[f].gauss_base;
+    }
+    s_off[i] = cnt;
+  }
+  __syncthreads();
+  // ---- workgroup scan (blocked: thread t owns 4t .. 4t+3) ----
+  uint32_t c[kExpandPer];
+  unsigned long long tsum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kExpandPer; ++k) {
+    c[k] = s_off[kExpandPer * tid + k];
+    tsum += c[k];
+  }
+  unsigned long long btotal;
+  const unsigned long long texcl = block_exclusive_scan<unsigned long long, kExpandThreads>(tsum, s_tmp64, btotal);
+  {
+    unsigned long long run = texcl;
+#pragma unroll
+    for (uint32_t k = 0; k < kExpandPer; ++k) {
+      s_off[kExpandPer * tid + k] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(run);
+      run += c[k];
+    }
+  }
+
+  // ---- decoupled look-back, window = the whole workgroup ----
+  const unsigned long long mine = btotal > kSat ? kSat : btotal;
+  unsigned long long excl = 0;
+  if (ticket == 0) {
+    if (tid == 0) st_agent(&a.lookback[0], kLbInc64 | mine);
+  } else {
+    if (tid == 0) st_agent(&a.lookback[ticket], kLbAgg64 | mine);
+    int64_t top = static_cast<int64_t>(ticket) - 1;
+    uint32_t spins = 0;
+    while (true) {
+      const int64_t idx = top - static_cast<int64_t>(tid);
+      const uint64_t w = idx >= 0 ? ld_agent(&a.lookback[idx]) : kLbInc64;
+      const uint32_t state = static_cast<uint32_t>(w >> 62);
+      if (tid == 0) {
+        s_first = 0xFFFFFFFFu;
+        s_retry = 0;
+      }
+      __syncthreads();
+      if (state == 2) atomicMin(&s_first, tid);
+      __syncthreads();
+      const uint32_t first = s_first;
+      if (state == 0 && tid < first) s_retry = 1;
+      __syncthreads();
+      if (s_retry) {
+        if (++spins > kSpinLimit) {
+          if (tid == 0) s_timeout = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+        continue;
+      }
+      const unsigned long long v = tid <= first ? (w & kLbMask64) : 0ull;
+      const unsigned long long sum = block_reduce_sum<unsigned long long, kExpandThreads>(v, s_tmp64);
+      excl += sum;
+      if (excl > kSat) excl = kSat;
+      if (first != 0xFFFFFFFFu) break;
+      top -= kExpandThreads;
+    }
+    if (tid == 0) {
+      const unsigned long long inc = excl + btotal;
+      st_agent(&a.lookback[ticket], kLbInc64 | (inc > kSat ? kSat : inc));
+    }
+  }
+  if (tid == 0) s_prefix = excl;
+  __syncthreads();
+  if (s_timeout) {
+    if (tid == 0) st_agent(const_cast<uint32_t*>(a.status), static_cast<uint32_t>(SS_ERR_TIMEOUT));
+    return;
+  }
+  const unsigned long long prefix = s_prefix;
+  uint32_t total = 0;
+  if (prefix < a.capacity) {
+    const unsigned long long room = a.capacity - prefix;
+    total = static_cast<uint32_t>(btotal < room ? btotal : room);
+  }
+  uint64_t* __restrict__ keys = a.keys + prefix;
+  uint32_t* __restrict__ vals = a.values + prefix;
+
+  // ---- expansion in rounds of kChunk pairs ----
+  for (uint32_t cb = 0; cb < total; cb += kChunk) {
+#pragma unroll
+    for (uint32_t k = 0; k < kChunkPer; ++k) s_map[k * kExpandThreads + tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kExpandPer; ++k) {
+      const uint32_t i = kExpandPer * tid + k;
+      const uint32_t o = s_off[i];
+      if (c[k] != 0 && o < cb + kChunk && o + c[k] > cb)
+        s_map[(o > cb ? o : cb) - cb] = static_cast<uint16_t>(i + 1);
+    }
+    __syncthreads();
+    // inclusive max-scan of the markers: per thread over its 8 slots, then
+    // across threads; slots before a thread's first marker take the maximum
+    // of all earlier threads
+    uint32_t m[kChunkPer];
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kChunkPer; ++k) {
+      run = max(run, static_cast<uint32_t>(s_map[kChunkPer * tid + k]));
+      m[k] = run;
+    }
+    s_incl[tid] = block_inclusive_max<kExpandThreads>(run, s_tmp);
+    __syncthreads();
+    const uint32_t prev = tid == 0 ? 0u : s_incl[tid - 1];
+#pragma unroll
+    for (uint32_t k = 0; k < kChunkPer; ++k) s_map[kChunkPer * tid + k] = static_cast<uint16_t>(max(m[k], prev));
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kChunkPer; ++k) {
+      const uint32_t q = cb + k * kExpandThreads + tid;
+      if (q < total) {
+        const uint32_t i = static_cast<uint32_t>(s_map[q - cb]) - 1u;
+        if (i >= kExpandTile) continue;  // every slot has an owner; kept for safety
+        const uint32_t kk = q - s_off[i];
+        const uint32_t wt = s_wt[i];
+        const uint32_t w = wt & 0xFFFFu;
+        const uint32_t dy = kk / w;
+        const uint32_t dx = kk - dy * w;
+        const uint32_t tile = s_org[i] + dy * (wt >> 16) + dx;
+        keys[q] = (static_cast<uint64_t>(tile) << 32) | s_dep[i];
+        vals[q] = s_loc[i];
+        for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&s_hist[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+      }
+    }
+    __syncthreads();
+  }
+  uint32_t* gh = a.hist + static_cast<size_t>(ticket % kHistCopies) * a.npasses * bins;
+  for (uint32_t i = tid; i < a.npasses * bins; i += kExpandThreads) {
+    const uint32_t v = s_hist[i];
+    if (v) atomicAdd(&gh[i], v);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_table, dim3(1), dim3(kArgFrames), 0, s, c, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s) {
+  const uint32_t blocks = (a.n + kCountKeysTile - 1) / kCountKeysTile;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_keys, dim3(blocks), dim3(kCountKeysThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_depth_bases(const DepthBasesArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_depth_bases, dim3(5), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
+  if (a.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand, dim3(a.nblocks), dim3(kExpandThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ss

@@ -53,6 +53,86 @@ struct HistArgs {
   uint32_t* hist;             // zeroed [kHistCopies][npasses][bins]
 };
 
+// One frame of a (possibly one-frame) batch, as the depth-first kernels see it.
+struct FrameInfo {
+  uint32_t gauss_base;   // first global Gaussian index of the frame
+  uint32_t n;            // Gaussians of the frame
+  uint32_t tiles_x, tiles_y;
+  uint32_t tile_base;    // first global tile id of the frame
+  uint32_t pad;
+  const ss_gaussian2d* gaussians;
+};
+static_assert(sizeof(FrameInfo) == 32, "frame table entry");
+
+// Frames carried by value in one launch's arguments.
+constexpr uint32_t kArgFrames = 32;
+constexpr uint32_t kMaxFrames = 256;
+
+struct TableChunk {
+  uint32_t first;        // table index of f[0]
+  uint32_t count;        // valid entries of f
+  FrameInfo f[kArgFrames];
+};
+
+// Depth-first kernels (see depthfirst.hip).
+struct CountKeysArgs {
+  const FrameInfo* table;   // [n_frames] in device memory
+  uint32_t n_frames;
+  uint32_t n;               // Gaussians of all frames
+  uint64_t* rect;           // out [n]: x0 | y0 << 16 | w << 32 | h << 48 (tiles)
+  uint32_t* key;            // out [n]: depth bits, or 0xFFFFFFFF when culled
+  uint32_t* val;            // out [n]: global Gaussian index
+  uint32_t* tiles_touched;  // optional [n]
+  uint32_t* hist;           // zeroed [kHistCopies][4][256] depth digit histograms
+  unsigned long long* totals;  // zeroed [1 + n_frames]: pairs per frame at [1 + f]
+                               // (only workgroups that span several frames add here)
+  unsigned long long* block_total;  // [nblocks] pairs of a one-frame workgroup, else 0
+  uint32_t* block_frame;    // [nblocks] that workgroup's frame
+  uint32_t* bad;            // zeroed flag: a touching Gaussian has a bad depth
+};
+
+struct ExpandArgs {
+  const FrameInfo* table;
+  uint32_t n_frames;
+  uint32_t n;               // sorted Gaussians
+  const uint32_t* key;      // sorted depth keys
+  const uint32_t* val;      // sorted global indices
+  const uint64_t* rect;     // by global index
+  uint32_t capacity;
+  uint64_t* keys;           // out pairs: global tile << 32 | depth bits
+  uint32_t* values;         // out: frame-local Gaussian index
+  uint32_t npasses;         // tile-digit passes that follow
+  uint32_t radix_bits;      // their digit width (<= 8)
+  uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits]
+  uint32_t* ticket;         // zeroed
+  uint64_t* lookback;       // zeroed [nblocks]
+  const uint32_t* status;
+  uint32_t nblocks;
+};
+
+hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s);
+hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s);
+// Digit bases of the 4 depth passes, and num_pairs / status from the totals.
+struct DepthBasesArgs {
+  const uint32_t* hist;
+  uint32_t* bases;
+  const unsigned long long* totals;
+  const unsigned long long* block_total;
+  const uint32_t* block_frame;
+  uint32_t count_blocks;
+  const uint32_t* bad;
+  uint32_t n_frames;
+  uint32_t capacity;
+  uint32_t* num_pairs;
+  uint32_t* status;
+  uint32_t* frame_pairs;       // optional
+  uint32_t* frame_pair_base;   // optional
+};
+hipError_t launch_depth_bases(const DepthBasesArgs& a, hipStream_t s);
+hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+constexpr uint32_t kCountKeysTile = 2048;   // Gaussians per count workgroup
+constexpr uint32_t kExpandTile = 2048;      // Gaussians per expand workgroup
+
 // Zeroes `bytes` (a multiple of 16) at p and, if not NULL, the word `extra`.
 hipError_t launch_clear(void* p, size_t bytes, uint32_t* extra, hipStream_t s);
 hipError_t launch_count_dup(const CountDupArgs& a, int radix_bits, bool dup, hipStream_t s);

@@ -147,3 +147,27 @@ def test_product_and_oracle_share_no_code():
         for fn in files:
             if fn.endswith((".hip", ".hpp")):
                 assert "oracle.h" not in open(os.path.join(dirpath, fn)).read()
+
+
+def test_batch_argument_errors():
+    fr = [frame(640, 360, n=100, ptr=1 << 12), frame(1280, 720, n=50, ptr=1 << 14)]
+    st, need = _abi.ss_batch_workspace_bytes(fr, 1000)
+    assert st == _abi.SS_OK and need > 0
+    assert _abi.ss_batch_workspace_bytes([], 10)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_batch_workspace_bytes([frame()] * 257, 10)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_batch_workspace_bytes([fr[0], frame(0, 5)], 10)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_batch_workspace_bytes(fr, 10, _abi.make_options(algorithm=2))[0] == _abi.SS_ERR_UNSUPPORTED
+    o = _abi.ss_batch_out()
+    o.pair_capacity = 1000
+    o.keys, o.values, o.tile_ranges = 1 << 20, 2 << 20, 3 << 20
+    assert _abi.ss_sort_batch(fr, o, 4 << 20, need - 1, None) == _abi.SS_ERR_WORKSPACE
+    o.tile_ranges = None
+    assert _abi.ss_sort_batch(fr, o, 4 << 20, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+
+
+def test_algorithm_option_validated():
+    f = frame(n=10, ptr=1 << 12)
+    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=3))[0] == _abi.SS_ERR_UNSUPPORTED
+    a = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=1))
+    b = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=2))
+    assert a[0] == b[0] == _abi.SS_OK and a[1] != b[1]

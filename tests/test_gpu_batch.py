@@ -1,0 +1,120 @@
+"""Batched (segmented) sort on the GPU against the oracle's batched layout:
+global tile ids tile_base[f] + t, frame-local values, frame-major segments,
+global ranges.  Bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_16298_amd as ss  # noqa: E402
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def run_batch(frames, capacity=None, **kw):
+    if capacity is None:
+        capacity = 0
+        for (w, h, rec) in frames:
+            cnt, _ = oracle.count(w, h, rec)
+            capacity += int(cnt.astype(np.uint64).sum())
+    b = ss.BatchSorter([(w, h, len(r)) for (w, h, r) in frames], capacity, **kw)
+    recs = [ss.records_to_device(r) for (_, _, r) in frames]
+    b(recs)
+    st, m = b.result()
+    return b, st, m
+
+
+def check_against_oracle(frames, b, m):
+    ref = oracle.sort_batch(frames)
+    assert m == int(ref.num_pairs.sum())
+    assert np.array_equal(u64(b.keys)[:m], ref.keys)
+    assert np.array_equal(u32(b.values)[:m], ref.values)
+    assert np.array_equal(u32(b.tile_ranges).reshape(-1, 2), ref.ranges)
+    assert np.array_equal(u32(b.frame_pairs), ref.num_pairs.astype(np.uint32))
+    assert np.array_equal(u32(b.frame_pair_base), ref.pair_base.astype(np.uint32))
+    assert np.array_equal(b.tile_base, ref.tile_base.astype(np.int64))
+
+
+@pytest.mark.parametrize("rb", [8, 4])
+def test_small_batch(rb):
+    frames = synth.make_batch(8, n_range=(5_000, 50_000))
+    b, st, m = run_batch(frames, radix_bits=rb)
+    assert st == 0
+    check_against_oracle(frames, b, m)
+
+
+def test_each_frame_alone_equals_its_segment():
+    frames = synth.make_batch(5, seed=77, n_range=(20_000, 60_000))
+    b, st, m = run_batch(frames)
+    assert st == 0
+    keys, vals = u64(b.keys)[:m], u32(b.values)[:m]
+    base, cnt = u32(b.frame_pair_base), u32(b.frame_pairs)
+    for f, (w, h, rec) in enumerate(frames):
+        out = ss.sort_frame(ss.records_to_device(rec), w, h)
+        st1, m1 = out.result()
+        assert st1 == 0 and m1 == cnt[f]
+        seg = slice(int(base[f]), int(base[f]) + m1)
+        tb = np.uint64(int(b.tile_base[f])) << np.uint64(32)
+        assert np.array_equal(keys[seg] - tb, u64(out.keys)[:m1])
+        assert np.array_equal(vals[seg], u32(out.values)[:m1])
+
+
+def test_batch_with_degenerate_frames():
+    rs = np.random.default_rng(3)
+    empty = np.zeros(0, dtype=synth.RECORD_DTYPE)
+    culled = synth.make_frame(synth.FrameSpec(300, 200, 4000), 4)
+    culled["radius"] = 0
+    one_tile = synth.make_frame(synth.FrameSpec(12, 10, 3000), 5)
+    normal = synth.make_frame(synth.FrameSpec(640, 360, 20000), 6)
+    ties = synth.make_frame(synth.FrameSpec(100, 100, 5000), 7)
+    ties["depth"] = rs.choice(np.float32([1.0, 2.0]), 5000)
+    frames = [(64, 64, empty), (300, 200, culled), (12, 10, one_tile), (640, 360, normal), (100, 100, ties),
+              (64, 64, empty)]
+    b, st, m = run_batch(frames)
+    assert st == 0
+    check_against_oracle(frames, b, m)
+
+
+def test_batch_capacity_error():
+    frames = synth.make_batch(3, n_range=(5_000, 9_000))
+    total = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)
+    b, st, m = run_batch(frames, capacity=total - 1)
+    assert st == ss._abi.SS_ERR_CAPACITY and m == total
+
+
+def test_full_64_frame_batch_sampled():
+    """The 64-frame batch at full size: three frames checked pair for pair
+    against the oracle, every frame checked by invariants."""
+    frames = synth.make_batch(64)
+    b, st, m = run_batch(frames)
+    assert st == 0
+    keys, vals = u64(b.keys)[:m], u32(b.values)[:m]
+    rng = u32(b.tile_ranges).reshape(-1, 2)
+    base, cnt = u32(b.frame_pair_base).astype(np.int64), u32(b.frame_pairs).astype(np.int64)
+    assert base[0] == 0 and np.array_equal(base[1:], (base + cnt)[:-1]) and base[-1] + cnt[-1] == m
+    assert np.all(keys[1:] >= keys[:-1])
+    assert rng[0, 0] == 0 and rng[-1, 1] == m and np.array_equal(rng[1:, 0], rng[:-1, 1])
+    sizes = [len(r) for (_, _, r) in frames]
+    for f in np.argsort(sizes)[:3]:
+        w, h, rec = frames[f]
+        ref = oracle.sort_frame(w, h, rec, stages=False)
+        seg = slice(int(base[f]), int(base[f] + cnt[f]))
+        assert cnt[f] == ref.num_pairs
+        tb = np.uint64(int(b.tile_base[f])) << np.uint64(32)
+        assert np.array_equal(keys[seg] - tb, ref.keys)
+        assert np.array_equal(vals[seg], ref.values)
+    for f, (w, h, rec) in enumerate(frames):
+        seg = slice(int(base[f]), int(base[f] + cnt[f]))
+        v = vals[seg]
+        cnt_g, _ = oracle.count(w, h, rec)
+        assert np.array_equal(np.bincount(v, minlength=len(rec))[:len(rec)], cnt_g)

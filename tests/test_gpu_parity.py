@@ -29,13 +29,17 @@ def u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False):
+ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT]
+
+
+def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False, algorithm=0):
     d = ss.records_to_device(rec)
     if capacity is None:
         _, _, m, s = ss.count_pairs(d, W, H)
         assert int(s.item()) == 0
         capacity = int(m.item()) & 0xFFFFFFFF
-    sorter = ss.FrameSorter(W, H, len(rec), capacity, radix_bits, items, stages=stages, unsorted=unsorted)
+    sorter = ss.FrameSorter(W, H, len(rec), capacity, radix_bits, items, stages=stages, unsorted=unsorted,
+                            algorithm=algorithm)
     out = sorter(d)
     st, m = out.result()
     res = {"status": st, "M": m}
@@ -63,34 +67,39 @@ def assert_same(W, H, rec, g, stages=True):
     return o
 
 
-def test_tiny_frames():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_tiny_frames(algo):
     rs = np.random.default_rng(2024)
     for case in range(60):
         W, H, rec = pins.random_tiny_frame(rs)
         print(f"tiny case {case}: {W}x{H} n={len(rec)}", flush=True)
-        assert_same(W, H, rec, gpu_frame(W, H, rec))
+        assert_same(W, H, rec, gpu_frame(W, H, rec, algorithm=algo))
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("name", ["small-256x256", "fullhd-1m"])
-def test_workload_frames(name):
+def test_workload_frames(name, algo):
     spec, seed = synth.FRAME_WORKLOADS[name]
     rec = synth.make_frame(spec, seed)
-    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec))
+    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec, algorithm=algo))
 
 
-def test_large_frame_full_size():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_large_frame_full_size(algo):
     spec, seed = synth.FRAME_WORKLOADS["large-6m"]
     rec = synth.make_frame(spec, seed)
-    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec, stages=False),
-                stages=False)
+    assert_same(spec.width, spec.height, rec,
+                gpu_frame(spec.width, spec.height, rec, stages=False, algorithm=algo), stages=False)
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("rb,items", [(8, 8), (8, 12), (6, 16), (4, 16), (4, 8)])
-def test_radix_widths_and_tiles(rb, items):
+def test_radix_widths_and_tiles(rb, items, algo):
     spec, seed = synth.FRAME_WORKLOADS["fullhd-1m"]
     spec = synth.scaled(spec, 150_000)
     rec = synth.make_frame(spec, seed)
-    assert_same(spec.width, spec.height, rec, gpu_frame(spec.width, spec.height, rec, radix_bits=rb, items=items))
+    assert_same(spec.width, spec.height, rec,
+                gpu_frame(spec.width, spec.height, rec, radix_bits=rb, items=items, algorithm=algo))
 
 
 def test_unsorted_stage_matches_duplication_order():
@@ -119,29 +128,35 @@ def blank(n):
     return np.zeros(n, dtype=synth.RECORD_DTYPE)
 
 
-def test_empty_and_degenerate_frames():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_empty_and_degenerate_frames(algo):
     # no Gaussians
-    assert_same(100, 70, blank(0), gpu_frame(100, 70, blank(0), capacity=0))
+    assert_same(100, 70, blank(0), gpu_frame(100, 70, blank(0), capacity=0, algorithm=algo))
     # every radius 0: M = 0, all ranges empty
     rec = synth.make_frame(synth.scaled(synth.SMALL, 5000), 5)
     rec["radius"] = 0
-    g = gpu_frame(256, 256, rec, capacity=0)
+    g = gpu_frame(256, 256, rec, capacity=0, algorithm=algo)
     assert g["M"] == 0 and not g["ranges"].any()
     # one tile (T = 1, 32-bit keys)
     rec = synth.make_frame(synth.FrameSpec(16, 9, 20_000), 6)
-    assert_same(16, 9, rec, gpu_frame(16, 9, rec))
+    assert_same(16, 9, rec, gpu_frame(16, 9, rec, algorithm=algo))
     # every pair in one tile of a large grid, equal depths (pure index order)
     rec = blank(70_001)
     rec["mean_x"], rec["mean_y"], rec["radius"], rec["depth"] = 16 * 700 + 8, 16 * 300 + 8, 1, 2.5
-    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec))
+    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec, algorithm=algo))
     # every Gaussian covers the whole grid
     rec = synth.make_frame(synth.FrameSpec(200, 120, 900), 8)
     rec["radius"] = 5000
-    assert_same(200, 120, rec, gpu_frame(200, 120, rec))
+    assert_same(200, 120, rec, gpu_frame(200, 120, rec, algorithm=algo))
+    # a few Gaussians covering thousands of tiles among many small ones
+    rec = synth.make_frame(synth.scaled(synth.FULL_HD, 30_000), 9)
+    rec["radius"][::997] = 700
+    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec, algorithm=algo))
 
 
-@pytest.mark.parametrize("m", [4095, 4096, 4097, 3 * 4096 - 1, 3 * 4096 + 1, 1023, 1025])
-def test_pair_counts_around_tile_sizes(m):
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("m", [4095, 4096, 4097, 3 * 4096 - 1, 3 * 4096 + 1, 1023, 1025, 8191, 8193, 2047, 2049])
+def test_pair_counts_around_tile_sizes(m, algo):
     # m Gaussians of one tile each: M = m, spread over the grid
     rs = np.random.default_rng(m)
     rec = blank(m)
@@ -149,40 +164,41 @@ def test_pair_counts_around_tile_sizes(m):
     rec["mean_y"] = 16 * (16 * rs.integers(0, 68, m) + 8)
     rec["radius"] = 1
     rec["depth"] = rs.choice(np.float32([1.0, 2.0, 3.0]), m)
-    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec))
+    assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec, algorithm=algo))
 
 
-def test_device_errors():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_device_errors(algo):
     spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
     rec = synth.make_frame(spec, seed)
     o = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
     # capacity one short
-    g = gpu_frame(256, 256, rec, capacity=o.num_pairs - 1)
+    g = gpu_frame(256, 256, rec, capacity=o.num_pairs - 1, algorithm=algo)
     assert g["status"] == _abi.SS_ERR_CAPACITY and g["M"] == o.num_pairs
     # a NaN or negative depth on a Gaussian that touches a tile
     for bad in (np.nan, -1.0, np.inf, 0.0):
         r2 = rec.copy()
         r2["depth"][1234] = bad
-        assert gpu_frame(256, 256, r2, capacity=o.num_pairs)["status"] == _abi.SS_ERR_INVALID_INPUT
+        assert gpu_frame(256, 256, r2, capacity=o.num_pairs, algorithm=algo)["status"] == _abi.SS_ERR_INVALID_INPUT
     # ... but not on a culled one
     r2 = rec.copy()
     r2["depth"][1234], r2["radius"][1234] = np.nan, 0
-    g = gpu_frame(256, 256, r2, capacity=o.num_pairs)
+    g = gpu_frame(256, 256, r2, capacity=o.num_pairs, algorithm=algo)
     assert g["status"] == 0
     assert_same(256, 256, r2, g)
     # 2^32 pairs or more: 300 Gaussians covering 4096 x 4096 tiles
     rec = blank(300)
     rec["mean_x"] = rec["mean_y"] = 16 * 32768
     rec["radius"], rec["depth"] = 40000, 1.0
-    g = gpu_frame(65536, 65536, rec, capacity=1000, stages=False)
+    g = gpu_frame(65536, 65536, rec, capacity=1000, stages=False, algorithm=algo)
     assert g["status"] == _abi.SS_ERR_OVERFLOW and g["M"] == 0xFFFFFFFF
     # a frame status is reset by the next call on the same buffers
     spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
     rec = synth.make_frame(spec, seed)
     d = ss.records_to_device(rec)
-    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs - 1)
+    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs - 1, algorithm=algo)
     assert sorter(d).result()[0] == _abi.SS_ERR_CAPACITY
-    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs)
+    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs, algorithm=algo)
     r2 = rec.copy()
     r2["depth"][7] = np.nan
     assert sorter(ss.records_to_device(r2)).result()[0] == _abi.SS_ERR_INVALID_INPUT
@@ -202,12 +218,13 @@ def test_sort_pairs_against_stable_argsort(n, key_bits):
     assert np.array_equal(u64(ko), ok) and np.array_equal(u32(vo), ov)
 
 
-def test_repeated_runs_are_identical():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_repeated_runs_are_identical(algo):
     spec, seed = synth.FRAME_WORKLOADS["fullhd-1m"]
     rec = synth.make_frame(spec, seed)
     d = ss.records_to_device(rec)
     _, _, m, _ = ss.count_pairs(d, spec.width, spec.height)
-    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), int(m.item()))
+    sorter = ss.FrameSorter(spec.width, spec.height, len(rec), int(m.item()), algorithm=algo)
     digests = set()
     for _ in range(10):
         out = sorter(d)

@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="fullhd-1m", choices=sorted(synth.FRAME_WORKLOADS))
+    p.add_argument("--workload", default="fullhd-1m", choices=sorted(synth.FRAME_WORKLOADS) + ["batch-64"])
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
@@ -135,10 +135,91 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def bench_batch(args):
+    """64 uneven frames: one segmented sort (eager, and captured in an
+    autotuned graph) against 64 plain per-frame launches, same outputs."""
+    import torch
+    import paper_2511_16298_amd as ss
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    frames = synth.make_batch(64)
+    recs = [ss.records_to_device(r, dev) for (_, _, r) in frames]
+    ms = []
+    for (w, h, _), d in zip(frames, recs):
+        _, _, m, st = ss.count_pairs(d, w, h)
+        assert int(st.item()) == 0
+        ms.append(int(m.item()))
+    total = sum(ms)
+    shapes = [(w, h, len(r)) for (w, h, r) in frames]
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    print(f"# batch-64: N={sum(s[2] for s in shapes)}, M={total}", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        ev[0].record(stream)
+        for i in range(K):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+        return ev[0].elapsed_time(ev[K]) / K, per
+
+    eager = ss.BatchSorter(shapes, total, device=dev)
+    t_eager, _ = timed(lambda: eager(recs, stream))
+    assert eager.result() == (0, total)
+    gsorter = ss.BatchSorter(shapes, total, device=dev, plan_workspace=True)
+    plan = ss.Plan(gsorter, recs, autotune=True, stream=stream)
+    t_graph, per_graph = timed(lambda: plan.launch(stream))
+    assert gsorter.result() == (0, total)
+    plain = [ss.FrameSorter(w, h, n, m, device=dev) for (w, h, n), m in zip(shapes, ms)]
+
+    def run_plain():
+        for so, d in zip(plain, recs):
+            so(d, stream)
+    t_plain, _ = timed(run_plain)
+    # identical outputs: every frame's plain result equals its batch segment
+    base = gsorter.frame_pair_base.cpu().numpy().astype(np.int64)
+    gk = gsorter.keys.cpu().numpy().view(np.uint64)
+    gv = gsorter.values.cpu().numpy().view(np.uint32)
+    same = True
+    for f, so in enumerate(plain):
+        k = so.out.keys.cpu().numpy().view(np.uint64)[:ms[f]]
+        v = so.out.values.cpu().numpy().view(np.uint32)[:ms[f]]
+        tb = np.uint64(int(gsorter.tile_base[f])) << np.uint64(32)
+        seg = slice(int(base[f]), int(base[f]) + ms[f])
+        same &= bool(np.array_equal(gk[seg] - tb, k) and np.array_equal(gv[seg], v))
+    cfg = plan.config()
+    line = {"metric": "sorted key-value pairs/s, 64-frame segmented batch vs 64 plain launches",
+            "value": total / (t_graph * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "batch-64: 64 frames, resolution uniform over 640x360/1280x720/1920x1080, "
+                                   "N log-uniform in [5e4, 2e6], seed 1003", "num_pairs": total,
+                       "parallelism": "single GPU"},
+            "batch_graph_pairs_per_s": total / (t_graph * 1e-3),
+            "batch_eager_pairs_per_s": total / (t_eager * 1e-3),
+            "plain_64_launches_pairs_per_s": total / (t_plain * 1e-3),
+            "speedup_vs_plain": t_plain / t_graph,
+            "latency_ms": {"p50": pct(per_graph, 50), "p99": pct(per_graph, 99)},
+            "autotuned": {k: v for k, v in cfg.items()}, "outputs_identical": same}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
+        return
+    if args.workload == "batch-64":
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_batch(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "

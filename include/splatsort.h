@@ -174,6 +174,37 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
 
+/* A plan: one batch shape (frame sizes, record and output pointers, the
+ * workspace) with the batched pipeline captured once into a HIP graph and
+ * replayed by ss_plan_launch.  Inputs may change between launches; their
+ * addresses and the frame shapes may not.  With autotune != 0, creation
+ * times every compiled pass configuration (radix width 4/6/8, items per
+ * thread, workgroup size) on the given data and keeps the fastest; the
+ * results are identical whichever is chosen.  Creation synchronises the
+ * stream; the workspace must hold ss_plan_workspace_bytes.  Graph capture
+ * runs on a stream the plan owns. */
+typedef struct ss_plan ss_plan;
+typedef struct ss_plan_desc {
+  uint32_t struct_size;      /* sizeof(ss_plan_desc) */
+  uint32_t n_frames;
+  const ss_frame* frames;    /* host array [n_frames]; gaussians are device pointers */
+  ss_batch_out out;
+  void* workspace;
+  size_t workspace_bytes;
+  uint32_t autotune;         /* 0: use options; 1: time the candidates, keep the fastest */
+  uint32_t tune_repeats;     /* launches timed per candidate (0 = 5) */
+  ss_options options;        /* starting / fixed configuration (timer ignored) */
+} ss_plan_desc;
+
+ss_status ss_plan_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uint32_t pair_capacity,
+                                  size_t* bytes);
+ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream);
+ss_status ss_plan_launch(ss_plan* plan, void* stream);
+/* The configuration in use (after autotuning) and the tuned time per launch
+ * of each candidate tried (ms, in the order they were tried; up to n). */
+ss_status ss_plan_config(const ss_plan* plan, ss_options* chosen, double* candidate_ms, uint32_t* n);
+void ss_plan_destroy(ss_plan* plan);
+
 /* Step a4 alone on caller data (the paper's random key-value sort benchmark,
  * Evaluation, "Datasets"): stable sort of n pairs by key bits [0, key_bits);
  * keys must be < 2^key_bits.  keys_in/values_in are not modified; they may

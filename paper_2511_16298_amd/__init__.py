@@ -17,7 +17,7 @@ from . import _abi
 from ._abi import (SS_ALGO_AUTO, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
-__all__ = ["FrameSorter", "BatchSorter", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
+__all__ = ["FrameSorter", "BatchSorter", "Plan", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
            "SS_ALGO_DIRECT"]
 
@@ -173,7 +173,7 @@ class BatchSorter:
     ``[(width, height, num_gaussians), ...]`` (one segmented sort)."""
 
     def __init__(self, shapes, pair_capacity: int, radix_bits: int = 0, items_per_thread: int = 0,
-                 workgroup_size: int = 0, device="cuda"):
+                 workgroup_size: int = 0, device="cuda", plan_workspace: bool = False):
         import numpy as np
         torch = _torch()
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
@@ -188,8 +188,12 @@ class BatchSorter:
             f.width, f.height, f.tile_px, f.num_gaussians = w, h, 16, n
             f.gaussians = 16 if n else None
             probe.append(f)
-        st, ws = _abi.ss_batch_workspace_bytes(probe, self.capacity, self.options)
-        check(st, "ss_batch_workspace_bytes")
+        if plan_workspace:
+            st, ws = _abi.ss_plan_workspace_bytes(probe, self.capacity)
+            check(st, "ss_plan_workspace_bytes")
+        else:
+            st, ws = _abi.ss_batch_workspace_bytes(probe, self.capacity, self.options)
+            check(st, "ss_batch_workspace_bytes")
         self.workspace_bytes = ws
         self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
         cap = max(self.capacity, 1)
@@ -226,6 +230,46 @@ class BatchSorter:
     def result(self):
         """Synchronise and return (status, total pairs)."""
         return int(self.status.item()), int(self.num_pairs.item()) & 0xFFFFFFFF
+
+    def frames_for(self, records_list):
+        return [_frame(rec, w, h) for rec, (w, h, _) in zip(records_list, self.shapes)]
+
+
+class Plan:
+    """A BatchSorter's pipeline captured into a HIP graph (``ss_plan_*``) for
+    fixed record tensors; ``autotune`` times every compiled pass configuration
+    first.  The sorter must have been made with ``plan_workspace=True``."""
+
+    def __init__(self, sorter: BatchSorter, records_list, autotune: bool = True, tune_repeats: int = 0,
+                 stream=None):
+        self.sorter = sorter
+        self.records = list(records_list)   # keep the captured inputs alive
+        st, h = _abi.ss_plan_create(sorter.frames_for(self.records), sorter._cout, sorter.workspace.data_ptr(),
+                                    sorter.workspace_bytes, _stream_handle(stream), int(autotune), tune_repeats,
+                                    sorter.options)
+        check(st, "ss_plan_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        check(_abi.ss_plan_launch(self.handle, _stream_handle(stream)), "ss_plan_launch")
+        return self.sorter
+
+    def config(self):
+        st, o, ms = _abi.ss_plan_config(self.handle)
+        check(st, "ss_plan_config")
+        return {"radix_bits": o.radix_bits, "items_per_thread": o.items_per_thread,
+                "workgroup_size": o.workgroup_size, "candidate_ms": ms}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _abi.ss_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def count_pairs(records, width: int, height: int, stream=None):

@@ -96,6 +96,13 @@ _P = ctypes.c_void_p
 _U32 = ctypes.c_uint32
 _SZ = ctypes.c_size_t
 
+
+class ss_plan_desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_frames", ctypes.c_uint32),
+                ("frames", ctypes.c_void_p), ("out", ss_batch_out), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("autotune", ctypes.c_uint32),
+                ("tune_repeats", ctypes.c_uint32), ("options", ss_options)]
+
 _SIGNATURES = {
     "ss_abi_version": ([], _U32),
     "ss_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -109,6 +116,12 @@ _SIGNATURES = {
                                   ctypes.POINTER(_SZ)], ctypes.c_int),
     "ss_sort_batch": ([ctypes.POINTER(ss_frame), _U32, ctypes.POINTER(ss_batch_out), _P, _SZ, _P,
                        ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_plan_workspace_bytes": ([ctypes.POINTER(ss_frame), _U32, _U32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ss_plan_create": ([ctypes.POINTER(_P), ctypes.POINTER(ss_plan_desc), _P], ctypes.c_int),
+    "ss_plan_launch": ([_P, _P], ctypes.c_int),
+    "ss_plan_config": ([_P, ctypes.POINTER(ss_options), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
+                       ctypes.c_int),
+    "ss_plan_destroy": ([_P], None),
     "ss_sort_pairs_workspace_bytes": ([_U32, _U32, ctypes.POINTER(ss_options), ctypes.POINTER(_SZ)],
                                       ctypes.c_int),
     "ss_sort_pairs": ([_P, _P, _U32, _U32, _P, _P, _P, _SZ, _P, ctypes.POINTER(ss_options)],
@@ -205,6 +218,47 @@ def ss_sort_batch(frames, out: ss_batch_out, workspace, workspace_bytes, stream,
     arr = _frames_array(frames)
     return lib().ss_sort_batch(arr, len(frames), ctypes.byref(out), workspace, workspace_bytes, stream,
                                ctypes.byref(options) if options is not None else None)
+
+
+def ss_plan_workspace_bytes(frames, pair_capacity: int):
+    arr = _frames_array(frames)
+    b = _SZ()
+    st = lib().ss_plan_workspace_bytes(arr, len(frames), pair_capacity, ctypes.byref(b))
+    return st, b.value
+
+
+def ss_plan_create(frames, out: ss_batch_out, workspace, workspace_bytes, stream, autotune=0, tune_repeats=0,
+                   options=None):
+    arr = _frames_array(frames)
+    d = ss_plan_desc()
+    d.struct_size = ctypes.sizeof(ss_plan_desc)
+    d.n_frames = len(frames)
+    d.frames = ctypes.addressof(arr)
+    d.out = out
+    d.workspace = workspace
+    d.workspace_bytes = workspace_bytes
+    d.autotune = autotune
+    d.tune_repeats = tune_repeats
+    d.options = options if options is not None else make_options()
+    h = _P()
+    st = lib().ss_plan_create(ctypes.byref(h), ctypes.byref(d), stream)
+    return st, h.value
+
+
+def ss_plan_launch(plan, stream) -> int:
+    return lib().ss_plan_launch(plan, stream)
+
+
+def ss_plan_config(plan, max_candidates: int = 16):
+    o = ss_options()
+    ms = (ctypes.c_double * max_candidates)()
+    n = _U32(max_candidates)
+    st = lib().ss_plan_config(plan, ctypes.byref(o), ms, ctypes.byref(n))
+    return st, o, [ms[i] for i in range(min(n.value, max_candidates))]
+
+
+def ss_plan_destroy(plan) -> None:
+    lib().ss_plan_destroy(plan)
 
 
 def ss_sort_pairs_workspace_bytes(n: int, key_bits: int, options=None):

@@ -1,0 +1,179 @@
+// Plans: a fixed batch shape whose whole pipeline is captured once into a
+// HIP graph and replayed; optional autotuning of the pass configuration by
+// timing every compiled candidate on the caller's data.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <new>
+#include <vector>
+
+#include "splatsort.h"
+
+struct ss_plan {
+  std::vector<ss_frame> frames;
+  ss_batch_out out{};
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+  ss_options options{};
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double> candidate_ms;
+};
+
+namespace {
+
+struct Candidate {
+  uint32_t radix_bits, items, threads;
+};
+
+// Every pass configuration compiled into the library.
+const Candidate kCandidates[] = {
+    {8, 16, 512}, {8, 8, 512}, {8, 16, 256}, {8, 12, 256}, {8, 8, 256}, {6, 16, 256}, {4, 16, 256},
+};
+
+ss_options with(const ss_options& base, const Candidate& c) {
+  ss_options o = base;
+  o.struct_size = sizeof(ss_options);
+  o.radix_bits = c.radix_bits;
+  o.items_per_thread = c.items;
+  o.workgroup_size = c.threads;
+  o.timer = nullptr;
+  o.flags = 0;
+  return o;
+}
+
+void destroy(ss_plan* p) {
+  if (p == nullptr) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  delete p;
+}
+
+// Mean milliseconds per launch of one configuration (after one warm-up).
+ss_status time_candidate(ss_plan* p, const ss_options& o, uint32_t repeats, hipStream_t s, double* ms) {
+  const uint32_t n = static_cast<uint32_t>(p->frames.size());
+  ss_status st = ss_sort_batch(p->frames.data(), n, &p->out, p->workspace, p->workspace_bytes, s, &o);
+  if (st != SS_OK) return st;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return SS_ERR_HIP;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return SS_ERR_HIP;
+  }
+  st = SS_OK;
+  if (hipEventRecord(a, s) != hipSuccess) st = SS_ERR_HIP;
+  for (uint32_t i = 0; st == SS_OK && i < repeats; ++i)
+    st = ss_sort_batch(p->frames.data(), n, &p->out, p->workspace, p->workspace_bytes, s, &o);
+  if (st == SS_OK && hipEventRecord(b, s) != hipSuccess) st = SS_ERR_HIP;
+  if (st == SS_OK && hipEventSynchronize(b) != hipSuccess) st = SS_ERR_HIP;
+  float t = 0.0f;
+  if (st == SS_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) st = SS_ERR_HIP;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = static_cast<double>(t) / repeats;
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ss_status ss_plan_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uint32_t pair_capacity,
+                                  size_t* bytes) {
+  if (bytes == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  size_t best = 0;
+  ss_options base{};
+  base.struct_size = sizeof(ss_options);
+  for (const Candidate& c : kCandidates) {
+    const ss_options o = with(base, c);
+    size_t b = 0;
+    const ss_status st = ss_batch_workspace_bytes(frames, n_frames, pair_capacity, &o, &b);
+    if (st != SS_OK) return st;
+    if (b > best) best = b;
+  }
+  *bytes = best;
+  return SS_OK;
+}
+
+ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream) {
+  if (plan == nullptr || desc == nullptr || desc->struct_size < sizeof(ss_plan_desc)) return SS_ERR_INVALID_ARGUMENT;
+  if (desc->frames == nullptr || desc->n_frames == 0) return SS_ERR_INVALID_ARGUMENT;
+  ss_plan* p = new (std::nothrow) ss_plan;
+  if (p == nullptr) return SS_ERR_HIP;
+  p->frames.assign(desc->frames, desc->frames + desc->n_frames);
+  p->out = desc->out;
+  p->workspace = desc->workspace;
+  p->workspace_bytes = desc->workspace_bytes;
+  p->options = desc->options;
+  p->options.struct_size = sizeof(ss_options);
+  p->options.timer = nullptr;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // validate the starting configuration without launching anything
+  size_t need = 0;
+  ss_status st = ss_batch_workspace_bytes(p->frames.data(), desc->n_frames, p->out.pair_capacity, &p->options,
+                                          &need);
+  if (st == SS_OK && desc->workspace_bytes < need) st = SS_ERR_WORKSPACE;
+  if (st == SS_OK && desc->autotune) {
+    const uint32_t repeats = desc->tune_repeats ? desc->tune_repeats : 5;
+    double best = 1e30;
+    ss_options chosen = p->options;
+    for (const Candidate& c : kCandidates) {
+      const ss_options o = with(p->options, c);
+      size_t b = 0;
+      if (ss_batch_workspace_bytes(p->frames.data(), desc->n_frames, p->out.pair_capacity, &o, &b) != SS_OK ||
+          b > desc->workspace_bytes)
+        continue;
+      double ms = 0.0;
+      st = time_candidate(p, o, repeats, s, &ms);
+      if (st != SS_OK) break;
+      p->candidate_ms.push_back(ms);
+      if (ms < best) {
+        best = ms;
+        chosen = o;
+      }
+    }
+    p->options = chosen;
+  }
+  if (st == SS_OK && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    st = SS_ERR_HIP;
+  if (st == SS_OK && hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    st = SS_ERR_HIP;
+  if (st == SS_OK) {
+    const ss_status launched = ss_sort_batch(p->frames.data(), desc->n_frames, &p->out, p->workspace,
+                                             p->workspace_bytes, p->capture_stream, &p->options);
+    const hipError_t ended = hipStreamEndCapture(p->capture_stream, &p->graph);
+    if (launched != SS_OK) st = launched;
+    else if (ended != hipSuccess) st = SS_ERR_HIP;
+  }
+  if (st == SS_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) st = SS_ERR_HIP;
+  if (st != SS_OK) {
+    destroy(p);
+    return st;
+  }
+  *plan = p;
+  return SS_OK;
+}
+
+ss_status ss_plan_launch(ss_plan* plan, void* stream) {
+  if (plan == nullptr || plan->exec == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  return hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK : SS_ERR_HIP;
+}
+
+ss_status ss_plan_config(const ss_plan* plan, ss_options* chosen, double* candidate_ms, uint32_t* n) {
+  if (plan == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  if (chosen) *chosen = plan->options;
+  if (n != nullptr) {
+    const uint32_t have = static_cast<uint32_t>(plan->candidate_ms.size());
+    const uint32_t k = candidate_ms ? (*n < have ? *n : have) : 0;
+    for (uint32_t i = 0; i < k; ++i) candidate_ms[i] = plan->candidate_ms[i];
+    *n = have;
+  }
+  return SS_OK;
+}
+
+void ss_plan_destroy(ss_plan* plan) { destroy(plan); }
+
+}  // extern "C"

@@ -118,3 +118,47 @@ def test_full_64_frame_batch_sampled():
         v = vals[seg]
         cnt_g, _ = oracle.count(w, h, rec)
         assert np.array_equal(np.bincount(v, minlength=len(rec))[:len(rec)], cnt_g)
+
+
+def test_plan_graph_replays_match_eager():
+    """A captured plan replayed several times, with eager work and host
+    synchronisations between replays, equals the eager result every time."""
+    frames = synth.make_batch(6, seed=91, n_range=(10_000, 40_000))
+    capacity = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)
+    shapes = [(w, h, len(r)) for (w, h, r) in frames]
+    recs = [ss.records_to_device(r) for (_, _, r) in frames]
+    eager = ss.BatchSorter(shapes, capacity)
+    eager(recs)
+    st, m = eager.result()
+    assert st == 0
+    ref = (u64(eager.keys)[:m].copy(), u32(eager.values)[:m].copy(), u32(eager.tile_ranges).copy())
+    sorter = ss.BatchSorter(shapes, capacity, plan_workspace=True)
+    plan = ss.Plan(sorter, recs, autotune=True, tune_repeats=2)
+    cfg = plan.config()
+    assert len(cfg["candidate_ms"]) >= 5 and cfg["radix_bits"] in (4, 6, 8)
+    for rep in range(4):
+        sorter.keys.fill_(-1)
+        sorter.values.fill_(-1)
+        torch.cuda.synchronize()
+        plan.launch()
+        _ = (torch.arange(1000, device="cuda") * 3).sum().item()   # eager work between replays
+        st, m2 = sorter.result()
+        assert st == 0 and m2 == m, rep
+        assert np.array_equal(u64(sorter.keys)[:m], ref[0]), rep
+        assert np.array_equal(u32(sorter.values)[:m], ref[1]), rep
+        assert np.array_equal(u32(sorter.tile_ranges), ref[2]), rep
+    # new record contents at the same addresses are picked up by a replay
+    frames2 = synth.make_batch(6, seed=91, n_range=(10_000, 40_000))
+    for r in frames2:
+        r[2]["depth"] = r[2]["depth"][::-1].copy()
+    cap2 = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames2)
+    assert cap2 == capacity
+    for d, (_, _, r) in zip(recs, frames2):
+        d.copy_(ss.records_to_device(r))
+    plan.launch()
+    st, m3 = sorter.result()
+    assert st == 0
+    ref2 = oracle.sort_batch(frames2)
+    assert np.array_equal(u64(sorter.keys)[:m3], ref2.keys)
+    assert np.array_equal(u32(sorter.values)[:m3], ref2.values)
+    plan.close()

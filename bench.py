@@ -46,7 +46,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="fullhd-1m", choices=sorted(synth.FRAME_WORKLOADS) + ["batch-64"])
+    p.add_argument("--workload", default="fullhd-1m",
+                   choices=sorted(synth.FRAME_WORKLOADS) + ["batch-64", "serve"])
+    p.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate (serve)")
+    p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
+    p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
@@ -210,16 +214,95 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args):
+    """Poisson request streams over a pool of device-resident frames drawn as
+    in the batch workload: continuous batching against one request at a time."""
+    import threading
+    import torch
+    import paper_2511_16298_amd as ss
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pool = synth.make_batch(64, seed=synth.SEED_BASE + 4)
+    recs = [ss.records_to_device(r, dev) for (_, _, r) in pool]
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    arena = int(args.arena_gib * (1 << 30))
+    results = {}
+    for mode, (frames, streams) in (("batched", (64, 2)), ("one_at_a_time", (1, 1))):
+        srv = ss.Server(arena, max_batch_frames=frames, n_streams=streams, device=dev)
+        for rate in rates:
+            seed = synth.SEED_BASE + 4 + int(rate)
+            arr = synth.poisson_arrivals(rate, args.serve_seconds, seed)
+            picks = synth.uniform_int(synth.stream_key(seed, 7), len(arr), len(pool))
+            tickets = []
+            lock = threading.Condition()
+            got = []
+
+            done_submitting = [False]
+
+            def collect():
+                i = 0
+                while True:
+                    with lock:
+                        while i >= len(tickets) and not done_submitting[0]:
+                            lock.wait(0.01)
+                        if i >= len(tickets):
+                            return
+                        t = tickets[i]
+                    r = srv.wait(t)
+                    got.append((r.status, r.num_pairs, r.submit_us, r.start_us, r.done_us, r.round_frames))
+                    srv.release(t)
+                    i += 1
+            th = threading.Thread(target=collect)
+            th.start()
+            t0 = time.perf_counter()
+            for a, k in zip(arr, picks):
+                delay = t0 + a - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                w, h, _ = pool[int(k)]
+                t = srv.submit(recs[int(k)], w, h)
+                with lock:
+                    tickets.append(t)
+                    lock.notify()
+            with lock:
+                done_submitting[0] = True
+                lock.notify()
+            th.join()
+            g = np.array([x[:5] for x in got], dtype=np.float64)
+            ok = g[:, 0] == 0
+            lat = (g[:, 4] - g[:, 2]) / 1e3   # ms
+            keep = (g[:, 2] - g[:, 2].min()) > 1e6   # skip the first second of arrivals
+            span = (g[:, 4].max() - g[:, 2].min()) / 1e6
+            results[f"{mode}@{int(rate)}"] = {
+                "requests": len(got), "ok": int(ok.sum()), "pairs": int(g[ok, 1].sum()),
+                "pairs_per_s": float(g[ok, 1].sum() / span), "p50_ms": pct(lat[keep], 50),
+                "p99_ms": pct(lat[keep], 99), "mean_round_frames": float(np.mean([x[5] for x in got])),
+                "offered_pairs_per_s": float(g[ok, 1].sum() / args.serve_seconds)}
+            print(f"# {mode} @ {rate:g}/s: {results[f'{mode}@{int(rate)}']}", file=sys.stderr, flush=True)
+        srv.close()
+    line = {"metric": "served frame-sort requests: pairs/s and p50/p99 request latency",
+            "value": results[f"batched@{int(rates[-1])}"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+            "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"serve: Poisson arrivals {args.serve_rates}/s for {args.serve_seconds:g} s "
+                                   f"each, frames drawn from a pool of 64 device-resident frames of the batch "
+                                   f"distribution, HBM budget {args.arena_gib:g} GiB",
+                       "parallelism": "single GPU"},
+            "runs": results}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
-    if args.workload == "batch-64":
+    if args.workload in ("batch-64", "serve"):
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
-        bench_batch(args)
+        (bench_batch if args.workload == "batch-64" else bench_serve)(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "

@@ -174,6 +174,15 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
 
+/* Batched sizing (steps a1-a2 for many frames): the pair count of every
+ * frame, written to d_frame_pairs[n_frames] (saturated at 2^32 - 1), their
+ * sum to *d_num_pairs, and SS_OK / SS_ERR_OVERFLOW / SS_ERR_INVALID_INPUT to
+ * *d_status.  Nothing else is written. */
+ss_status ss_batch_count_workspace_bytes(const ss_frame* frames, uint32_t n_frames, size_t* bytes);
+ss_status ss_batch_count_pairs(const ss_frame* frames, uint32_t n_frames, uint32_t* d_frame_pairs,
+                               uint32_t* d_num_pairs, uint32_t* d_status, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
 /* A plan: one batch shape (frame sizes, record and output pointers, the
  * workspace) with the batched pipeline captured once into a HIP graph and
  * replayed by ss_plan_launch.  Inputs may change between launches; their
@@ -204,6 +213,55 @@ ss_status ss_plan_launch(ss_plan* plan, void* stream);
  * of each candidate tried (ms, in the order they were tried; up to n). */
 ss_status ss_plan_config(const ss_plan* plan, ss_options* chosen, double* candidate_ms, uint32_t* n);
 void ss_plan_destroy(ss_plan* plan);
+
+/* Serving.  Frame-sort requests arrive over time (ss_server_submit from any
+ * host thread).  A scheduler thread owned by the server sizes the waiting
+ * requests with one batched count, admits the longest FIFO prefix whose
+ * round (workspace + outputs) fits the caller's arena now, and launches it
+ * as one segmented sort (ss_sort_batch) on one of n_streams streams, so a
+ * round can run while the next is being sized and launched (continuous
+ * batching).  A request that could not fit even an empty arena completes
+ * with SS_ERR_BUDGET; others wait for space.  Outputs stay in the arena until
+ * ss_server_release; workspace is freed when the round completes.  With
+ * max_batch_frames = 1 and n_streams = 1 the server is a one-request-at-a-
+ * time plain path.  The records of a request must stay valid and unchanged
+ * until it completes.  Results are bit-identical to ss_sort_frame on the
+ * frame alone (after removing the round offsets below). */
+typedef struct ss_server ss_server;
+typedef struct ss_server_desc {
+  uint32_t struct_size;       /* sizeof(ss_server_desc) */
+  uint32_t max_batch_frames;  /* frames per round, 1 .. SS_MAX_BATCH_FRAMES */
+  uint32_t n_streams;         /* rounds in flight at once, 1 .. 8 */
+  uint32_t reserved;          /* 0 */
+  ss_options options;         /* pass configuration of every round (timer ignored) */
+} ss_server_desc;
+
+typedef struct ss_result {
+  ss_status status;
+  uint32_t num_pairs;           /* M of this frame */
+  const uint64_t* keys;         /* device [M], in the arena; tile part = tile_base + t */
+  const uint32_t* values;       /* device [M]: Gaussian indices of the frame */
+  const uint32_t* tile_ranges;  /* device [2 T]: pair indices of the round; subtract pair_base */
+  uint32_t tile_base;           /* first global tile id of the frame in its round */
+  uint32_t pair_base;           /* first pair of the frame in its round */
+  uint32_t round_frames;        /* frames sorted together with this one */
+  uint32_t reserved;
+  double submit_us, start_us, done_us;  /* host steady clock: submitted, launched, seen complete */
+} ss_result;
+
+typedef struct ss_server_counters {
+  uint64_t rounds, admitted, completed, rejected, pending, arena_used;
+  double mean_round_frames;
+} ss_server_counters;
+
+ss_status ss_server_create(ss_server** server, void* d_arena, size_t arena_bytes, const ss_server_desc* desc);
+ss_status ss_server_submit(ss_server* server, const ss_frame* frame, uint64_t* ticket);
+/* Blocks until the request has completed; out stays valid until release. */
+ss_status ss_server_wait(ss_server* server, uint64_t ticket, ss_result* out);
+ss_status ss_server_release(ss_server* server, uint64_t ticket);
+ss_status ss_server_stats(ss_server* server, ss_server_counters* out);
+/* Drains every submitted request, then stops the scheduler. */
+void ss_server_destroy(ss_server* server);
 
 /* Step a4 alone on caller data (the paper's random key-value sort benchmark,
  * Evaluation, "Datasets"): stable sort of n pairs by key bits [0, key_bits);

@@ -17,7 +17,7 @@ from . import _abi
 from ._abi import (SS_ALGO_AUTO, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
-__all__ = ["FrameSorter", "BatchSorter", "Plan", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
+__all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
            "SS_ALGO_DIRECT"]
 
@@ -263,6 +263,67 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             _abi.ss_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """``ss_server_*``: continuous-batching frame-sort service over a device
+    arena (a torch uint8 tensor owned by this object)."""
+
+    def __init__(self, arena_bytes: int, max_batch_frames: int = 64, n_streams: int = 2, device="cuda",
+                 radix_bits: int = 0, items_per_thread: int = 0, workgroup_size: int = 0):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        opts = make_options(radix_bits, items_per_thread, workgroup_size=workgroup_size)
+        st, h = _abi.ss_server_create(self.arena.data_ptr(), int(arena_bytes), max_batch_frames, n_streams, opts)
+        check(st, "ss_server_create")
+        self.handle = h
+
+    def submit(self, records, width: int, height: int) -> int:
+        st, t = _abi.ss_server_submit(self.handle, _frame(records, width, height))
+        check(st, "ss_server_submit")
+        return t
+
+    def wait(self, ticket: int):
+        st, r = _abi.ss_server_wait(self.handle, ticket)
+        check(st, "ss_server_wait")
+        return r
+
+    def release(self, ticket: int):
+        check(_abi.ss_server_release(self.handle, ticket), "ss_server_release")
+
+    def stats(self):
+        st, c = _abi.ss_server_stats(self.handle)
+        check(st, "ss_server_stats")
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
+    def result_arrays(self, r, num_tiles: int):
+        """Host copies of a completed result: keys with the frame's own tile
+        ids, values, and frame-local ranges (the device arrays live inside
+        the arena, so they are slices of it)."""
+        import numpy as np
+        base = self.arena.data_ptr()
+        m = int(r.num_pairs)
+
+        def grab(ptr, nbytes):
+            off = int(ptr) - base
+            return self.arena[off:off + nbytes].cpu().numpy()
+        k = grab(r.keys, 8 * m).view(np.uint64).copy()
+        v = grab(r.values, 4 * m).view(np.uint32).copy()
+        rg = grab(r.tile_ranges, 8 * num_tiles).view(np.uint32).reshape(num_tiles, 2).copy()
+        k -= np.uint64(int(r.tile_base)) << np.uint64(32)
+        rg -= np.uint32(int(r.pair_base))
+        return k, v, rg
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _abi.ss_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -97,6 +97,24 @@ _U32 = ctypes.c_uint32
 _SZ = ctypes.c_size_t
 
 
+class ss_server_desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_batch_frames", ctypes.c_uint32),
+                ("n_streams", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("options", ss_options)]
+
+
+class ss_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("num_pairs", ctypes.c_uint32), ("keys", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("tile_ranges", ctypes.c_void_p), ("tile_base", ctypes.c_uint32),
+                ("pair_base", ctypes.c_uint32), ("round_frames", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class ss_server_counters(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64), ("arena_used", ctypes.c_uint64),
+                ("mean_round_frames", ctypes.c_double)]
+
+
 class ss_plan_desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("n_frames", ctypes.c_uint32),
                 ("frames", ctypes.c_void_p), ("out", ss_batch_out), ("workspace", ctypes.c_void_p),
@@ -122,6 +140,14 @@ _SIGNATURES = {
     "ss_plan_config": ([_P, ctypes.POINTER(ss_options), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
                        ctypes.c_int),
     "ss_plan_destroy": ([_P], None),
+    "ss_batch_count_workspace_bytes": ([ctypes.POINTER(ss_frame), _U32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ss_batch_count_pairs": ([ctypes.POINTER(ss_frame), _U32, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "ss_server_create": ([ctypes.POINTER(_P), _P, _SZ, ctypes.POINTER(ss_server_desc)], ctypes.c_int),
+    "ss_server_submit": ([_P, ctypes.POINTER(ss_frame), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ss_server_wait": ([_P, ctypes.c_uint64, ctypes.POINTER(ss_result)], ctypes.c_int),
+    "ss_server_release": ([_P, ctypes.c_uint64], ctypes.c_int),
+    "ss_server_stats": ([_P, ctypes.POINTER(ss_server_counters)], ctypes.c_int),
+    "ss_server_destroy": ([_P], None),
     "ss_sort_pairs_workspace_bytes": ([_U32, _U32, ctypes.POINTER(ss_options), ctypes.POINTER(_SZ)],
                                       ctypes.c_int),
     "ss_sort_pairs": ([_P, _P, _U32, _U32, _P, _P, _P, _SZ, _P, ctypes.POINTER(ss_options)],
@@ -259,6 +285,57 @@ def ss_plan_config(plan, max_candidates: int = 16):
 
 def ss_plan_destroy(plan) -> None:
     lib().ss_plan_destroy(plan)
+
+
+def ss_batch_count_workspace_bytes(frames):
+    arr = _frames_array(frames)
+    b = _SZ()
+    st = lib().ss_batch_count_workspace_bytes(arr, len(frames), ctypes.byref(b))
+    return st, b.value
+
+
+def ss_batch_count_pairs(frames, d_frame_pairs, d_num_pairs, d_status, workspace, workspace_bytes, stream):
+    arr = _frames_array(frames)
+    return lib().ss_batch_count_pairs(arr, len(frames), d_frame_pairs, d_num_pairs, d_status, workspace,
+                                      workspace_bytes, stream)
+
+
+def ss_server_create(arena, arena_bytes, max_batch_frames, n_streams, options=None):
+    d = ss_server_desc()
+    d.struct_size = ctypes.sizeof(ss_server_desc)
+    d.max_batch_frames = max_batch_frames
+    d.n_streams = n_streams
+    d.reserved = 0
+    d.options = options if options is not None else make_options()
+    h = _P()
+    st = lib().ss_server_create(ctypes.byref(h), arena, arena_bytes, ctypes.byref(d))
+    return st, h.value
+
+
+def ss_server_submit(server, frame: ss_frame):
+    t = ctypes.c_uint64()
+    st = lib().ss_server_submit(server, ctypes.byref(frame), ctypes.byref(t))
+    return st, t.value
+
+
+def ss_server_wait(server, ticket: int):
+    r = ss_result()
+    st = lib().ss_server_wait(server, ticket, ctypes.byref(r))
+    return st, r
+
+
+def ss_server_release(server, ticket: int) -> int:
+    return lib().ss_server_release(server, ticket)
+
+
+def ss_server_stats(server):
+    c = ss_server_counters()
+    st = lib().ss_server_stats(server, ctypes.byref(c))
+    return st, c
+
+
+def ss_server_destroy(server) -> None:
+    lib().ss_server_destroy(server)
 
 
 def ss_sort_pairs_workspace_bytes(n: int, key_bits: int, options=None):

@@ -650,6 +650,70 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
   return run_depth_first(L, lay, o, io, workspace, s);
 }
 
+// Batched sizing: per-frame pair counts only.
+struct CountLayout {
+  uint32_t ck_blocks = 0;
+  size_t counters = 0, scalars = 0, bad = 0, totals = 0, block_total = 0, block_frame = 0, clear_end = 0,
+         table = 0, total = 0;
+};
+
+static CountLayout make_count_layout(uint64_t n, uint32_t n_frames) {
+  CountLayout L;
+  L.ck_blocks = static_cast<uint32_t>((n + kCountKeysTile - 1) / kCountKeysTile);
+  size_t off = 0;
+  L.counters = off;    off = align_up(off + 64 * sizeof(uint32_t));
+  L.scalars = off;     off = align_up(off + 4 * sizeof(uint32_t));
+  L.bad = off;         off = align_up(off + sizeof(uint32_t));
+  L.totals = off;      off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
+  L.clear_end = off;
+  L.block_total = off; off = align_up(off + static_cast<size_t>(L.ck_blocks) * sizeof(uint64_t));
+  L.block_frame = off; off = align_up(off + static_cast<size_t>(L.ck_blocks) * sizeof(uint32_t));
+  L.table = off;       off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
+  L.total = off;
+  return L;
+}
+
+ss_status ss_batch_count_workspace_bytes(const ss_frame* frames, uint32_t n_frames, size_t* bytes) {
+  if (bytes == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  BatchShape b;
+  SS_TRY(batch_shape(frames, n_frames, &b));
+  *bytes = make_count_layout(b.n, n_frames).total;
+  return SS_OK;
+}
+
+ss_status ss_batch_count_pairs(const ss_frame* frames, uint32_t n_frames, uint32_t* d_frame_pairs,
+                               uint32_t* d_num_pairs, uint32_t* d_status, void* workspace, size_t workspace_bytes,
+                               void* stream) {
+  BatchShape b;
+  SS_TRY(batch_shape(frames, n_frames, &b));
+  if (d_frame_pairs == nullptr || d_num_pairs == nullptr || d_status == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  const CountLayout lay = make_count_layout(b.n, n_frames);
+  if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total) return SS_ERR_WORKSPACE;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Launcher L(s, nullptr);
+  FrameInfo* table = at<FrameInfo>(workspace, lay.table);
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, d_status, s); }));
+  for (uint32_t first = 0; first < n_frames; first += kArgFrames) {
+    TableChunk c{};
+    c.first = first;
+    c.count = n_frames - first < kArgFrames ? n_frames - first : kArgFrames;
+    for (uint32_t i = 0; i < c.count; ++i) c.f[i] = b.table[first + i];
+    SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_put_table(c, table, s); }));
+  }
+  CountKeysArgs ck{};
+  ck.table = table;
+  ck.n_frames = n_frames;
+  ck.n = static_cast<uint32_t>(b.n);
+  ck.totals = at<unsigned long long>(workspace, lay.totals);
+  ck.block_total = at<unsigned long long>(workspace, lay.block_total);
+  ck.block_frame = at<uint32_t>(workspace, lay.block_frame);
+  ck.bad = at<uint32_t>(workspace, lay.bad);
+  SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
+  DepthBasesArgs db{nullptr, nullptr, ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, n_frames,
+                    0xFFFFFFFFu, d_num_pairs, d_status, d_frame_pairs, nullptr};
+  return L.run(SS_KERNEL_DIGIT_BASES, [&] { return launch_depth_bases(db, s); });
+}
+
 ss_status ss_sort_pairs_workspace_bytes(uint32_t n, uint32_t key_bits, const ss_options* options,
                                         size_t* bytes) {
   if (bytes == nullptr || key_bits < 1 || key_bits > 64 || n > SS_MAX_PAIR_CAPACITY)

@@ -93,12 +93,14 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
     }
     if (cnt != 0 && dbits - 1u >= 0x7F7FFFFFu) bad = true;
     const uint32_t key = cnt != 0 ? dbits : 0xFFFFFFFFu;
-    a.rect[g] = rect;
-    a.key[g] = key;
-    a.val[g] = g;
-    if (a.tiles_touched) a.tiles_touched[g] = cnt;
+    if (a.rect != nullptr) {  // NULL: counts only (batched sizing)
+      a.rect[g] = rect;
+      a.key[g] = key;
+      a.val[g] = g;
 #pragma unroll
-    for (uint32_t p = 0; p < 4; ++p) atomicAdd(&s_hist[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+      for (uint32_t p = 0; p < 4; ++p) atomicAdd(&s_hist[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+    }
+    if (a.tiles_touched) a.tiles_touched[g] = cnt;
     if (!one_frame && cnt) atomicAdd(&s_fm[f], static_cast<unsigned long long>(cnt));
     tsum += cnt;
   }
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
   if (!one_frame)
     for (uint32_t f = tid; f < a.n_frames; f += kCountKeysThreads)
       if (s_fm[f]) atomicAdd(&a.totals[1 + f], s_fm[f]);
+  if (a.rect == nullptr) return;
   uint32_t* gh = a.hist + static_cast<size_t>(blockIdx.x % kHistCopies) * 4 * 256;
   for (uint32_t i = tid; i < 4 * 256; i += kCountKeysThreads) {
     const uint32_t v = s_hist[i];
@@ -129,6 +132,7 @@ __global__ __launch_bounds__(256) void k_depth_bases(DepthBasesArgs a) {
   __shared__ unsigned long long s_tmp64[4];
   const uint32_t d = threadIdx.x;
   if (blockIdx.x < 4) {
+    if (a.bases == nullptr) return;  // counts only
     const uint32_t p = blockIdx.x;
     uint32_t tot = 0;
 #pragma unroll

@@ -171,3 +171,21 @@ def test_algorithm_option_validated():
     a = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=1))
     b = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=2))
     assert a[0] == b[0] == _abi.SS_OK and a[1] != b[1]
+
+
+def test_server_and_count_argument_errors():
+    # rejected before any HIP call: no GPU needed
+    assert _abi.ss_server_create(None, 1 << 20, 4, 1)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20 | 8, 1 << 20, 4, 1)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20, 1 << 20, 0, 1)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20, 1 << 20, 257, 1)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20, 1 << 20, 4, 0)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20, 1 << 20, 4, 9)[0] == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_server_create(1 << 20, 1 << 20, 4, 1, _abi.make_options(5))[0] == _abi.SS_ERR_UNSUPPORTED
+    fr = [frame(640, 360, n=100, ptr=1 << 12)]
+    st, need = _abi.ss_batch_count_workspace_bytes(fr)
+    assert st == _abi.SS_OK and need > 0
+    assert _abi.ss_batch_count_pairs(fr, None, 1 << 10, 1 << 11, 1 << 20, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
+    assert _abi.ss_batch_count_pairs(fr, 1 << 9, 1 << 10, 1 << 11, 1 << 20, need - 1, None) == _abi.SS_ERR_WORKSPACE
+    st, need = _abi.ss_plan_workspace_bytes(fr, 1000)
+    assert st == _abi.SS_OK and need > 0

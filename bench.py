@@ -96,28 +96,42 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     with open(os.path.join(PROFILES, f"kernel_stats_{workload}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
+    def short_name(name):
+        return name.replace("ss::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
     def per_kernel(kind):
         rows = _rows(os.path.join(d, kind, "*counter_collection.csv"))
-        copy = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
-        passes = [float(r["Counter_Value"]) for r in rows if PASS_KERNEL in r["Kernel_Name"]]
-        return copy, passes
-    fc, fp = per_kernel("fetch")
-    wc, wp = per_kernel("write")
+        by = {}
+        for r in rows:
+            by.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        copy = [v for k, vs in by.items() if k.startswith("k_copy") for v in vs]
+        return copy, by
+    fc, fby = per_kernel("fetch")
+    wc, wby = per_kernel("write")
     kib = copy_mib * 1024.0
     f_scale, w_scale = kib / (sum(fc) / len(fc)), kib / (sum(wc) / len(wc))
+    # the measured kernel: the 64-bit-key (tile) sort pass
+    tile = [k for k in fby if k.startswith(PASS_KERNEL) and "unsigned long" in k]
+    assert len(tile) == 1, tile
+    fp, wp = fby[tile[0]], wby[tile[0]]
     fetch = sum(fp) / len(fp) * f_scale * 1024.0
     write = sum(wp) / len(wp) * w_scale * 1024.0
-    rec = {"kernel": PASS_KERNEL, "workload": workload, "source_sha256_16": source_hash(),
+    others = {k: {"dispatches": len(fby[k]),
+                  "fetch_bytes_per_launch": round(sum(fby[k]) / len(fby[k]) * f_scale * 1024.0),
+                  "write_bytes_per_launch": round(sum(wby[k]) / len(wby[k]) * w_scale * 1024.0)}
+              for k in sorted(fby) if k in wby and not k.startswith("at::") and "rocclr" not in k}
+    rec = {"kernel": tile[0], "workload": workload, "source_sha256_16": source_hash(),
            "copy_calibration_mib": copy_mib, "fetch_scale": f_scale, "write_scale": w_scale,
            "dispatches": len(fp), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-           "traffic_bytes_per_launch": fetch + write,
+           "traffic_bytes_per_launch": fetch + write, "per_kernel": others,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py "
                         f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py "
                         f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}"]}
     with open(os.path.join(PROFILES, f"{PASS_KERNEL}_{workload}_traffic.txt"), "w") as f:
-        f.write("# HBM traffic of one sort pass (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
-                "# the scales make a plain copy of copy_calibration_mib MiB read and write exactly that)\n")
+        f.write("# HBM traffic of one tile sort pass (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
+                "# the scales make a plain copy of copy_calibration_mib MiB read and write exactly that),\n"
+                "# and the same per launch for every kernel of the step\n")
         f.write(json.dumps(rec, indent=1) + "\n")
     print(json.dumps(rec))
 
@@ -377,7 +391,8 @@ def main():
                        ("expand", _abi.SS_KERNEL_EXPAND), ("sort_pass", _abi.SS_KERNEL_SORT_PASS),
                        ("ranges", _abi.SS_KERNEL_RANGES)):
         ms, n = timer.read(kind)
-        kern[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "us_per_step": 1e3 * ms / K}
+        if n:
+            kern[name] = {"launches": n, "avg_us": 1e3 * ms / n, "us_per_step": 1e3 * ms / K}
     timer.close()
     pass_us = kern["sort_pass"]["avg_us"]
     pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair

@@ -287,7 +287,8 @@ typedef enum ss_kernel_kind {
   SS_KERNEL_RANGES = 3,     /* a5 */
   SS_KERNEL_COPY = 4,       /* ss_copy_bytes */
   SS_KERNEL_HIST = 5,       /* digit histograms of caller keys (ss_sort_pairs) */
-  SS_KERNEL_DIGIT_BASES = 6, /* exclusive prefix of the digit totals */
+  SS_KERNEL_DIGIT_BASES = 6, /* pair totals of ss_batch_count_pairs (sort passes derive
+                               their digit bases from the histograms) */
   SS_KERNEL_DEPTH_PASS = 7, /* depth-first: one pass of the Gaussian depth sort */
   SS_KERNEL_EXPAND = 8,     /* depth-first: pairs in depth order */
   SS_KERNEL_KINDS = 9

@@ -121,18 +121,20 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
 // Depth-first path (one frame or a batch).  Zeroed part: counters, scalars,
 // bad flag, totals, count-only scan look-back, expand look-back, histograms
 // and look-back words of the depth and tile passes; then the frame table,
-// digit bases, rectangles, the Gaussian sort buffers and the alternate pair
-// buffers.
+// tile digit bases, rectangles, the Gaussian sort buffers and the alternate
+// pair buffers.
 // ---------------------------------------------------------------------------
 struct PassCfg {
   uint32_t items = 16, threads = 512;
   uint32_t tile() const { return items * threads; }
 };
 
-// Depth-sort passes run over N Gaussians (8-byte items): smaller tiles keep
-// the chip busy when N is small.
+// Depth-sort passes run over N Gaussians (8-byte items).  Their time is
+// set by per-workgroup latency (ticket, look-back round trips) more than by
+// bandwidth, so fewer, larger workgroups win; below 2^21 Gaussians a
+// half-size tile keeps more CUs busy.
 PassCfg depth_cfg(uint32_t n) {
-  if (n < (1u << 21)) return PassCfg{8, 256};
+  if (n < (1u << 21)) return PassCfg{8, 512};
   return PassCfg{16, 512};
 }
 
@@ -142,7 +144,7 @@ struct DfLayout {
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
   size_t counters = 0, scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
-         lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_d = 0, bases_t = 0, rect = 0, key = 0, val = 0,
+         lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
          key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, total = 0;
 };
 
@@ -159,7 +161,7 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.tcfg = PassCfg{o.items, o.threads};
   L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
   L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile();
-  L.eblocks = (n + kExpandTile - 1) / kExpandTile;
+  L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
   L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
   size_t off = 0;
   L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
@@ -177,7 +179,6 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses) * L.tblocks * L.tbins * sizeof(uint32_t));
   L.clear_end = off;
   L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
-  L.bases_d = off;   off = align_up(off + 4 * 256 * sizeof(uint32_t));
   L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
   L.rect = off;      off = align_up(off + static_cast<size_t>(n) * sizeof(uint64_t));
   L.key = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
@@ -255,7 +256,9 @@ struct PassChain {
   const uint32_t* num_pairs;  // device M or NULL (then n_fixed)
   uint32_t n_fixed;
   uint32_t* status;
-  const uint32_t* bases;      // [npasses][bins]
+  const uint32_t* bases;      // 64-bit keys: [npasses][bins] digit bases
+  const uint32_t* hist;       // 32-bit keys: pass p's totals at hist + p * bins, copies hist_stride apart
+  uint32_t hist_stride;
   uint32_t* tickets;          // [npasses]
   uint32_t* lookback;         // [npasses][nblocks][bins]
 };
@@ -274,7 +277,9 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.n_fixed = c.n_fixed;
       a.status = c.status;
       a.shift = c.shift0 + p * c.radix_bits;
-      a.bases = c.bases + static_cast<size_t>(p) * bins;
+      a.bases = c.bases ? c.bases + static_cast<size_t>(p) * bins : nullptr;
+      a.hist = c.hist ? c.hist + static_cast<size_t>(p) * bins : nullptr;
+      a.hist_stride = c.hist_stride;
       a.ticket = c.tickets + p;
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       if (launch_pass(a, static_cast<int>(c.key_bytes), static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
@@ -304,7 +309,7 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
   bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
 
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, s); }));
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, nullptr, nullptr, s); }));
   CountDupArgs a{};
   a.gaussians = frame->gaussians;
   a.n = frame->num_gaussians;
@@ -339,12 +344,29 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
     vd[p] = bv[(p + 1) % 2];
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
-              kd.data(), vd.data(), d_num_pairs, 0, d_status, bases,
+              kd.data(), vd.data(), d_num_pairs, 0, d_status, bases, nullptr, 0,
               at<uint32_t>(ws, lay.counters) + kCounterPass, at<uint32_t>(ws, lay.pass_lb)};
   SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   return L.run(SS_KERNEL_RANGES, [&] {
     return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
   });
+}
+
+// Zeroes the workspace head and stores the frame table: the first kArgFrames
+// frames ride along with the clear kernel, the rest in further launches.
+ss_status clear_and_upload(Launcher& L, void* ws, size_t clear_bytes, uint32_t* d_status, const FrameInfo* host_table,
+                           uint32_t n_frames, FrameInfo* table, hipStream_t s) {
+  for (uint32_t first = 0; first == 0 || first < n_frames; first += kArgFrames) {
+    TableChunk c{};
+    c.first = first;
+    c.count = n_frames - first < kArgFrames ? n_frames - first : kArgFrames;
+    for (uint32_t i = 0; i < c.count; ++i) c.f[i] = host_table[first + i];
+    if (first == 0)
+      SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, clear_bytes, d_status, &c, table, s); }));
+    else
+      SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_put_table(c, table, s); }));
+  }
+  return SS_OK;
 }
 
 // --------------------------- depth-first path ------------------------------
@@ -370,14 +392,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   uint32_t* counters = at<uint32_t>(ws, lay.counters);
   FrameInfo* table = at<FrameInfo>(ws, lay.table);
 
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, s); }));
-  for (uint32_t first = 0; first < lay.n_frames; first += kArgFrames) {
-    TableChunk c{};
-    c.first = first;
-    c.count = lay.n_frames - first < kArgFrames ? lay.n_frames - first : kArgFrames;
-    for (uint32_t i = 0; i < c.count; ++i) c.f[i] = io.host_table[first + i];
-    SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_put_table(c, table, s); }));
-  }
+  SS_TRY(clear_and_upload(L, ws, lay.clear_end, d_status, io.host_table, lay.n_frames, table, s));
   if (io.offsets != nullptr) {
     // the index-order scan exists only for this optional output
     CountDupArgs a{};
@@ -412,10 +427,6 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   ck.block_frame = at<uint32_t>(ws, lay.block_frame);
   ck.bad = at<uint32_t>(ws, lay.bad);
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
-  DepthBasesArgs db{ck.hist, at<uint32_t>(ws, lay.bases_d), ck.totals, ck.block_total, ck.block_frame,
-                    lay.ck_blocks, ck.bad, lay.n_frames, lay.capacity, d_num_pairs, d_status,
-                    io.frame_pairs, io.frame_pair_base};
-  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] { return launch_depth_bases(db, s); }));
 
   // stable sort of the N Gaussians by depth: key -> alt -> key -> alt -> key
   {
@@ -424,7 +435,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     void* kd[4] = {key_alt, key, key_alt, key};
     uint32_t* vd[4] = {val_alt, val, val_alt, val};
     PassChain c{4, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
-                at<uint32_t>(ws, lay.bases_d), counters + kCounterPass, at<uint32_t>(ws, lay.lb_d)};
+                nullptr, ck.hist, 4 * 256, counters + kCounterPass, at<uint32_t>(ws, lay.lb_d)};
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
 
@@ -453,6 +464,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.lookback = at<uint64_t>(ws, lay.expand_lb);
   e.status = d_status;
   e.nblocks = lay.eblocks;
+  e.totals = PairTotalsArgs{ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, lay.n_frames,
+                            lay.capacity, d_num_pairs, d_status, io.frame_pairs, io.frame_pair_base};
   SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
   if (P > 0) {
     uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
@@ -470,7 +483,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       vd[p] = bv[(p + 1) % 2];
     }
     PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                d_status, bases_t, counters + kCounterPass + 4, at<uint32_t>(ws, lay.lb_t)};
+                d_status, bases_t, nullptr, 0, counters + kCounterPass + 4, at<uint32_t>(ws, lay.lb_t)};
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   }
   return L.run(SS_KERNEL_RANGES, [&] {
@@ -574,7 +587,7 @@ ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint3
     return SS_ERR_WORKSPACE;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, nullptr);
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, d_status, s); }));
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, d_status, nullptr, nullptr, s); }));
   CountDupArgs a{};
   a.gaussians = frame->gaussians;
   a.n = frame->num_gaussians;
@@ -692,14 +705,7 @@ ss_status ss_batch_count_pairs(const ss_frame* frames, uint32_t n_frames, uint32
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, nullptr);
   FrameInfo* table = at<FrameInfo>(workspace, lay.table);
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, d_status, s); }));
-  for (uint32_t first = 0; first < n_frames; first += kArgFrames) {
-    TableChunk c{};
-    c.first = first;
-    c.count = n_frames - first < kArgFrames ? n_frames - first : kArgFrames;
-    for (uint32_t i = 0; i < c.count; ++i) c.f[i] = b.table[first + i];
-    SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_put_table(c, table, s); }));
-  }
+  SS_TRY(clear_and_upload(L, workspace, lay.clear_end, d_status, b.table.data(), n_frames, table, s));
   CountKeysArgs ck{};
   ck.table = table;
   ck.n_frames = n_frames;
@@ -709,9 +715,9 @@ ss_status ss_batch_count_pairs(const ss_frame* frames, uint32_t n_frames, uint32
   ck.block_frame = at<uint32_t>(workspace, lay.block_frame);
   ck.bad = at<uint32_t>(workspace, lay.bad);
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
-  DepthBasesArgs db{nullptr, nullptr, ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, n_frames,
+  PairTotalsArgs pt{ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, n_frames,
                     0xFFFFFFFFu, d_num_pairs, d_status, d_frame_pairs, nullptr};
-  return L.run(SS_KERNEL_DIGIT_BASES, [&] { return launch_depth_bases(db, s); });
+  return L.run(SS_KERNEL_DIGIT_BASES, [&] { return launch_pair_totals(pt, s); });
 }
 
 ss_status ss_sort_pairs_workspace_bytes(uint32_t n, uint32_t key_bits, const ss_options* options,
@@ -742,7 +748,7 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   if (n == 0) return SS_OK;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);
-  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, nullptr, s); }));
+  SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, nullptr, nullptr, nullptr, s); }));
   HistArgs h{keys_in, n, lay.npasses, at<uint32_t>(workspace, lay.hist)};
   SS_TRY(L.run(SS_KERNEL_HIST, [&] { return launch_hist(h, static_cast<int>(o.radix_bits), s); }));
   uint32_t* bases = at<uint32_t>(workspace, lay.bases);
@@ -764,7 +770,7 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
     vs[p] = p == 0 ? values_in : vd[p - 1];
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
-              kd.data(), vd.data(), nullptr, n, nullptr, bases,
+              kd.data(), vd.data(), nullptr, n, nullptr, bases, nullptr, 0,
               at<uint32_t>(workspace, lay.counters) + kCounterPass, at<uint32_t>(workspace, lay.pass_lb)};
   return run_chain(L, SS_KERNEL_SORT_PASS, c, s);
 }

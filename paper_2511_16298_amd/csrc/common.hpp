@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "splatsort.h"
+
 namespace ss {
 
 constexpr int kWave = 64;
@@ -83,6 +85,57 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* s_tmp, T& total) {
   __syncthreads();
   total = sum;
   return before + inc - v;
+}
+
+// Decoupled look-back for one digit (one calling thread per digit): adds up
+// the digit's counts in workgroups 0 .. t-1 of `lb` ([workgroup][stride]
+// words, this workgroup's aggregate already published) and publishes this
+// workgroup's inclusive count.  Each round reads the words of
+// kLookbackWindow predecessors at once (independent loads, so one memory
+// latency per round) and consumes them nearest first, up to the first
+// inclusive word; a word not yet published ends the round there.  Returns
+// false after kSpinLimit fruitless rounds, having raised SS_ERR_TIMEOUT in
+// *status (when not NULL).
+constexpr int kLookbackWindow = 8;
+
+__device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_t stride, uint32_t d, uint32_t own,
+                                               uint32_t* status, uint32_t& excl) {
+  excl = 0;
+  if (t == 0) return true;
+  int32_t kb = static_cast<int32_t>(t) - 1;  // nearest predecessor not yet consumed
+  uint32_t spins = 0;
+  while (true) {
+    uint32_t w[kLookbackWindow];
+#pragma unroll
+    for (int j = 0; j < kLookbackWindow; ++j)
+      w[j] = kb - j >= 0 ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbInc32;
+    uint32_t add = 0;
+    int32_t used = 0;
+    bool inc = false, stall = false;
+#pragma unroll
+    for (int j = 0; j < kLookbackWindow; ++j) {
+      if (inc || stall) continue;
+      if ((w[j] & ~kLbMask32) == 0) {
+        stall = true;
+      } else {
+        add += w[j] & kLbMask32;
+        ++used;
+        inc = (w[j] & kLbInc32) != 0;
+      }
+    }
+    excl += add;
+    if (inc) break;
+    kb -= used;
+    if (stall) {
+      if (++spins > kSpinLimit) {
+        if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  st_agent(&lb[static_cast<size_t>(t) * stride + d], kLbInc32 | (excl + own));
+  return true;
 }
 
 }  // namespace ss

@@ -123,51 +123,49 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
   }
 }
 
-// Digit bases of the four depth passes (workgroups 0-3); workgroup 4 sums
-// the count workgroups' totals per frame, then writes num_pairs, status and
-// the per-frame pair counts and first pairs.
-__global__ __launch_bounds__(256) void k_depth_bases(DepthBasesArgs a) {
-  __shared__ uint32_t s_tmp[4];
-  __shared__ unsigned long long s_fm[kMaxFrames];
-  __shared__ unsigned long long s_tmp64[4];
+// Pair totals after the count kernel: per frame, the sum of the one-frame
+// count workgroups' totals plus what multi-frame workgroups added directly;
+// then all pairs, num_pairs, the status (bad depth, over 2^32 pairs, over
+// capacity) and the per-frame pair counts and first pairs.  One workgroup of
+// THREADS >= 256 threads; s_fm holds kMaxFrames values.
+template <int THREADS>
+__device__ __forceinline__ void finish_totals(const PairTotalsArgs& a, unsigned long long* s_fm,
+                                              unsigned long long* s_tmp64, uint32_t* s_tmp) {
   const uint32_t d = threadIdx.x;
-  if (blockIdx.x < 4) {
-    if (a.bases == nullptr) return;  // counts only
-    const uint32_t p = blockIdx.x;
-    uint32_t tot = 0;
-#pragma unroll
-    for (uint32_t c = 0; c < kHistCopies; ++c) tot += a.hist[(static_cast<size_t>(c) * 4 + p) * 256 + d];
-    uint32_t all;
-    const uint32_t ex = block_exclusive_scan<uint32_t, 256>(tot, s_tmp, all);
-    a.bases[p * 256 + d] = ex;
-    return;
-  }
-  for (uint32_t f = d; f < a.n_frames; f += 256) s_fm[f] = a.totals[1 + f];
+  for (uint32_t f = d; f < a.n_frames; f += THREADS) s_fm[f] = a.totals[1 + f];
   __syncthreads();
-  for (uint32_t b = d; b < a.count_blocks; b += 256) {
+  for (uint32_t b = d; b < a.count_blocks; b += THREADS) {
     const unsigned long long t = a.block_total[b];
     if (t) atomicAdd(&s_fm[a.block_frame[b]], t);
   }
   __syncthreads();
   const unsigned long long fm = d < a.n_frames ? s_fm[d] : 0ull;
   unsigned long long m;
-  block_exclusive_scan<unsigned long long, 256>(fm, s_tmp64, m);
+  block_exclusive_scan<unsigned long long, THREADS>(fm, s_tmp64, m);
   if (d == 0) {
     uint32_t st = SS_OK;
     if (*a.bad) st = SS_ERR_INVALID_INPUT;
     else if (m > 0xFFFFFFFFull) st = SS_ERR_OVERFLOW;
     else if (m > a.capacity) st = SS_ERR_CAPACITY;
     *a.num_pairs = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(m);
-    *a.status = st;
+    if (*a.status == SS_OK) *a.status = st;
   }
   if (a.frame_pairs == nullptr) return;
   const uint32_t f32 = fm > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fm);
   uint32_t all;
-  const uint32_t ex = block_exclusive_scan<uint32_t, 256>(f32, s_tmp, all);
+  const uint32_t ex = block_exclusive_scan<uint32_t, THREADS>(f32, s_tmp, all);
   if (d < a.n_frames) {
     a.frame_pairs[d] = f32;
     if (a.frame_pair_base) a.frame_pair_base[d] = ex;
   }
+}
+
+// The totals alone (batched sizing: counts without the sort).
+__global__ __launch_bounds__(256) void k_pair_totals(PairTotalsArgs a) {
+  __shared__ unsigned long long s_fm[kMaxFrames];
+  __shared__ unsigned long long s_tmp64[4];
+  __shared__ uint32_t s_tmp[4];
+  finish_totals<256>(a, s_fm, s_tmp64, s_tmp);
 }
 
 template <typename T, int THREADS>
@@ -219,8 +217,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   __shared__ uint32_t s_tmp[kExpandThreads / kWave];
   __shared__ uint32_t s_ticket, s_first, s_retry, s_timeout;
   __shared__ unsigned long long s_prefix;
+  __shared__ unsigned long long s_fm[kMaxFrames];
 
-  if (*a.status != SS_OK) return;
+  // No status test on entry: workgroup 0 sets the status from the totals
+  // while the others run, and every workgroup must publish its look-back
+  // word.  Writes stay below capacity whatever the status becomes.
   const uint32_t tid = threadIdx.x;
   if (tid == 0) {
     s_ticket = atomicAdd(a.ticket, 1u);
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   }
   if (tid == 0) s_prefix = excl;
   __syncthreads();
+  if (ticket == 0) finish_totals<kExpandThreads>(a.totals, s_fm, s_tmp64, s_tmp);
   if (s_timeout) {
     if (tid == 0) st_agent(const_cast<uint32_t*>(a.status), static_cast<uint32_t>(SS_ERR_TIMEOUT));
     return;
@@ -405,8 +407,8 @@ hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_depth_bases(const DepthBasesArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_depth_bases, dim3(5), dim3(256), 0, s, a);
+hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

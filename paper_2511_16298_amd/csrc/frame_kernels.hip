@@ -28,8 +28,10 @@ __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
   return s > kCountSat ? kCountSat : s;
 }
 
-__global__ void k_clear(uint4* __restrict__ p, size_t n16, uint32_t* __restrict__ extra) {
+__global__ void k_clear(uint4* __restrict__ p, size_t n16, uint32_t* __restrict__ extra, TableChunk c,
+                        FrameInfo* __restrict__ table) {
   if (extra != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *extra = 0;
+  if (blockIdx.x == 0 && threadIdx.x < c.count) table[c.first + threadIdx.x] = c.f[threadIdx.x];
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0, 0, 0, 0);
@@ -340,10 +342,14 @@ uint32_t stream_grid(size_t n16) {
 
 }  // namespace
 
-hipError_t launch_clear(void* p, size_t bytes, uint32_t* extra, hipStream_t s) {
+hipError_t launch_clear(void* p, size_t bytes, uint32_t* extra, const TableChunk* chunk, FrameInfo* table,
+                        hipStream_t s) {
   const size_t n16 = bytes / 16;
-  if (n16 == 0 && extra == nullptr) return hipSuccess;
-  hipLaunchKernelGGL(k_clear, dim3(stream_grid(n16)), dim3(256), 0, s, static_cast<uint4*>(p), n16, extra);
+  if (n16 == 0 && extra == nullptr && (chunk == nullptr || chunk->count == 0)) return hipSuccess;
+  TableChunk c{};
+  if (chunk != nullptr) c = *chunk;
+  hipLaunchKernelGGL(k_clear, dim3(stream_grid(n16)), dim3(256), 0, s, static_cast<uint4*>(p), n16, extra, c,
+                     table);
   return hipGetLastError();
 }
 

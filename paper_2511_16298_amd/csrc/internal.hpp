@@ -41,7 +41,13 @@ struct PassArgs {
   uint32_t n_fixed;
   uint32_t* status;           // device status word or NULL
   uint32_t shift;             // first key bit of this digit
-  const uint32_t* bases;      // [bins] exclusive prefix of this pass's digit totals
+  // Where the digit bases come from: 64-bit-key passes read `bases` ([bins]
+  // exclusive prefix of the digit totals); 32-bit-key passes (the Gaussian
+  // depth sort, one small grid) sum the kHistCopies histogram copies
+  // themselves, copy c at hist + c * hist_stride.
+  const uint32_t* bases;
+  const uint32_t* hist;
+  uint32_t hist_stride;
   uint32_t* ticket;           // zeroed counter
   uint32_t* lookback;         // zeroed [nblocks][bins]
 };
@@ -91,6 +97,22 @@ struct CountKeysArgs {
   uint32_t* bad;            // zeroed flag: a touching Gaussian has a bad depth
 };
 
+// Pair totals: per frame (sum of the count workgroups' totals), all frames,
+// and from them num_pairs and the status word.
+struct PairTotalsArgs {
+  const unsigned long long* totals;       // [1 + n_frames], from multi-frame count workgroups
+  const unsigned long long* block_total;  // [count_blocks]
+  const uint32_t* block_frame;            // [count_blocks]
+  uint32_t count_blocks;
+  const uint32_t* bad;
+  uint32_t n_frames;
+  uint32_t capacity;
+  uint32_t* num_pairs;
+  uint32_t* status;            // set only while it still reads SS_OK
+  uint32_t* frame_pairs;       // optional
+  uint32_t* frame_pair_base;   // optional
+};
+
 struct ExpandArgs {
   const FrameInfo* table;
   uint32_t n_frames;
@@ -106,35 +128,22 @@ struct ExpandArgs {
   uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits]
   uint32_t* ticket;         // zeroed
   uint64_t* lookback;       // zeroed [nblocks]
-  const uint32_t* status;
+  uint32_t* status;
   uint32_t nblocks;
+  PairTotalsArgs totals;    // finished by workgroup 0 (ticket 0)
 };
 
 hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s);
 hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s);
-// Digit bases of the 4 depth passes, and num_pairs / status from the totals.
-struct DepthBasesArgs {
-  const uint32_t* hist;
-  uint32_t* bases;
-  const unsigned long long* totals;
-  const unsigned long long* block_total;
-  const uint32_t* block_frame;
-  uint32_t count_blocks;
-  const uint32_t* bad;
-  uint32_t n_frames;
-  uint32_t capacity;
-  uint32_t* num_pairs;
-  uint32_t* status;
-  uint32_t* frame_pairs;       // optional
-  uint32_t* frame_pair_base;   // optional
-};
-hipError_t launch_depth_bases(const DepthBasesArgs& a, hipStream_t s);
+hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
 constexpr uint32_t kCountKeysTile = 2048;   // Gaussians per count workgroup
 constexpr uint32_t kExpandTile = 2048;      // Gaussians per expand workgroup
 
-// Zeroes `bytes` (a multiple of 16) at p and, if not NULL, the word `extra`.
-hipError_t launch_clear(void* p, size_t bytes, uint32_t* extra, hipStream_t s);
+// Zeroes `bytes` (a multiple of 16) at p and, if not NULL, the word `extra`;
+// with a non-NULL chunk also stores its frames into `table`.
+hipError_t launch_clear(void* p, size_t bytes, uint32_t* extra, const TableChunk* chunk, FrameInfo* table,
+                        hipStream_t s);
 hipError_t launch_count_dup(const CountDupArgs& a, int radix_bits, bool dup, hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys, const uint32_t* num_pairs, const uint32_t* status,
                          uint32_t capacity, uint32_t num_tiles, uint32_t* ranges, hipStream_t s);

@@ -33,7 +33,7 @@ struct PassSmem {
   uint32_t wcnt[(THREADS / kWave) << RB];
   uint32_t dstart[1 << RB];
   uint32_t gofs[1 << RB];
-  uint32_t tmp[THREADS / kWave];
+  unsigned long long tmp[THREADS / kWave];
   uint32_t ticket;
   uint32_t timeout;
 };
@@ -48,7 +48,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   constexpr uint32_t DMASK = BINS - 1;
   constexpr int TILE = THREADS * ITEMS;
   const int tid = threadIdx.x;
-  const uint32_t gbase = tid < BINS ? a.bases[tid] : 0u;
+  // 32-bit keys: global total of digit tid (summed over the histogram
+  // copies), whose exclusive prefix over the digits is the digit's first
+  // output slot; parked in LDS so that no register holds it through the
+  // ranking
+  if constexpr (sizeof(K) == 4) {
+    if (tid < BINS) {
+      uint32_t gtot = 0;
+#pragma unroll
+      for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + tid];
+      sm.gofs[tid] = gtot;
+    }
+  }
 
   // ---- load (wave-striped) ----
   const K* __restrict__ kin = static_cast<const K*>(a.kin);
@@ -119,8 +130,21 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
     }
     st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
   }
-  uint32_t total;
-  const uint32_t lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, sm.tmp, total);
+  uint32_t gbase, lexcl;
+  if constexpr (sizeof(K) == 4) {
+    // one scan for both prefixes over the digits: the global digit bases
+    // (high word) and this tile's digit starts (low word); neither carries
+    const uint32_t gtot = tid < BINS ? sm.gofs[tid] : 0u;
+    unsigned long long total;
+    const unsigned long long both = block_exclusive_scan<unsigned long long, THREADS>(
+        (static_cast<unsigned long long>(gtot) << 32) | bcnt, sm.tmp, total);
+    gbase = static_cast<uint32_t>(both >> 32);
+    lexcl = static_cast<uint32_t>(both);
+  } else {
+    uint32_t total;
+    gbase = tid < BINS ? a.bases[tid] : 0u;
+    lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, reinterpret_cast<uint32_t*>(sm.tmp), total);
+  }
   if (tid < BINS) sm.dstart[tid] = lexcl;
   __syncthreads();
 
@@ -136,26 +160,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
   if (tid < BINS) {
     uint32_t excl = 0;
-    if (t > 0) {
-      int32_t kb = static_cast<int32_t>(t) - 1;
-      uint32_t spins = 0;
-      while (true) {
-        const uint32_t w = ld_agent(&a.lookback[static_cast<size_t>(kb) * BINS + tid]);
-        if ((w & ~kLbMask32) == 0) {
-          if (++spins > kSpinLimit) {
-            sm.timeout = 1;
-            if (a.status) st_agent(a.status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += w & kLbMask32;
-        if (w & kLbInc32) break;
-        --kb;
-      }
-      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], kLbInc32 | (excl + bcnt));
-    }
+    if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl)) sm.timeout = 1;
     sm.gofs[tid] = gbase + excl - lexcl;
   }
   __syncthreads();

@@ -47,10 +47,16 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="fullhd-1m",
-                   choices=sorted(synth.FRAME_WORKLOADS) + ["batch-64", "serve"])
-    p.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate (serve)")
+                   choices=sorted(synth.FRAME_WORKLOADS) + sorted(synth.SUPPLEMENTARY_WORKLOADS)
+                   + ["batch-64", "serve", "sweep"])
+    p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
     p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
+    p.add_argument("--small-arena-gib", type=float, default=0.5,
+                   help="second budget, run at the highest rate to force admission stalls (serve; 0: skip)")
+    p.add_argument("--pool-frames", type=int, default=512, help="device-resident request frames (serve)")
+    p.add_argument("--sweep-mpairs", default="0.5,1,2,4,8,17,32,64,100",
+                   help="sort-only sizes in millions of pairs (sweep)")
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
@@ -235,75 +241,150 @@ def bench_serve(args):
     import torch
     import paper_2511_16298_amd as ss
 
+    # the request pool is drawn on the host before anything touches the GPU
+    # (forked workers, one frame each)
+    import multiprocessing as mp
+    t_gen = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as workers:
+        pool = workers.starmap(synth.batch_frame, [(synth.SEED_BASE + 4, f) for f in range(args.pool_frames)])
+    print(f"# pool: {len(pool)} frames, N={sum(len(r) for _, _, r in pool)}, drawn in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    pool = synth.make_batch(64, seed=synth.SEED_BASE + 4)
-    recs = [ss.records_to_device(r, dev) for (_, _, r) in pool]
+    recs = []
+    for i in range(len(pool)):
+        recs.append(ss.records_to_device(pool[i][2], dev))
+        pool[i] = (pool[i][0], pool[i][1], None)   # keep the shape only
     rates = [float(x) for x in args.serve_rates.split(",")]
     arena = int(args.arena_gib * (1 << 30))
-    results = {}
-    for mode, (frames, streams) in (("batched", (64, 2)), ("one_at_a_time", (1, 1))):
-        srv = ss.Server(arena, max_batch_frames=frames, n_streams=streams, device=dev)
-        for rate in rates:
-            seed = synth.SEED_BASE + 4 + int(rate)
-            arr = synth.poisson_arrivals(rate, args.serve_seconds, seed)
-            picks = synth.uniform_int(synth.stream_key(seed, 7), len(arr), len(pool))
-            tickets = []
-            lock = threading.Condition()
-            got = []
 
-            done_submitting = [False]
+    def run_trace(srv, rate):
+        seed = synth.SEED_BASE + 4 + int(rate)
+        arr = synth.poisson_arrivals(rate, args.serve_seconds, seed)
+        picks = synth.uniform_int(synth.stream_key(seed, 7), len(arr), len(pool))
+        tickets = []
+        lock = threading.Condition()
+        got = []
+        done_submitting = [False]
 
-            def collect():
-                i = 0
-                while True:
-                    with lock:
-                        while i >= len(tickets) and not done_submitting[0]:
-                            lock.wait(0.01)
-                        if i >= len(tickets):
-                            return
-                        t = tickets[i]
-                    r = srv.wait(t)
-                    got.append((r.status, r.num_pairs, r.submit_us, r.start_us, r.done_us, r.round_frames))
-                    srv.release(t)
-                    i += 1
-            th = threading.Thread(target=collect)
-            th.start()
-            t0 = time.perf_counter()
-            for a, k in zip(arr, picks):
-                delay = t0 + a - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                w, h, _ = pool[int(k)]
-                t = srv.submit(recs[int(k)], w, h)
+        def collect():
+            i = 0
+            while True:
                 with lock:
-                    tickets.append(t)
-                    lock.notify()
+                    while i >= len(tickets) and not done_submitting[0]:
+                        lock.wait(0.01)
+                    if i >= len(tickets):
+                        return
+                    t = tickets[i]
+                r = srv.wait(t)
+                got.append((r.status, r.num_pairs, r.submit_us, r.start_us, r.done_us, r.round_frames))
+                srv.release(t)
+                i += 1
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for a, k in zip(arr, picks):
+            delay = t0 + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            w, h, _ = pool[int(k)]
+            t = srv.submit(recs[int(k)], w, h)
             with lock:
-                done_submitting[0] = True
+                tickets.append(t)
                 lock.notify()
-            th.join()
-            g = np.array([x[:5] for x in got], dtype=np.float64)
-            ok = g[:, 0] == 0
-            lat = (g[:, 4] - g[:, 2]) / 1e3   # ms
-            keep = (g[:, 2] - g[:, 2].min()) > 1e6   # skip the first second of arrivals
-            span = (g[:, 4].max() - g[:, 2].min()) / 1e6
-            results[f"{mode}@{int(rate)}"] = {
-                "requests": len(got), "ok": int(ok.sum()), "pairs": int(g[ok, 1].sum()),
-                "pairs_per_s": float(g[ok, 1].sum() / span), "p50_ms": pct(lat[keep], 50),
-                "p99_ms": pct(lat[keep], 99), "mean_round_frames": float(np.mean([x[5] for x in got])),
+        with lock:
+            done_submitting[0] = True
+            lock.notify()
+        th.join()
+        g = np.array([x[:5] for x in got], dtype=np.float64)
+        ok = g[:, 0] == 0
+        lat = (g[:, 4] - g[:, 2]) / 1e3   # ms
+        keep = ok & ((g[:, 2] - g[:, 2].min()) > 1e6)   # skip the first second of arrivals
+        span = (g[:, 4].max() - g[:, 2].min()) / 1e6
+        return {"requests": len(got), "ok": int(ok.sum()), "rejected_budget": int((g[:, 0] == 8).sum()),
+                "pairs": int(g[ok, 1].sum()), "pairs_per_s": float(g[ok, 1].sum() / span),
+                "p50_ms": pct(lat[keep], 50), "p99_ms": pct(lat[keep], 99),
+                "mean_round_frames": float(np.mean([x[5] for x in got])),
                 "offered_pairs_per_s": float(g[ok, 1].sum() / args.serve_seconds)}
-            print(f"# {mode} @ {rate:g}/s: {results[f'{mode}@{int(rate)}']}", file=sys.stderr, flush=True)
+
+    runs = [("batched", 64, 2, arena, rates), ("one_at_a_time", 1, 1, arena, rates)]
+    if args.small_arena_gib > 0:
+        runs.append(("batched_small_arena", 64, 2, int(args.small_arena_gib * (1 << 30)), rates[-1:]))
+    results = {}
+    for mode, frames, streams, budget, mode_rates in runs:
+        srv = ss.Server(budget, max_batch_frames=frames, n_streams=streams, device=dev)
+        for rate in mode_rates:
+            key = f"{mode}@{int(rate)}"
+            results[key] = run_trace(srv, rate)
+            print(f"# {key}: {results[key]}", file=sys.stderr, flush=True)
         srv.close()
     line = {"metric": "served frame-sort requests: pairs/s and p50/p99 request latency",
             "value": results[f"batched@{int(rates[-1])}"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
             "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": f"serve: Poisson arrivals {args.serve_rates}/s for {args.serve_seconds:g} s "
-                                   f"each, frames drawn from a pool of 64 device-resident frames of the batch "
-                                   f"distribution, HBM budget {args.arena_gib:g} GiB",
+                                   f"each, frames drawn from a pool of {len(pool)} device-resident frames of "
+                                   f"the batch distribution, HBM budget {args.arena_gib:g} GiB (and "
+                                   f"{args.small_arena_gib:g} GiB at the highest rate)",
                        "parallelism": "single GPU"},
             "runs": results}
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(args):
+    """Sort alone (step a4 through ss_sort_pairs) over random 45-bit keys, the
+    paper's random key-value sweep extended to 10^8 pairs."""
+    import torch
+    import paper_2511_16298_amd as ss
+    from paper_2511_16298_amd import _abi
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    key_bits = 45
+    rows = {}
+    for mp_ in [float(x) for x in args.sweep_mpairs.split(",")]:
+        m = int(mp_ * 1e6)
+        keys, vals = synth.sort_sweep_pairs(m, key_bits, seed=synth.SEED_BASE + 5)
+        ki = torch.from_numpy(keys.view(np.int64)).to(dev)
+        vi = torch.from_numpy(vals.view(np.int32)).to(dev)
+        del keys, vals
+        ko, vo = torch.empty_like(ki), torch.empty_like(vi)
+        opts = ss.make_options()
+        st, ws = _abi.ss_sort_pairs_workspace_bytes(m, key_bits, opts)
+        assert st == 0
+        work = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+
+        def step():
+            st_ = _abi.ss_sort_pairs(ki.data_ptr(), vi.data_ptr(), m, key_bits, ko.data_ptr(), vo.data_ptr(),
+                                     work.data_ptr(), ws, stream.cuda_stream, opts)
+            assert st_ == 0
+        reps = max(3, min(args.steps, int(2e9 / max(m, 1))))
+        for _ in range(min(args.warmup, 5)):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ok = bool(torch.all(ko[1:] >= ko[:-1]).item()) if m > 1 else True
+        passes = -(-key_bits // 8)
+        rows[f"{mp_:g}M"] = {"pairs": m, "ms": ms, "pairs_per_s": m / (ms * 1e-3),
+                             "pass_bytes_GBps": 24.0 * m * passes / (ms * 1e-3) / 1e9, "sorted": ok}
+        print(f"# sweep {mp_:g}M: {rows[f'{mp_:g}M']}", file=sys.stderr, flush=True)
+        del ki, vi, ko, vo, work
+        torch.cuda.empty_cache()
+    best = max(rows.values(), key=lambda r: r["pairs_per_s"])
+    line = {"metric": "sort-only pairs/s over random 45-bit keys (supplementary sweep)",
+            "value": best["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": None, "warmup": None,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"sweep: ss_sort_pairs, uniform 45-bit keys, sizes {args.sweep_mpairs} M pairs",
+                       "parallelism": "single GPU"},
+            "runs": rows}
     print(json.dumps(line), flush=True)
 
 
@@ -312,11 +393,11 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
-    if args.workload in ("batch-64", "serve"):
+    if args.workload in ("batch-64", "serve", "sweep"):
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
-        (bench_batch if args.workload == "batch-64" else bench_serve)(args)
+        {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep}[args.workload](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "
@@ -327,7 +408,7 @@ def main():
     import paper_2511_16298_amd as ss
     from paper_2511_16298_amd import _abi
 
-    spec, seed = synth.FRAME_WORKLOADS[args.workload]
+    spec, seed = synth.workload(args.workload)
     rec = synth.make_frame(spec, seed)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -350,7 +431,7 @@ def main():
         del a, b
 
     print(f"# workload {args.workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
-          f"T={tx * ty}, key bits {key_bits}, passes {passes}", file=sys.stderr, flush=True)
+          f"T={tx * ty}, key bits {key_bits}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         sorter(d, stream)
@@ -397,9 +478,15 @@ def main():
     pass_us = kern["sort_pass"]["avg_us"]
     pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair
     achieved = pass_bytes / (pass_us * 1e-6) / 1e9
-    # whole-step algorithmic bytes (model): 48 N + (28 + 24 P) M + 8 T
+    # whole-step algorithmic bytes of the depth-first path that runs:
+    # count 16N read + 16N write (rectangle, depth key, index), four depth
+    # passes 16N each, expand 16N read + 12M write, Pt tile passes 24M each,
+    # ranges 8M + 8T -- 112 N + (20 + 24 Pt) M + 8 T.  The direct path would
+    # move 48 N + (28 + 24 P) M + 8 T.
     N = len(rec)
-    step_bytes = 48.0 * N + (28.0 + 24.0 * passes) * M + 8.0 * tx * ty
+    tile_passes = -(-(key_bits - 32) // rb)
+    step_bytes = 112.0 * N + (20.0 + 24.0 * tile_passes) * M + 8.0 * tx * ty
+    direct_bytes = 48.0 * N + (28.0 + 24.0 * passes) * M + 8.0 * tx * ty
 
     pairs_per_s = M / (ms_per_step * 1e-3)
     line = {
@@ -417,14 +504,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {spec.width}x{spec.height} image, 16x16 tiles "
                                f"({tx}x{ty}={tx * ty}), N={N} projected Gaussians, seed {seed}",
-                   "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "passes": passes,
-                   "parallelism": "single GPU"},
+                   "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "path": "depth-first",
+                   "depth_passes": 4, "tile_passes": tile_passes, "parallelism": "single GPU"},
         "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99), "max": max(step_ms)},
         "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": profiled_traffic(args.workload),
                      "bytes_per_launch": pass_bytes, "avg_launch_us": pass_us},
-        "step_model": {"bytes": step_bytes, "GB/s": step_bytes / (ms_per_step * 1e-3) / 1e9,
-                       "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "step_model": {"path": "depth-first", "bytes": step_bytes, "GB/s": step_bytes / (ms_per_step * 1e-3) / 1e9,
+                       "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                       "direct_path_bytes": direct_bytes},
         "kernels": kern,
         "instrumented_ms_per_step": instr_ms_per_step,
     }

@@ -205,6 +205,17 @@ FRAME_WORKLOADS = {"small-256x256": (SMALL, SEED_BASE + 0),
                    "fullhd-1m": (FULL_HD, SEED_BASE + 1),
                    "large-6m": (LARGE, SEED_BASE + 2)}
 
+#: supplementary: the heavy-tailed frame scaled to about 10^8 pairs (about
+#: 1.2 GB of keys and values per sort pass)
+SUPPLEMENTARY_WORKLOADS = {"large-2b-22m": (dataclasses.replace(LARGE, n=21_800_000), SEED_BASE + 2)}
+
+
+def workload(name: str) -> tuple:
+    """(FrameSpec, seed) of a single-frame workload, core or supplementary."""
+    if name in FRAME_WORKLOADS:
+        return FRAME_WORKLOADS[name]
+    return SUPPLEMENTARY_WORKLOADS[name]
+
 BATCH_RESOLUTIONS = ((640, 360), (1280, 720), (1920, 1080))
 BATCH_N_RANGE = (50_000, 2_000_000)
 
@@ -227,14 +238,16 @@ def batch_frame_spec(seed: int, frame_index: int,
     return dataclasses.replace(FULL_HD, width=w, height=h, n=n)
 
 
+def batch_frame(seed: int, frame_index: int, n_range: Sequence[int] = BATCH_N_RANGE) -> tuple:
+    """Frame ``frame_index`` of batch stream ``seed`` as ``(width, height, records)``."""
+    spec = batch_frame_spec(seed, frame_index, n_range)
+    return spec.width, spec.height, make_frame(spec, seed, frame_index)
+
+
 def make_batch(n_frames: int, seed: int = SEED_BASE + 3,
                n_range: Sequence[int] = BATCH_N_RANGE) -> List[tuple]:
     """``n_frames`` uneven frames as ``(width, height, records)`` tuples."""
-    out = []
-    for f in range(n_frames):
-        spec = batch_frame_spec(seed, f, n_range)
-        out.append((spec.width, spec.height, make_frame(spec, seed, f)))
-    return out
+    return [batch_frame(seed, f, n_range) for f in range(n_frames)]
 
 
 def poisson_arrivals(rate_per_s: float, duration_s: float, seed: int) -> np.ndarray:

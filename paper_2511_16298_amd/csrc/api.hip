@@ -20,9 +20,6 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 // Counter words at the start of the workspace.
-constexpr uint32_t kCounterTicket = 0;   // direct path: count / duplicate tickets
-constexpr uint32_t kCounterExpand = 1;   // depth-first: expand tickets
-constexpr uint32_t kCounterPass = 16;    // + p: tickets of sort pass p (p < 48)
 
 struct Options {
   uint32_t radix_bits = kDefaultRadix;
@@ -87,12 +84,12 @@ T* at(void* ws, size_t off) {
 
 // ---------------------------------------------------------------------------
 // Direct path: count/scan/duplicate in index order, then P passes over the
-// full key.  Workspace: [counters | scalars | bases | scan look-back |
+// full key.  Workspace: [scalars | bases | scan look-back |
 // histograms | pass look-back] zeroed per call, then the alternate buffers.
 // ---------------------------------------------------------------------------
 struct Layout {
   uint32_t npasses = 0, bins = 0, count_blocks = 0, pass_blocks = 0, tile = 0;
-  size_t counters = 0, scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, bases = 0, clear_end = 0;
+  size_t scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, bases = 0, clear_end = 0;
   size_t alt_keys = 0, alt_vals = 0, total = 0;
 };
 
@@ -104,7 +101,6 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
   L.tile = o.threads * o.items;
   L.pass_blocks = (capacity + L.tile - 1) / L.tile;
   size_t off = 0;
-  L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
   L.scalars = off;   off = align_up(off + 4 * sizeof(uint32_t));
   L.bases = off;     off = align_up(off + static_cast<size_t>(L.npasses) * L.bins * sizeof(uint32_t));
   L.scan_lb = off;   off = align_up(off + static_cast<size_t>(L.count_blocks) * sizeof(uint64_t));
@@ -118,7 +114,7 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
 }
 
 // ---------------------------------------------------------------------------
-// Depth-first path (one frame or a batch).  Zeroed part: counters, scalars,
+// Depth-first path (one frame or a batch).  Zeroed part: scalars,
 // bad flag, totals, count-only scan look-back, expand look-back, histograms
 // and look-back words of the depth and tile passes; then the frame table,
 // tile digit bases, rectangles, the Gaussian sort buffers and the alternate
@@ -143,7 +139,7 @@ struct DfLayout {
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
-  size_t counters = 0, scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
+  size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
          lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
          key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, total = 0;
 };
@@ -164,7 +160,6 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
   L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
   size_t off = 0;
-  L.counters = off;  off = align_up(off + 64 * sizeof(uint32_t));
   L.scalars = off;   off = align_up(off + 4 * sizeof(uint32_t));
   L.bad = off;       off = align_up(off + sizeof(uint32_t));
   L.totals = off;    off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
@@ -259,7 +254,6 @@ struct PassChain {
   const uint32_t* bases;      // 64-bit keys: [npasses][bins] digit bases
   const uint32_t* hist;       // 32-bit keys: pass p's totals at hist + p * bins, copies hist_stride apart
   uint32_t hist_stride;
-  uint32_t* tickets;          // [npasses]
   uint32_t* lookback;         // [npasses][nblocks][bins]
 };
 
@@ -280,7 +274,6 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.bases = c.bases ? c.bases + static_cast<size_t>(p) * bins : nullptr;
       a.hist = c.hist ? c.hist + static_cast<size_t>(p) * bins : nullptr;
       a.hist_stride = c.hist_stride;
-      a.ticket = c.tickets + p;
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       if (launch_pass(a, static_cast<int>(c.key_bytes), static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
                       static_cast<int>(c.cfg.threads), c.nblocks, s) != hipSuccess)
@@ -321,7 +314,6 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   a.offsets = out->offsets;
   a.keys = bk[0];
   a.values = bv[0];
-  a.ticket = at<uint32_t>(ws, lay.counters) + kCounterTicket;
   a.lookback = at<uint64_t>(ws, lay.scan_lb);
   a.hist = at<uint32_t>(ws, lay.hist);
   a.num_pairs = d_num_pairs;
@@ -345,7 +337,7 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
               kd.data(), vd.data(), d_num_pairs, 0, d_status, bases, nullptr, 0,
-              at<uint32_t>(ws, lay.counters) + kCounterPass, at<uint32_t>(ws, lay.pass_lb)};
+              at<uint32_t>(ws, lay.pass_lb)};
   SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   return L.run(SS_KERNEL_RANGES, [&] {
     return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
@@ -389,7 +381,6 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   uint32_t* scal = at<uint32_t>(ws, lay.scalars);
   uint32_t* d_status = io.status ? io.status : scal + 0;
   uint32_t* d_num_pairs = io.num_pairs ? io.num_pairs : scal + 1;
-  uint32_t* counters = at<uint32_t>(ws, lay.counters);
   FrameInfo* table = at<FrameInfo>(ws, lay.table);
 
   SS_TRY(clear_and_upload(L, ws, lay.clear_end, d_status, io.host_table, lay.n_frames, table, s));
@@ -401,7 +392,6 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     a.tiles_x = io.host_table[0].tiles_x;
     a.tiles_y = io.host_table[0].tiles_y;
     a.offsets = io.offsets;
-    a.ticket = counters + kCounterTicket;
     a.lookback = at<uint64_t>(ws, lay.scan_lb);
     a.num_pairs = scal + 2;
     a.status = scal + 3;
@@ -435,7 +425,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     void* kd[4] = {key_alt, key, key_alt, key};
     uint32_t* vd[4] = {val_alt, val, val_alt, val};
     PassChain c{4, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
-                nullptr, ck.hist, 4 * 256, counters + kCounterPass, at<uint32_t>(ws, lay.lb_d)};
+                nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d)};
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
 
@@ -460,7 +450,6 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.npasses = P;
   e.radix_bits = o.radix_bits;
   e.hist = at<uint32_t>(ws, lay.hist_t);
-  e.ticket = counters + kCounterExpand;
   e.lookback = at<uint64_t>(ws, lay.expand_lb);
   e.status = d_status;
   e.nblocks = lay.eblocks;
@@ -483,7 +472,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       vd[p] = bv[(p + 1) % 2];
     }
     PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                d_status, bases_t, nullptr, 0, counters + kCounterPass + 4, at<uint32_t>(ws, lay.lb_t)};
+                d_status, bases_t, nullptr, 0, at<uint32_t>(ws, lay.lb_t)};
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   }
   return L.run(SS_KERNEL_RANGES, [&] {
@@ -595,7 +584,6 @@ ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint3
   a.tiles_y = g.tiles_y;
   a.tiles_touched = d_tiles_touched;
   a.offsets = d_offsets;
-  a.ticket = at<uint32_t>(workspace, lay.counters) + kCounterTicket;
   a.lookback = at<uint64_t>(workspace, lay.scan_lb);
   a.hist = at<uint32_t>(workspace, lay.hist);
   a.num_pairs = d_num_pairs;
@@ -666,7 +654,7 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
 // Batched sizing: per-frame pair counts only.
 struct CountLayout {
   uint32_t ck_blocks = 0;
-  size_t counters = 0, scalars = 0, bad = 0, totals = 0, block_total = 0, block_frame = 0, clear_end = 0,
+  size_t scalars = 0, bad = 0, totals = 0, block_total = 0, block_frame = 0, clear_end = 0,
          table = 0, total = 0;
 };
 
@@ -674,7 +662,6 @@ static CountLayout make_count_layout(uint64_t n, uint32_t n_frames) {
   CountLayout L;
   L.ck_blocks = static_cast<uint32_t>((n + kCountKeysTile - 1) / kCountKeysTile);
   size_t off = 0;
-  L.counters = off;    off = align_up(off + 64 * sizeof(uint32_t));
   L.scalars = off;     off = align_up(off + 4 * sizeof(uint32_t));
   L.bad = off;         off = align_up(off + sizeof(uint32_t));
   L.totals = off;      off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
@@ -771,7 +758,7 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
               kd.data(), vd.data(), nullptr, n, nullptr, bases, nullptr, 0,
-              at<uint32_t>(workspace, lay.counters) + kCounterPass, at<uint32_t>(workspace, lay.pass_lb)};
+              at<uint32_t>(workspace, lay.pass_lb)};
   return run_chain(L, SS_KERNEL_SORT_PASS, c, s);
 }
 

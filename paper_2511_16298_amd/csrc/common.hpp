@@ -21,6 +21,14 @@ constexpr uint64_t kLbInc64 = 2ull << 62;
 constexpr uint64_t kLbBad64 = 1ull << 61;
 constexpr uint64_t kLbMask64 = (1ull << 61) - 1;
 
+// Look-back order.  Workgroup b takes tile b of the input and waits only on
+// workgroups with smaller indices.  The dispatcher hands each XCD its
+// workgroups in increasing index order, so the smallest undispatched
+// workgroup always finds a slot once the running, smaller ones finish: no
+// wait can block forever, and no atomic ticket (whose same-address atomics
+// serialise at about 12 ns per workgroup) is needed.  Results do not depend
+// on the dispatch order at all; the bounded spin below only guards progress.
+//
 // A bounded spin: after this many polls a waiting workgroup gives up, raises
 // SS_ERR_TIMEOUT in the status word and leaves (its output is then invalid,
 // but the grid always drains).  Far above any legitimate wait.

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   __shared__ uint32_t s_hist[8 * 256];   // tile digits: up to 32 bits at 4 bits per pass
   __shared__ unsigned long long s_tmp64[kExpandThreads / kWave];
   __shared__ uint32_t s_tmp[kExpandThreads / kWave];
-  __shared__ uint32_t s_ticket, s_first, s_retry, s_timeout;
+  __shared__ uint32_t s_first, s_retry, s_timeout;
   __shared__ unsigned long long s_prefix;
   __shared__ unsigned long long s_fm[kMaxFrames];
 
@@ -223,16 +223,13 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   // while the others run, and every workgroup must publish its look-back
   // word.  Writes stay below capacity whatever the status becomes.
   const uint32_t tid = threadIdx.x;
-  if (tid == 0) {
-    s_ticket = atomicAdd(a.ticket, 1u);
-    s_timeout = 0;
-  }
+  if (tid == 0) s_timeout = 0;
   for (uint32_t i = tid; i < a.n_frames; i += kExpandThreads) s_tab[i] = a.table[i];
   const uint32_t rb = a.radix_bits;
   const uint32_t bins = 1u << rb;
   for (uint32_t i = tid; i < a.npasses * bins; i += kExpandThreads) s_hist[i] = 0;
   __syncthreads();
-  const uint32_t ticket = s_ticket;
+  const uint32_t ticket = blockIdx.x;   // look-back order (see common.hpp)
   const uint32_t base = ticket * kExpandTile;
 
   // ---- Gaussians of this workgroup: striped loads, per-Gaussian info ----

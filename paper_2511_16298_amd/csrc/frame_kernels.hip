@@ -43,9 +43,8 @@ __global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, s
     dst[i] = src[i];
 }
 
-// One workgroup takes 1024 consecutive Gaussians (its ticket, drawn from an
-// atomic counter so that every earlier ticket belongs to a workgroup that is
-// already running: the look-back below always makes progress).
+// Workgroup b takes the 1024 consecutive Gaussians of tile b (look-back order
+// as described in common.hpp).
 //  a1: overlap rectangle of each Gaussian's open bounding box with the tile
 //      grid, in 1/16-px integers: x0 = floor((X - 16 r) / 256),
 //      x1 = ceil((X + 16 r) / 256), clamped to [0, tiles_x]; radius 0 culls.
@@ -67,18 +66,16 @@ __global__ __launch_bounds__(kCountThreads) void k_count_dup(CountDupArgs a) {
   __shared__ uint32_t s_loc[kCountTile]; // counts, then local exclusive offsets
   __shared__ uint32_t s_hist[DUP ? MAXP * BINS : 1];
   __shared__ uint64_t s_tmp[kCountThreads / kWave];
-  __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_bad;
 
   const int tid = threadIdx.x;
   const uint32_t npasses = a.npasses;
   const uint32_t depth_passes = 32 / RB < npasses ? 32 / RB : npasses;
-  if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
   if (DUP)
     for (uint32_t i = tid; i < npasses * BINS; i += kCountThreads) s_hist[i] = 0;
   __syncthreads();
-  const uint32_t ticket = s_ticket;
+  const uint32_t ticket = blockIdx.x;
   const uint64_t gbase = static_cast<uint64_t>(ticket) * kCountTile;
 
   // ---- a1 (striped, coalesced 16-byte loads) ----

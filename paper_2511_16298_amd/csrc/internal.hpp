@@ -24,7 +24,6 @@ struct CountDupArgs {
   uint32_t* offsets;        // optional [n]
   uint64_t* keys;           // [capacity] unsorted pairs
   uint32_t* values;
-  uint32_t* ticket;         // zeroed counter
   uint64_t* lookback;       // zeroed [nblocks]
   uint32_t* hist;           // zeroed [kHistCopies][npasses][bins]
   uint32_t* num_pairs;
@@ -48,7 +47,6 @@ struct PassArgs {
   const uint32_t* bases;
   const uint32_t* hist;
   uint32_t hist_stride;
-  uint32_t* ticket;           // zeroed counter
   uint32_t* lookback;         // zeroed [nblocks][bins]
 };
 
@@ -126,11 +124,10 @@ struct ExpandArgs {
   uint32_t npasses;         // tile-digit passes that follow
   uint32_t radix_bits;      // their digit width (<= 8)
   uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits]
-  uint32_t* ticket;         // zeroed
   uint64_t* lookback;       // zeroed [nblocks]
   uint32_t* status;
   uint32_t nblocks;
-  PairTotalsArgs totals;    // finished by workgroup 0 (ticket 0)
+  PairTotalsArgs totals;    // finished by workgroup 0
 };
 
 hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s);

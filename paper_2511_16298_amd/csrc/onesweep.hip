@@ -34,7 +34,6 @@ struct PassSmem {
   uint32_t dstart[1 << RB];
   uint32_t gofs[1 << RB];
   unsigned long long tmp[THREADS / kWave];
-  uint32_t ticket;
   uint32_t timeout;
 };
 
@@ -205,13 +204,10 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   if (a.status && *a.status != SS_OK) return;
   const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    sm.ticket = atomicAdd(a.ticket, 1u);
-    sm.timeout = 0;
-  }
+  if (tid == 0) sm.timeout = 0;
   for (int i = tid; i < (THREADS / kWave) << RB; i += THREADS) sm.wcnt[i] = 0;
   __syncthreads();
-  const uint32_t t = sm.ticket;
+  const uint32_t t = blockIdx.x;
   const uint32_t base = t * TILE;
   if (base >= n) return;  // uniform over the workgroup
   if (n - base >= static_cast<uint32_t>(TILE))

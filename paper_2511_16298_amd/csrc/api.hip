@@ -172,9 +172,9 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * L.tpasses * L.tbins * sizeof(uint32_t));
   L.lb_d = off;      off = align_up(off + static_cast<size_t>(4) * L.dblocks * 256 * sizeof(uint32_t));
   L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses) * L.tblocks * L.tbins * sizeof(uint32_t));
+  L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
   L.clear_end = off;
   L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
-  L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
   L.rect = off;      off = align_up(off + static_cast<size_t>(n) * sizeof(uint64_t));
   L.key = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
   L.val = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
@@ -251,8 +251,8 @@ struct PassChain {
   const uint32_t* num_pairs;  // device M or NULL (then n_fixed)
   uint32_t n_fixed;
   uint32_t* status;
-  const uint32_t* bases;      // 64-bit keys: [npasses][bins] digit bases
-  const uint32_t* hist;       // 32-bit keys: pass p's totals at hist + p * bins, copies hist_stride apart
+  uint32_t* bases;            // 64-bit keys: [npasses][bins] published digit bases (zeroed), or NULL
+  const uint32_t* hist;       // pass p's totals at hist + p * bins, copies hist_stride apart
   uint32_t hist_stride;
   uint32_t* lookback;         // [npasses][nblocks][bins]
 };
@@ -274,6 +274,7 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.bases = c.bases ? c.bases + static_cast<size_t>(p) * bins : nullptr;
       a.hist = c.hist ? c.hist + static_cast<size_t>(p) * bins : nullptr;
       a.hist_stride = c.hist_stride;
+      a.publish_passes = c.bases != nullptr && p == 0 ? c.npasses : 0u;
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       if (launch_pass(a, static_cast<int>(c.key_bytes), static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
                       static_cast<int>(c.cfg.threads), c.nblocks, s) != hipSuccess)
@@ -322,9 +323,6 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
   if (unsorted) return SS_OK;
   uint32_t* bases = at<uint32_t>(ws, lay.bases);
-  SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
-    return launch_digit_bases(a.hist, lay.npasses, bases, static_cast<int>(o.radix_bits), s);
-  }));
   std::vector<const void*> ks(P);
   std::vector<const uint32_t*> vs(P);
   std::vector<void*> kd(P);
@@ -336,7 +334,7 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
     vd[p] = bv[(p + 1) % 2];
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
-              kd.data(), vd.data(), d_num_pairs, 0, d_status, bases, nullptr, 0,
+              kd.data(), vd.data(), d_num_pairs, 0, d_status, bases, a.hist, lay.npasses * lay.bins,
               at<uint32_t>(ws, lay.pass_lb)};
   SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   return L.run(SS_KERNEL_RANGES, [&] {
@@ -458,9 +456,6 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
   if (P > 0) {
     uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
-    SS_TRY(L.run(SS_KERNEL_DIGIT_BASES, [&] {
-      return launch_digit_bases(e.hist, P, bases_t, static_cast<int>(o.radix_bits), s);
-    }));
     std::vector<const void*> ks(P);
     std::vector<const uint32_t*> vs(P);
     std::vector<void*> kd(P);
@@ -472,7 +467,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       vd[p] = bv[(p + 1) % 2];
     }
     PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                d_status, bases_t, nullptr, 0, at<uint32_t>(ws, lay.lb_t)};
+                d_status, bases_t, e.hist, P * lay.tbins, at<uint32_t>(ws, lay.lb_t)};
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   }
   return L.run(SS_KERNEL_RANGES, [&] {
@@ -739,9 +734,6 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   HistArgs h{keys_in, n, lay.npasses, at<uint32_t>(workspace, lay.hist)};
   SS_TRY(L.run(SS_KERNEL_HIST, [&] { return launch_hist(h, static_cast<int>(o.radix_bits), s); }));
   uint32_t* bases = at<uint32_t>(workspace, lay.bases);
-  SS_TRY(L.run(SS_KERNEL_HIST, [&] {
-    return launch_digit_bases(h.hist, lay.npasses, bases, static_cast<int>(o.radix_bits), s);
-  }));
   uint64_t* alt_k = at<uint64_t>(workspace, lay.alt_keys);
   uint32_t* alt_v = at<uint32_t>(workspace, lay.alt_vals);
   const uint32_t P = lay.npasses;
@@ -757,7 +749,7 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
     vs[p] = p == 0 ? values_in : vd[p - 1];
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
-              kd.data(), vd.data(), nullptr, n, nullptr, bases, nullptr, 0,
+              kd.data(), vd.data(), nullptr, n, nullptr, bases, h.hist, lay.npasses * lay.bins,
               at<uint32_t>(workspace, lay.pass_lb)};
   return run_chain(L, SS_KERNEL_SORT_PASS, c, s);
 }

@@ -20,6 +20,8 @@ constexpr uint64_t kLbAgg64 = 1ull << 62;
 constexpr uint64_t kLbInc64 = 2ull << 62;
 constexpr uint64_t kLbBad64 = 1ull << 61;
 constexpr uint64_t kLbMask64 = (1ull << 61) - 1;
+// A published digit base (counts stay below 2^30).
+constexpr uint32_t kBasePublished = 1u << 31;
 
 // Look-back order.  Workgroup b takes tile b of the input and waits only on
 // workgroups with smaller indices.  The dispatcher hands each XCD its

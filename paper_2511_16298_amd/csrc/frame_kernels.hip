@@ -264,25 +264,6 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
 
 // Exclusive prefix over digits of the global digit totals of every pass
 // (the histogram copies summed).  One workgroup of 256 threads per pass.
-template <int RB>
-__global__ __launch_bounds__(256) void k_digit_bases(const uint32_t* __restrict__ hist, uint32_t npasses,
-                                                     uint32_t* __restrict__ bases) {
-  constexpr int BINS = 1 << RB;
-  __shared__ uint32_t s_tmp[4];
-  const uint32_t d = threadIdx.x;
-  const uint32_t p = blockIdx.x;
-  uint32_t c[kHistCopies];
-#pragma unroll
-  for (uint32_t i = 0; i < kHistCopies; ++i)
-    c[i] = d < BINS ? hist[(static_cast<size_t>(i) * npasses + p) * BINS + d] : 0u;
-  uint32_t tot = 0;
-#pragma unroll
-  for (uint32_t i = 0; i < kHistCopies; ++i) tot += c[i];
-  uint32_t all;
-  const uint32_t ex = block_exclusive_scan<uint32_t, 256>(tot, s_tmp, all);
-  if (d < BINS) bases[p * BINS + d] = ex;
-}
-
 // a5: thread i compares the tile of pair i - 1 with the tile of pair i
 // (tile -1 before the first pair, tile T after the last).  At a change from
 // a to b it closes a at i, gives every tile strictly between a and b the
@@ -365,19 +346,6 @@ hipError_t launch_count_dup(const CountDupArgs& a, int radix_bits, bool dup, hip
     case 8: return count_dup_rb<8>(a, dup, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_digit_bases(const uint32_t* hist, uint32_t npasses, uint32_t* bases, int radix_bits,
-                              hipStream_t s) {
-  if (npasses == 0) return hipSuccess;
-  const dim3 g(npasses), b(256);
-  switch (radix_bits) {
-    case 4: hipLaunchKernelGGL((k_digit_bases<4>), g, b, 0, s, hist, npasses, bases); break;
-    case 6: hipLaunchKernelGGL((k_digit_bases<6>), g, b, 0, s, hist, npasses, bases); break;
-    case 8: hipLaunchKernelGGL((k_digit_bases<8>), g, b, 0, s, hist, npasses, bases); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s) {

@@ -40,13 +40,17 @@ struct PassArgs {
   uint32_t n_fixed;
   uint32_t* status;           // device status word or NULL
   uint32_t shift;             // first key bit of this digit
-  // Where the digit bases come from: 64-bit-key passes read `bases` ([bins]
-  // exclusive prefix of the digit totals); 32-bit-key passes (the Gaussian
-  // depth sort, one small grid) sum the kHistCopies histogram copies
-  // themselves, copy c at hist + c * hist_stride.
-  const uint32_t* bases;
+  // Where the digit bases come from.  32-bit-key passes (the Gaussian depth
+  // sort, one small grid) sum the kHistCopies histogram copies themselves,
+  // copy c at hist + c * hist_stride.  64-bit-key passes read `bases`
+  // ([bins] exclusive prefixes of the digit totals, bit 31 set once
+  // published, zeroed before the first pass); in the first pass of a chain
+  // (publish_passes > 0) an extra workgroup 0 computes them from `hist` for
+  // this and the next publish_passes - 1 passes (pass q at + q * bins of both).
+  uint32_t* bases;
   const uint32_t* hist;
   uint32_t hist_stride;
+  uint32_t publish_passes;
   uint32_t* lookback;         // zeroed [nblocks][bins]
 };
 
@@ -146,9 +150,6 @@ hipError_t launch_ranges(const uint64_t* keys, const uint32_t* num_pairs, const 
                          uint32_t capacity, uint32_t num_tiles, uint32_t* ranges, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
-// bases[p][d] = sum over histogram copies and digits d' < d of hist[c][p][d'].
-hipError_t launch_digit_bases(const uint32_t* hist, uint32_t npasses, uint32_t* bases, int radix_bits,
-                              hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s);
 

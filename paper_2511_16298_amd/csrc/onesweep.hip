@@ -141,8 +141,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
     lexcl = static_cast<uint32_t>(both);
   } else {
     uint32_t total;
-    gbase = tid < BINS ? a.bases[tid] : 0u;
     lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, reinterpret_cast<uint32_t*>(sm.tmp), total);
+    gbase = 0;  // read next to the look-back (below), where its temporaries are free
   }
   if (tid < BINS) sm.dstart[tid] = lexcl;
   __syncthreads();
@@ -158,6 +158,21 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
   if (tid < BINS) {
+    if constexpr (sizeof(K) == 8) {
+      // published by workgroup 0 of the chain's first pass, long before any
+      // workgroup gets here
+      uint32_t w = ld_agent(&a.bases[tid]), spins = 0;
+      while ((w & kBasePublished) == 0) {
+        if (++spins > kSpinLimit) {
+          sm.timeout = 1;
+          if (a.status) st_agent(a.status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        w = ld_agent(&a.bases[tid]);
+      }
+      gbase = w & ~kBasePublished;
+    }
     uint32_t excl = 0;
     if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl)) sm.timeout = 1;
     sm.gofs[tid] = gbase + excl - lexcl;
@@ -197,6 +212,26 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   }
 }
 
+// The extra workgroup of a chain's first 64-bit pass: digit bases of
+// publish_passes passes from the histogram copies, published with bit 31 set
+// (the current pass's first, since this launch's tiles need those now).
+template <int RB, int THREADS>
+__device__ __forceinline__ void publish_bases(const PassArgs& a, uint32_t* s_tmp) {
+  constexpr int BINS = 1 << RB;
+  const int tid = threadIdx.x;
+  for (uint32_t q = 0; q < a.publish_passes; ++q) {
+    uint32_t tot = 0;
+    if (tid < BINS) {
+#pragma unroll
+      for (uint32_t c = 0; c < kHistCopies; ++c)
+        tot += a.hist[static_cast<size_t>(c) * a.hist_stride + q * BINS + tid];
+    }
+    uint32_t all;
+    const uint32_t ex = block_exclusive_scan<uint32_t, THREADS>(tot, s_tmp, all);
+    if (tid < BINS) st_agent(&a.bases[q * BINS + tid], ex | kBasePublished);
+  }
+}
+
 template <typename K, int RB, int ITEMS, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   constexpr int TILE = THREADS * ITEMS;
@@ -207,7 +242,19 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   if (tid == 0) sm.timeout = 0;
   for (int i = tid; i < (THREADS / kWave) << RB; i += THREADS) sm.wcnt[i] = 0;
   __syncthreads();
-  const uint32_t t = blockIdx.x;
+  // In a chain's first 64-bit pass workgroup 0 only publishes the digit
+  // bases (dispatched first, it has them out before any tile needs them, and
+  // no tile's look-back waits on it); tile b is then workgroup b + 1.
+  uint32_t t = blockIdx.x;
+  if constexpr (sizeof(K) == 8) {
+    if (a.publish_passes != 0) {
+      if (t == 0) {
+        publish_bases<RB, THREADS>(a, reinterpret_cast<uint32_t*>(sm.tmp));
+        return;
+      }
+      --t;
+    }
+  }
   const uint32_t base = t * TILE;
   if (base >= n) return;  // uniform over the workgroup
   if (n - base >= static_cast<uint32_t>(TILE))
@@ -218,7 +265,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
 
 template <typename K, int RB, int ITEMS, int THREADS>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS>), dim3(nblocks), dim3(THREADS), 0, s, a);
+  const uint32_t grid = nblocks + (sizeof(K) == 8 && a.publish_passes != 0 ? 1u : 0u);
+  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS>), dim3(grid), dim3(THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -58,8 +58,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.oracle_sort.argtypes = [_P, _P, _U64]
     lib.oracle_ranges.argtypes = [_P, _U64, _U64, _P]
     lib.oracle_sort_frame.argtypes = [fp, _U64, _P, _P, _P, _P, _P, _P, _P, _P]
+    lib.oracle_render.argtypes = [fp, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
     for f in (lib.oracle_tile_grid, lib.oracle_count, lib.oracle_scan, lib.oracle_duplicate,
-              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame):
+              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame, lib.oracle_render):
         f.restype = ctypes.c_int
     return lib
 
@@ -188,6 +189,35 @@ def sort_frame(width: int, height: int, records: np.ndarray, tile_px: int = 16,
                        cnt if cnt is not None else empty, off if off is not None else empty,
                        uk[:mm] if uk is not None else empty, uv[:mm] if uv is not None else empty,
                        k[:mm], v[:mm], r)
+
+
+@dataclasses.dataclass
+class RenderResult:
+    status: int
+    color: np.ndarray      # float64 [3, H, W]
+    T: np.ndarray          # float64 [H, W], final transmittance
+    n_contrib: np.ndarray  # uint32 [H, W], Gaussians composited
+    margin: np.ndarray     # float64 [H, W], closest relative distance to a threshold
+
+
+def render(width: int, height: int, records: np.ndarray, conic_opacity: np.ndarray, rgb: np.ndarray,
+           values: np.ndarray, ranges: np.ndarray, background=(0.0, 0.0, 0.0), exact: bool = False) -> RenderResult:
+    """Alpha blending of every tile's sorted Gaussians (oracle_render).
+    ``conic_opacity`` and ``rgb`` are float32 [N, 4]; ``values``/``ranges`` a
+    sorted frame."""
+    fr, rec = _frame(width, height, records)
+    co = np.ascontiguousarray(conic_opacity, dtype=np.float32).reshape(-1, 4)
+    cl = np.ascontiguousarray(rgb, dtype=np.float32).reshape(-1, 4)
+    vals = np.ascontiguousarray(values, dtype=np.uint32)
+    rng = np.ascontiguousarray(ranges, dtype=np.uint32)
+    bg = np.ascontiguousarray(background, dtype=np.float64)
+    color = np.zeros((3, height, width), np.float64)
+    T = np.zeros((height, width), np.float64)
+    k = np.zeros((height, width), np.uint32)
+    margin = np.zeros((height, width), np.float64)
+    st = lib().oracle_render(ctypes.byref(fr), _ptr(co), _ptr(cl), _ptr(vals), _ptr(rng), _ptr(bg), int(exact),
+                             _ptr(color), _ptr(T), _ptr(k), _ptr(margin))
+    return RenderResult(st, color, T, k, margin)
 
 
 @dataclasses.dataclass

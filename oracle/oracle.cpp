@@ -14,7 +14,12 @@
 //    uses a 64-bit integer key built from tile number and depth; only the tile
 //    part of the key is needed to find each tile's range afterwards.
 //  * Design, table of grouped preprocessing outputs: the duplication step
-//    reads exactly the 2D mean, the depth and the radius of each Gaussian.
+//    reads exactly the 2D mean, the depth and the radius of each Gaussian;
+//    rendering also reads the conic-and-opacity and colour groups.
+//  * Background, "Rendering", and Design, "Efficient Tile-Based Rendering":
+//    every 16x16 tile composites its sorted Gaussians per pixel by alpha
+//    blending, with the compositing rule of 3D Gaussian Splatting (Kerbl et
+//    al. 2023), which the paper builds on (oracle_render).
 //
 // Readings where the paper is silent (each one also listed with the design
 // notes of the repository):
@@ -231,6 +236,52 @@ int oracle_sort_frame(const oracle_frame* f, uint64_t capacity,
   if (values) std::copy(v.begin(), v.end(), values);
 
   if (ranges) oracle_ranges(k.data(), m, static_cast<uint64_t>(tiles_x) * tiles_y, ranges);
+  return ORACLE_OK;
+}
+
+int oracle_render(const oracle_frame* f, const float* conic_opacity, const float* rgb, const uint32_t* values,
+                  const uint32_t* ranges, const double background[3], int exact, double* out_color,
+                  double* out_T, uint32_t* n_contrib, double* margin) {
+  uint32_t tiles_x, tiles_y;
+  if (oracle_tile_grid(f, &tiles_x, &tiles_y) != ORACLE_OK || background == nullptr) return ORACLE_ERR_INVALID_ARGUMENT;
+  if (f->num_gaussians > 0 && (conic_opacity == nullptr || rgb == nullptr)) return ORACLE_ERR_INVALID_ARGUMENT;
+  const uint64_t W = f->width, H = f->height;
+  const double kMinAlpha = 1.0 / 255.0, kMaxAlpha = 0.99, kMinT = 1e-4;
+  for (uint64_t y = 0; y < H; ++y) {
+    for (uint64_t x = 0; x < W; ++x) {
+      const uint64_t tile = (y / 16) * tiles_x + x / 16;
+      const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+      double T = 1.0, c[3] = {0.0, 0.0, 0.0}, m = 1.0;
+      uint32_t k = 0;
+      for (uint32_t i = start; i < end; ++i) {
+        const uint32_t g = values[i];
+        const oracle_gaussian& G = f->gaussians[g];
+        const double dx = G.mean_x / 16.0 - (static_cast<double>(x) + 0.5);
+        const double dy = G.mean_y / 16.0 - (static_cast<double>(y) + 0.5);
+        const double a = conic_opacity[4 * g], b = conic_opacity[4 * g + 1], cc = conic_opacity[4 * g + 2];
+        const double q = a * dx * dx + 2.0 * b * dx * dy + cc * dy * dy;
+        double alpha = conic_opacity[4 * g + 3] * std::exp(-0.5 * q);
+        if (!exact) {
+          if (q < 0.0) continue;
+          alpha = std::min(kMaxAlpha, alpha);
+          m = std::min(m, std::fabs(alpha - kMinAlpha) / kMinAlpha);
+          if (alpha < kMinAlpha) continue;
+          const double next = T * (1.0 - alpha);
+          m = std::min(m, std::fabs(next - kMinT) / kMinT);
+          if (next < kMinT) break;
+        }
+        for (int ch = 0; ch < 3; ++ch) c[ch] += rgb[4 * g + ch] * alpha * T;
+        T *= 1.0 - alpha;
+        ++k;
+      }
+      const uint64_t px = y * W + x;
+      if (out_color)
+        for (int ch = 0; ch < 3; ++ch) out_color[ch * W * H + px] = c[ch] + T * background[ch];
+      if (out_T) out_T[px] = T;
+      if (n_contrib) n_contrib[px] = k;
+      if (margin) margin[px] = m;
+    }
+  }
   return ORACLE_OK;
 }
 

@@ -80,6 +80,31 @@ int oracle_sort_frame(const oracle_frame* f, uint64_t capacity,
                       uint64_t* keys, uint32_t* values, uint32_t* ranges,
                       uint64_t* num_pairs);
 
+/* Render (the step after the sort; paper: Background, "Rendering", and
+ * Design, "Efficient Tile-Based Rendering"): every pixel of a tile composites
+ * the tile's Gaussians front to back, in the order of the sorted values,
+ * by alpha blending as in 3D Gaussian Splatting (Kerbl et al. 2023):
+ *   pixel (x, y) is sampled at its centre (x + 1/2, y + 1/2), in the frame in
+ *   which a Gaussian's mean is (mean_x / 16, mean_y / 16);
+ *   d = mean - sample; q = a dx^2 + 2 b dx dy + c dy^2 with (a, b, c) the
+ *   conic (inverse 2D covariance); alpha = opacity * exp(-q / 2);
+ *   colour += rgb * alpha * T, then T *= 1 - alpha, starting from T = 1;
+ *   the result is colour + T * background.
+ * The 3DGS rasteriser's thresholds apply unless exact != 0: a Gaussian with
+ * q < 0 is skipped, alpha is capped at 0.99, a Gaussian with alpha < 1/255
+ * is skipped, and a pixel stops (without that Gaussian) once T (1 - alpha)
+ * would drop below 1e-4.  Arithmetic in double.
+ *
+ * conic_opacity[4g..4g+3] = a, b, c, opacity; rgb[4g..4g+2] = colour.
+ * values/ranges are a sorted frame (oracle_sort_frame).  Outputs per pixel,
+ * row-major, colour planar [3][H][W]: out_color, out_T (final T), n_contrib
+ * (Gaussians composited) and margin (the smallest relative distance of an
+ * evaluated alpha to 1/255 or of T (1 - alpha) to 1e-4; 1 if none) -- any
+ * output may be NULL. */
+int oracle_render(const oracle_frame* f, const float* conic_opacity, const float* rgb, const uint32_t* values,
+                  const uint32_t* ranges, const double background[3], int exact, double* out_color,
+                  double* out_T, uint32_t* n_contrib, double* margin);
+
 #ifdef __cplusplus
 }
 #endif

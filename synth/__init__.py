@@ -187,6 +187,39 @@ def make_frame(spec: FrameSpec, seed: int, frame_index: int = 0) -> np.ndarray:
     return rec
 
 
+_V_S1, _V_S2, _V_THETA, _V_OPACITY, _V_RGB = range(16, 21)
+
+
+def make_render_attrs(records: np.ndarray, seed: int, frame_index: int = 0) -> tuple:
+    """Per-Gaussian render inputs for ``records`` (frame ``frame_index`` of
+    stream ``seed``): ``(conic_opacity, rgb)``, float32 [N, 4] each.
+
+    The 2D covariance has principal standard deviations s1 = (r/3) U(0.6, 1)
+    and s2 = s1 U(0.25, 1) (so the record's radius r still bounds 3 s1) at an
+    angle U(0, pi); the conic is its inverse (a, b, c) = (Syy, -Sxy, Sxx)/det.
+    Opacity U(0.05, 0.99); colour U(0, 1) per channel; the fourth colour
+    component is 0."""
+    n = len(records)
+    key = stream_key(seed, frame_index, 1 << 23)
+    r = records["radius"].astype(np.float64)
+    s1 = np.maximum(r, 1.0) / 3.0 * (0.6 + 0.4 * uniform01(stream_key(key, _V_S1), n))
+    s2 = s1 * (0.25 + 0.75 * uniform01(stream_key(key, _V_S2), n))
+    th = math.pi * uniform01(stream_key(key, _V_THETA), n)
+    cs, sn = np.cos(th), np.sin(th)
+    sxx = s1 * s1 * cs * cs + s2 * s2 * sn * sn
+    syy = s1 * s1 * sn * sn + s2 * s2 * cs * cs
+    sxy = (s1 * s1 - s2 * s2) * sn * cs
+    det = sxx * syy - sxy * sxy
+    conic_opacity = np.empty((n, 4), np.float32)
+    conic_opacity[:, 0] = syy / det
+    conic_opacity[:, 1] = -sxy / det
+    conic_opacity[:, 2] = sxx / det
+    conic_opacity[:, 3] = 0.05 + 0.94 * uniform01(stream_key(key, _V_OPACITY), n)
+    rgb = np.zeros((n, 4), np.float32)
+    rgb[:, :3] = uniform01(stream_key(key, _V_RGB), 3 * n).reshape(n, 3)
+    return conic_opacity, rgb
+
+
 # ----------------------------------------------------------------------------
 # the benchmark workloads
 # ----------------------------------------------------------------------------

@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="fullhd-1m",
                    choices=sorted(synth.FRAME_WORKLOADS) + sorted(synth.SUPPLEMENTARY_WORKLOADS)
-                   + ["batch-64", "serve", "sweep"])
+                   + ["batch-64", "serve", "sweep", "render"])
     p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
     p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
@@ -88,7 +88,7 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     stats = _rows(os.path.join(d, "stats", "*kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics, workload {workload}",
              "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
-             "python3 bench.py --steps 20 --warmup 5 --no-cpu-baseline",
+             f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline",
              f"pass-kernel source sha256[:16]: {source_hash()}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -101,6 +101,8 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
                      f"{float(r['Percentage']):.1f} |")
     with open(os.path.join(PROFILES, f"kernel_stats_{workload}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    if not os.path.isdir(os.path.join(d, "fetch")):
+        return   # kernel times only (e.g. the render workload, which is ALU-bound)
 
     def short_name(name):
         return name.replace("ss::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
@@ -331,6 +333,72 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+RENDER_FLOPS_PER_EVAL = 18   # dy 1, quadratic form 4, scale 1, exp 1, alpha 1, cap 1, T 2, weight 1, colour 6
+
+
+def bench_render(args):
+    """Alpha blending of the sorted full-HD frame (the step after the sort):
+    frames/s with the records, render inputs and sorted lists resident in HBM."""
+    import torch
+    import paper_2511_16298_amd as ss
+
+    spec, seed = synth.workload("fullhd-1m")
+    rec = synth.make_frame(spec, seed)
+    co, cl = synth.make_render_attrs(rec, seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    d = ss.records_to_device(rec, dev)
+    srt = ss.sort_frame(d, spec.width, spec.height)
+    st, M = srt.result()
+    assert st == 0
+    cod, cld = ss.render_attrs_to_device(co, cl, dev)
+    bg = (0.0, 0.0, 0.0)
+    r = ss.Renderer(spec.width, spec.height, device=dev)
+    for _ in range(args.warmup):
+        r(d, cod, cld, srt.values, srt.tile_ranges, srt.status, bg)
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    ev[0].record(stream)
+    for i in range(K):
+        r(d, cod, cld, srt.values, srt.tile_ranges, srt.status, bg)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+    ms = ev[0].elapsed_time(ev[K]) / K
+    # evaluations (pixel, Gaussian) the method performs, from the counting variant
+    rs = ss.Renderer(spec.width, spec.height, device=dev, want_T=True, want_contrib=True, want_tile_evals=True)
+    rs(d, cod, cld, srt.values, srt.tile_ranges, srt.status, bg)
+    torch.cuda.synchronize()
+    evals = int(rs.out.tile_evals.cpu().numpy().view(np.uint32).astype(np.int64).sum())
+    tflops = RENDER_FLOPS_PER_EVAL * evals / (ms * 1e-3) / 1e12
+    line = {"metric": "rendered frames/s (alpha blending of a sorted frame, FP32)", "value": 1e3 / ms,
+            "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"render fullhd-1m: {spec.width}x{spec.height}, N={len(rec)}, M={M} sorted pairs, "
+                                   f"synthetic conic/opacity/colour (seed {seed}), 3DGS thresholds",
+                       "parallelism": "single GPU"},
+            "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
+            "roofline": {"bound": "alu", "kernel": "k_render", "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s",
+                         "frac": tflops / 157.3, "traffic": None, "evaluations": evals,
+                         "flops_per_evaluation": RENDER_FLOPS_PER_EVAL}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        o = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+        ref = oracle.render(spec.width, spec.height, rec, co, cl, o.values, o.ranges, bg)
+        spent = time.perf_counter() - t
+        gpu = rs.out.color.cpu().numpy().astype(np.float64)
+        ok = ref.margin >= 1e-4
+        tol = 2e-6 + 2.4e-7 * ref.n_contrib.astype(np.float64)
+        line["cpu_baseline"] = {"value": 1.0 / spent, "unit": "frames/s", "cores": 1, "kind": "oracle",
+                                "sample": f"one fullhd-1m frame, oracle sort + FP64 render ({spent:.1f} s, single-threaded)"}
+        line["parity_vs_oracle"] = bool(np.all((np.abs(gpu - ref.color).max(axis=0) <= tol)[ok]))
+        line["parity_unambiguous_pixels"] = float(ok.mean())
+    print(json.dumps(line), flush=True)
+
+
 def bench_sweep(args):
     """Sort alone (step a4 through ss_sort_pairs) over random 45-bit keys, the
     paper's random key-value sweep extended to 10^8 pairs."""
@@ -393,11 +461,12 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
-    if args.workload in ("batch-64", "serve", "sweep"):
+    if args.workload in ("batch-64", "serve", "sweep", "render"):
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
-        {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep}[args.workload](args)
+        {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
+         "render": bench_render}[args.workload](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "

@@ -280,6 +280,47 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
 ss_status ss_copy_bytes(void* d_dst, const void* d_src, size_t bytes, void* stream,
                         const ss_options* options);
 
+/* ---------------------------------------------------------------------------
+ * Rendering (the step after the sort; paper: Background, "Rendering", and
+ * Design, "Efficient Tile-Based Rendering").  Every pixel of a 16x16 tile
+ * composites the tile's sorted Gaussians front to back by alpha blending, with
+ * the compositing rule of 3D Gaussian Splatting that the paper builds on:
+ * pixel (x, y) is sampled at (x + 1/2, y + 1/2) in the frame of the means
+ * (mean_x / 16, mean_y / 16); d = mean - sample; q = a dx^2 + 2 b dx dy +
+ * c dy^2 with the conic (a, b, c) = inverse 2D covariance; alpha = opacity *
+ * exp(-q / 2); colour += rgb * alpha * T, T *= 1 - alpha from T = 1; the pixel
+ * gets colour + T * background.  Unless SS_RENDER_EXACT is set, the
+ * rasteriser's thresholds apply: q < 0 is skipped, alpha is capped at 0.99,
+ * alpha < 1/255 is skipped, and a pixel stops before a Gaussian that would
+ * take T below 1e-4.  FP32 arithmetic.
+ * ------------------------------------------------------------------------- */
+#define SS_RENDER_EXACT 1u
+
+typedef struct ss_render_desc {
+  uint32_t struct_size;         /* sizeof(ss_render_desc) */
+  uint32_t flags;               /* SS_RENDER_* */
+  const float* conic_opacity;   /* device [N][4]: a, b, c, opacity (16-B aligned) */
+  const float* rgb;             /* device [N][4]: r, g, b, unused (16-B aligned) */
+  const uint32_t* values;       /* device: the frame's sorted Gaussian indices */
+  const uint32_t* tile_ranges;  /* device [2T]: the frame's tile ranges */
+  const uint32_t* status;       /* device status of the sort, or NULL; when it
+                                   does not read SS_OK nothing is written */
+  float background[3];
+  float* out_color;             /* device [3][H][W] planar, row-major */
+  float* out_T;                 /* device [H][W] final transmittance, or NULL */
+  uint32_t* out_contrib;        /* device [H][W] Gaussians composited, or NULL */
+  uint32_t* out_tile_evals;     /* device [T] (pixel, Gaussian) evaluations per
+                                   tile (the arithmetic done), or NULL */
+  ss_timer* timer;              /* optional (kind SS_KERNEL_RENDER) */
+} ss_render_desc;
+
+/* Renders one sorted frame: `frame` gives the image size and the records
+ * (the means), `desc` the render inputs and outputs; values and ranges are
+ * those of an ss_sort_frame call on the same frame (one workgroup wave per
+ * tile; nothing else is read or written).  Errors: SS_ERR_INVALID_ARGUMENT for
+ * a NULL or misaligned pointer or an unknown flag. */
+ss_status ss_render_frame(const ss_frame* frame, const ss_render_desc* desc, void* stream);
+
 typedef enum ss_kernel_kind {
   SS_KERNEL_CLEAR = 0,      /* zeroes counters and look-back state */
   SS_KERNEL_COUNT_DUP = 1,  /* direct: a1+a2+a3 fused; depth-first: a1 (counts, keys) */
@@ -291,7 +332,8 @@ typedef enum ss_kernel_kind {
                                their digit bases from the histograms) */
   SS_KERNEL_DEPTH_PASS = 7, /* depth-first: one pass of the Gaussian depth sort */
   SS_KERNEL_EXPAND = 8,     /* depth-first: pairs in depth order */
-  SS_KERNEL_KINDS = 9
+  SS_KERNEL_RENDER = 9,     /* ss_render_frame */
+  SS_KERNEL_KINDS = 10
 } ss_kernel_kind;
 
 /* Event pool for per-kernel timing.  Create once (host), pass in

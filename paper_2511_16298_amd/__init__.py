@@ -17,7 +17,8 @@ from . import _abi
 from ._abi import (SS_ALGO_AUTO, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
-__all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "sort_frame", "count_pairs", "sort_pairs", "copy_bytes", "Timer",
+__all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "Renderer", "render_attrs_to_device", "sort_frame",
+           "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
            "SS_ALGO_DIRECT"]
 
@@ -386,6 +387,50 @@ def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, it
                             work.data_ptr(), ws, _stream_handle(stream), opts)
     check(st, "ss_sort_pairs")
     return ko, vo
+
+
+@dataclasses.dataclass
+class RenderOutput:
+    color: "object"        # float32 [3, H, W]
+    T: "object"            # float32 [H, W] or None
+    contrib: "object"      # int32 [H, W] or None
+    tile_evals: "object"   # int32 [T] or None
+
+
+class Renderer:
+    """Pre-allocated outputs for repeated ``ss_render_frame`` calls on frames
+    of one size (alpha blending over a sorted frame's tile lists)."""
+
+    def __init__(self, width: int, height: int, device="cuda", want_T: bool = False,
+                 want_contrib: bool = False, want_tile_evals: bool = False):
+        torch = _torch()
+        self.width, self.height = width, height
+        tx, ty, _ = geometry(width, height)
+        self.out = RenderOutput(
+            torch.empty((3, height, width), dtype=torch.float32, device=device),
+            torch.empty((height, width), dtype=torch.float32, device=device) if want_T else None,
+            torch.empty((height, width), dtype=torch.int32, device=device) if want_contrib else None,
+            torch.empty(tx * ty, dtype=torch.int32, device=device) if want_tile_evals else None)
+
+    def __call__(self, records, conic_opacity, rgb, values, tile_ranges, status=None, background=(0.0, 0.0, 0.0),
+                 exact: bool = False, stream=None, timer: Optional[Timer] = None) -> RenderOutput:
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+        f = _frame(records, self.width, self.height)
+        o = self.out
+        d = _abi.make_render_desc(ptr(conic_opacity), ptr(rgb), ptr(values), ptr(tile_ranges), ptr(o.color),
+                                  ptr(status), background, exact, ptr(o.T), ptr(o.contrib), ptr(o.tile_evals),
+                                  timer.handle if timer is not None else None)
+        check(_abi.ss_render_frame(f, d, _stream_handle(stream)), "ss_render_frame")
+        return o
+
+
+def render_attrs_to_device(conic_opacity, rgb, device="cuda"):
+    """float32 [N, 4] numpy arrays as device tensors."""
+    import numpy as np
+    torch = _torch()
+    return (torch.from_numpy(np.ascontiguousarray(conic_opacity, dtype=np.float32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.float32)).to(device))
 
 
 def copy_bytes(dst, src, nbytes: int, stream=None, timer: Optional[Timer] = None):

@@ -32,6 +32,8 @@ SS_KERNEL_HIST = 5
 SS_KERNEL_DIGIT_BASES = 6
 SS_KERNEL_DEPTH_PASS = 7
 SS_KERNEL_EXPAND = 8
+SS_KERNEL_RENDER = 9
+SS_RENDER_EXACT = 1
 
 SS_ALGO_AUTO = 0
 SS_ALGO_DEPTH_FIRST = 1
@@ -121,6 +123,14 @@ class ss_plan_desc(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("autotune", ctypes.c_uint32),
                 ("tune_repeats", ctypes.c_uint32), ("options", ss_options)]
 
+class ss_render_desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("conic_opacity", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("tile_ranges", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("background", ctypes.c_float * 3), ("out_color", ctypes.c_void_p), ("out_T", ctypes.c_void_p),
+                ("out_contrib", ctypes.c_void_p), ("out_tile_evals", ctypes.c_void_p), ("timer", ctypes.c_void_p)]
+
+
 _SIGNATURES = {
     "ss_abi_version": ([], _U32),
     "ss_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -153,6 +163,7 @@ _SIGNATURES = {
     "ss_sort_pairs": ([_P, _P, _U32, _U32, _P, _P, _P, _SZ, _P, ctypes.POINTER(ss_options)],
                       ctypes.c_int),
     "ss_copy_bytes": ([_P, _P, _SZ, _P, ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_render_frame": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_render_desc), _P], ctypes.c_int),
     "ss_timer_create": ([ctypes.POINTER(_P), _U32], ctypes.c_int),
     "ss_timer_reset": ([_P], ctypes.c_int),
     "ss_timer_read": ([_P, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)], ctypes.c_int),
@@ -349,6 +360,23 @@ def ss_sort_pairs(keys_in, values_in, n, key_bits, keys_out, values_out, workspa
                   options=None):
     return lib().ss_sort_pairs(keys_in, values_in, n, key_bits, keys_out, values_out, workspace, workspace_bytes,
                                stream, ctypes.byref(options) if options is not None else None)
+
+
+def make_render_desc(conic_opacity, rgb, values, tile_ranges, out_color, status=None, background=(0.0, 0.0, 0.0),
+                     exact=False, out_T=None, out_contrib=None, out_tile_evals=None, timer=None) -> ss_render_desc:
+    d = ss_render_desc()
+    d.struct_size = ctypes.sizeof(ss_render_desc)
+    d.flags = SS_RENDER_EXACT if exact else 0
+    d.conic_opacity, d.rgb, d.values, d.tile_ranges = conic_opacity, rgb, values, tile_ranges
+    d.status, d.out_color, d.out_T, d.out_contrib = status, out_color, out_T, out_contrib
+    d.out_tile_evals, d.timer = out_tile_evals, timer
+    for i in range(3):
+        d.background[i] = float(background[i])
+    return d
+
+
+def ss_render_frame(frame, desc, stream):
+    return lib().ss_render_frame(ctypes.byref(frame), ctypes.byref(desc), stream)
 
 
 def ss_copy_bytes(dst, src, nbytes, stream, options=None):

@@ -520,6 +520,41 @@ extern "C" {
 
 uint32_t ss_abi_version(void) { return SS_ABI_VERSION; }
 
+ss_status ss_render_frame(const ss_frame* frame, const ss_render_desc* desc, void* stream) {
+  using namespace ss;
+  Geometry g;
+  SS_TRY(frame_geometry(frame, &g));
+  if (desc == nullptr || desc->struct_size < sizeof(ss_render_desc)) return SS_ERR_INVALID_ARGUMENT;
+  if ((desc->flags & ~SS_RENDER_EXACT) != 0) return SS_ERR_INVALID_ARGUMENT;
+  if (desc->out_color == nullptr || desc->tile_ranges == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  if (frame->num_gaussians > 0 &&
+      (desc->conic_opacity == nullptr || desc->rgb == nullptr || desc->values == nullptr))
+    return SS_ERR_INVALID_ARGUMENT;
+  if (!aligned(desc->conic_opacity, 16) || !aligned(desc->rgb, 16) || !aligned(desc->out_color, 4) ||
+      !aligned(desc->tile_ranges, 4) || !aligned(desc->values, 4))
+    return SS_ERR_INVALID_ARGUMENT;
+  RenderArgs a{};
+  a.gaussians = frame->gaussians;
+  a.conic_opacity = desc->conic_opacity;
+  a.rgb = desc->rgb;
+  a.values = desc->values;
+  a.ranges = desc->tile_ranges;
+  a.status = desc->status;
+  a.width = frame->width;
+  a.height = frame->height;
+  a.tiles_x = g.tiles_x;
+  a.tiles_y = g.tiles_y;
+  for (int c = 0; c < 3; ++c) a.bg[c] = desc->background[c];
+  a.color = desc->out_color;
+  a.T = desc->out_T;
+  a.contrib = desc->out_contrib;
+  a.tile_evals = desc->out_tile_evals;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Launcher L(s, desc->timer);
+  return L.run(SS_KERNEL_RENDER,
+               [&] { return launch_render(a, (desc->flags & SS_RENDER_EXACT) != 0, s); });
+}
+
 const char* ss_status_string(ss_status s) {
   switch (s) {
     case SS_OK: return "ok";

@@ -153,6 +153,23 @@ hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s);
 
+// Render (see render.hip).
+struct RenderArgs {
+  const ss_gaussian2d* gaussians;
+  const float* conic_opacity;   // [N][4]
+  const float* rgb;             // [N][4]
+  const uint32_t* values;
+  const uint32_t* ranges;       // [2T]
+  const uint32_t* status;       // or NULL
+  uint32_t width, height, tiles_x, tiles_y;
+  float bg[3];
+  float* color;                 // [3][H][W]
+  float* T;                     // [H][W] or NULL
+  uint32_t* contrib;            // [H][W] or NULL
+  uint32_t* tile_evals;         // [T] or NULL
+};
+hipError_t launch_render(const RenderArgs& a, bool exact, hipStream_t s);
+
 // Sort-pass configurations (radix width, items per thread, workgroup size)
 // compiled into the library.
 bool pass_config_supported(int radix_bits, int items, int threads);

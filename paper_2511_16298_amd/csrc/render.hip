@@ -1,0 +1,159 @@
+// Rendering: per-tile alpha blending over the sorted tile lists (paper:
+// Background, "Rendering"; Design, "Efficient Tile-Based Rendering" -- one
+// workgroup per 16x16 tile, several pixels per thread, colour channels
+// unrolled).  On MI355X one wave64 owns one tile: lane l holds the four
+// pixels l, l + 64, l + 128, l + 192 of the tile (rows l/16, l/16 + 4, ...).
+// Every 64 list entries the lanes load one Gaussian each (mean, conic and
+// opacity, colour); the wave then walks them in order, each Gaussian's nine
+// values broadcast from its lane with readlane (no LDS, no barrier), and
+// every lane blends its four pixels.  The wave leaves the list as soon as all
+// 256 pixels have stopped.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ss {
+namespace {
+
+constexpr uint32_t kRenderWaves = 4;  // tiles per workgroup
+constexpr float kMaxAlpha = 0.99f;
+constexpr float kMinAlpha = 1.0f / 255.0f;
+constexpr float kMinT = 1e-4f;
+
+__device__ __forceinline__ float bcast(float v, uint32_t lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// EXACT: no thresholds.  STATS: also count the Gaussians composited per pixel
+// and the evaluations per tile.  A pixel that has stopped keeps its T with the
+// sign bit set (T > 0 means live), so the thresholds cost selects, not
+// branches, and the lanes never diverge.
+template <bool EXACT, bool STATS>
+__global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
+  if (a.status && *a.status != SS_OK) return;
+  const uint32_t lane = lane_id();
+  const uint32_t tile = blockIdx.x * kRenderWaves + threadIdx.x / kWave;
+  if (tile >= a.tiles_x * a.tiles_y) return;  // uniform over the wave
+  const uint32_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+
+  // sample points of this lane's four pixels
+  const float sx = static_cast<float>(tx * 16 + (lane & 15)) + 0.5f;
+  float sy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sy[k] = static_cast<float>(ty * 16 + (lane >> 4) + 4 * k) + 0.5f;
+
+  float T[4], cr[4], cg[4], cb[4];
+  uint32_t n[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T[k] = 1.0f;
+    cr[k] = cg[k] = cb[k] = 0.0f;
+    n[k] = 0;
+  }
+  uint32_t evals = 0;
+
+  for (uint32_t b = start; b < end; b += kWave) {
+    // one Gaussian per lane
+    float gx = 0.f, gy = 0.f, ca = 0.f, cbv = 0.f, cc = 0.f, op = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+    if (b + lane < end) {
+      const uint32_t gi = a.values[b + lane];
+      const int2 m = *reinterpret_cast<const int2*>(a.gaussians + gi);
+      gx = static_cast<float>(m.x) * (1.0f / 16.0f);
+      gy = static_cast<float>(m.y) * (1.0f / 16.0f);
+      const float4 co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
+      const float4 cl = reinterpret_cast<const float4*>(a.rgb)[gi];
+      ca = co.x;
+      cbv = co.y;
+      cc = co.z;
+      op = co.w;
+      r = cl.x;
+      g = cl.y;
+      bl = cl.z;
+    }
+    const uint32_t count = end - b < kWave ? end - b : kWave;
+    bool any_live = true;
+    for (uint32_t j = 0; j < count && any_live; ++j) {
+      const float Gx = bcast(gx, j), Gy = bcast(gy, j);
+      const float A = bcast(ca, j), B = bcast(cbv, j), C = bcast(cc, j), O = bcast(op, j);
+      const float R = bcast(r, j), Gc = bcast(g, j), Bl = bcast(bl, j);
+      // q = A dx^2 + 2 B dx dy + C dy^2 = qa + dy (2 B dx + C dy): the dx
+      // terms are shared by the lane's four pixels (one column)
+      const float dx = Gx - sx;
+      const float qa = A * dx * dx;
+      const float qb = 2.0f * B * dx;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float dy = Gy - sy[k];
+        const float q = fmaf(dy, fmaf(C, dy, qb), qa);
+        const float e = O * __expf(-0.5f * q);
+        if (EXACT) {
+          const float w = e * T[k];
+          cr[k] = fmaf(R, w, cr[k]);
+          cg[k] = fmaf(Gc, w, cg[k]);
+          cb[k] = fmaf(Bl, w, cb[k]);
+          T[k] = fmaf(-e, T[k], T[k]);
+          if (STATS) ++n[k];
+        } else {
+          const float alpha = fminf(kMaxAlpha, e);
+          if (STATS) evals += T[k] > 0.0f ? 1u : 0u;
+          const float ae = (q >= 0.0f && alpha >= kMinAlpha && T[k] > 0.0f) ? alpha : 0.0f;
+          const float next = fmaf(-ae, T[k], T[k]);
+          const bool stop = next < kMinT;         // also true for a pixel already stopped
+          const float w = stop ? 0.0f : ae * T[k];
+          cr[k] = fmaf(R, w, cr[k]);
+          cg[k] = fmaf(Gc, w, cg[k]);
+          cb[k] = fmaf(Bl, w, cb[k]);
+          T[k] = stop ? -fabsf(T[k]) : next;
+          if (STATS) n[k] += w != 0.0f ? 1u : 0u;
+        }
+      }
+      if (EXACT) {
+        if (STATS) evals += 4;
+      } else {
+        any_live = ballot(fmaxf(fmaxf(T[0], T[1]), fmaxf(T[2], T[3])) > 0.0f) != 0;
+      }
+    }
+    if (!any_live) break;
+  }
+
+  const uint32_t W = a.width, H = a.height;
+  const size_t plane = static_cast<size_t>(W) * H;
+  const uint32_t px = tx * 16 + (lane & 15);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t py = ty * 16 + (lane >> 4) + 4 * k;
+    const float t = fabsf(T[k]);
+    if (px < W && py < H) {
+      const size_t o = static_cast<size_t>(py) * W + px;
+      a.color[o] = cr[k] + t * a.bg[0];
+      a.color[plane + o] = cg[k] + t * a.bg[1];
+      a.color[2 * plane + o] = cb[k] + t * a.bg[2];
+      if (a.T) a.T[o] = t;
+      if (STATS && a.contrib) a.contrib[o] = n[k];
+    }
+  }
+  if (STATS && a.tile_evals) {
+    // sum over the wave of the per-lane evaluation counts
+    uint32_t e = evals;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) e += __shfl_xor(e, d, kWave);
+    if (lane == 0) a.tile_evals[tile] = e;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_render(const RenderArgs& a, bool exact, hipStream_t s) {
+  const uint32_t tiles = a.tiles_x * a.tiles_y;
+  const uint32_t blocks = (tiles + kRenderWaves - 1) / kRenderWaves;
+  if (blocks == 0) return hipSuccess;
+  const dim3 g(blocks), t(kRenderWaves * kWave);
+  const bool stats = a.contrib != nullptr || a.tile_evals != nullptr;
+  if (exact && stats) hipLaunchKernelGGL((k_render<true, true>), g, t, 0, s, a);
+  else if (exact) hipLaunchKernelGGL((k_render<true, false>), g, t, 0, s, a);
+  else if (stats) hipLaunchKernelGGL((k_render<false, true>), g, t, 0, s, a);
+  else hipLaunchKernelGGL((k_render<false, false>), g, t, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ss

@@ -189,3 +189,28 @@ def test_server_and_count_argument_errors():
     assert _abi.ss_batch_count_pairs(fr, 1 << 9, 1 << 10, 1 << 11, 1 << 20, need - 1, None) == _abi.SS_ERR_WORKSPACE
     st, need = _abi.ss_plan_workspace_bytes(fr, 1000)
     assert st == _abi.SS_OK and need > 0
+
+
+def test_render_argument_errors_are_synchronous():
+    f = frame(64, 32, n=10, ptr=1 << 12)
+    a = 1 << 20
+    good = dict(conic_opacity=a, rgb=2 * a, values=3 * a, tile_ranges=4 * a, out_color=5 * a)
+
+    def call(fr=f, struct_size=None, flags=0, **kw):
+        args = dict(good)
+        args.update(kw)
+        d = _abi.make_render_desc(args["conic_opacity"], args["rgb"], args["values"], args["tile_ranges"],
+                                  args["out_color"])
+        d.flags = flags
+        if struct_size is not None:
+            d.struct_size = struct_size
+        return _abi.ss_render_frame(fr, d, None)
+
+    bad = _abi.SS_ERR_INVALID_ARGUMENT
+    assert call(struct_size=8) == bad
+    assert call(flags=2) == bad
+    assert call(out_color=None) == bad
+    assert call(tile_ranges=None) == bad
+    assert call(conic_opacity=None) == bad and call(rgb=None) == bad and call(values=None) == bad
+    assert call(conic_opacity=a + 8) == bad and call(rgb=2 * a + 4) == bad
+    assert call(fr=frame(0, 32, n=10, ptr=1 << 12)) == bad

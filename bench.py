@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
+    p.add_argument("--algorithm", default="depth-first", choices=["depth-first", "direct", "bitonic"],
+                   help="frame sort algorithm (frames, sweep)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle baseline (whole frames until exceeded)")
@@ -418,7 +420,7 @@ def bench_sweep(args):
         vi = torch.from_numpy(vals.view(np.int32)).to(dev)
         del keys, vals
         ko, vo = torch.empty_like(ki), torch.empty_like(vi)
-        opts = ss.make_options()
+        opts = ss.make_options(algorithm=ss.SS_ALGO_BITONIC if args.algorithm == "bitonic" else 0)
         st, ws = _abi.ss_sort_pairs_workspace_bytes(m, key_bits, opts)
         assert st == 0
         work = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
@@ -485,8 +487,10 @@ def main():
     _, _, m_t, s_t = ss.count_pairs(d, spec.width, spec.height)
     assert int(s_t.item()) == 0
     M = int(m_t.item()) & 0xFFFFFFFF
+    algo = {"depth-first": ss.SS_ALGO_DEPTH_FIRST, "direct": ss.SS_ALGO_DIRECT,
+            "bitonic": ss.SS_ALGO_BITONIC}[args.algorithm]
     sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev,
-                            workgroup_size=args.wg)
+                            workgroup_size=args.wg, algorithm=algo)
     tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
     rb = args.radix_bits or 8
     passes = -(-key_bits // rb)
@@ -573,7 +577,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {spec.width}x{spec.height} image, 16x16 tiles "
                                f"({tx}x{ty}={tx * ty}), N={N} projected Gaussians, seed {seed}",
-                   "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "path": "depth-first",
+                   "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "path": args.algorithm,
                    "depth_passes": 4, "tile_passes": tile_passes, "parallelism": "single GPU"},
         "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99), "max": max(step_ms)},
         "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,

@@ -100,7 +100,7 @@ typedef struct ss_options {
                               supported, else 256); 512 needs radix_bits 8
                               and items 8 or 16.  A pass tile holds
                               workgroup_size * items_per_thread pairs. */
-  uint32_t algorithm;      /* SS_ALGO_*; both give bit-identical results */
+  uint32_t algorithm;      /* SS_ALGO_*; all give bit-identical frame results */
 } ss_options;
 
 /* SS_ALGO_DIRECT: duplicate in index order, then ceil((ceil(log2 T) + 32) /
@@ -114,6 +114,15 @@ typedef struct ss_options {
 #define SS_ALGO_AUTO 0u
 #define SS_ALGO_DEPTH_FIRST 1u
 #define SS_ALGO_DIRECT 2u
+/* SS_ALGO_BITONIC: the paper's own sort (Background, "Sorting"; Design,
+ * "Sorting Optimizations in Context of 3DGS"): duplicate in index order, then
+ * a bitonic network over the pairs padded to a power of two, comparing
+ * (key, value); partner steps below 4,096 elements run fused in LDS, longer
+ * ones three at a time.  Frames only (not batches); in ss_sort_pairs it
+ * orders by (key bits [0, key_bits), value), which equals the stable order
+ * when the values of equal keys increase in input order.  Workspace grows to
+ * the padded size. */
+#define SS_ALGO_BITONIC 3u
 
 /* Stop after step a3: keys/values receive the duplicated pairs in
  * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no

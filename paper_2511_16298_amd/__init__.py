@@ -14,13 +14,13 @@ import dataclasses
 from typing import Optional
 
 from . import _abi
-from ._abi import (SS_ALGO_AUTO, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
+from ._abi import (SS_ALGO_AUTO, SS_ALGO_BITONIC, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
 __all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "Renderer", "render_attrs_to_device", "sort_frame",
            "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
-           "SS_ALGO_DIRECT"]
+           "SS_ALGO_DIRECT", "SS_ALGO_BITONIC"]
 
 
 def _torch():
@@ -371,13 +371,14 @@ def sort_frame(records, width: int, height: int, capacity: Optional[int] = None,
 
 
 def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, items_per_thread: int = 0,
-               timer: Optional[Timer] = None, workgroup_size: int = 0):
+               timer: Optional[Timer] = None, workgroup_size: int = 0, algorithm: int = 0):
     """Step a4 alone: stable sort of (int64 keys, int32 values) by key bits
-    [0, key_bits).  Returns new (keys, values) tensors."""
+    [0, key_bits) (``SS_ALGO_BITONIC``: by (key bits, value)).  Returns new
+    (keys, values) tensors."""
     torch = _torch()
     n = int(keys.shape[0])
     opts = make_options(radix_bits, items_per_thread, timer.handle if timer is not None else None,
-                        workgroup_size=workgroup_size)
+                        workgroup_size=workgroup_size, algorithm=algorithm)
     st, ws = _abi.ss_sort_pairs_workspace_bytes(n, key_bits, opts)
     check(st, "ss_sort_pairs_workspace_bytes")
     work = torch.empty(max(ws, 256), dtype=torch.uint8, device=keys.device)

@@ -38,6 +38,7 @@ SS_RENDER_EXACT = 1
 SS_ALGO_AUTO = 0
 SS_ALGO_DEPTH_FIRST = 1
 SS_ALGO_DIRECT = 2
+SS_ALGO_BITONIC = 3
 SS_MAX_BATCH_FRAMES = 256
 
 SS_FLAG_UNSORTED = 1

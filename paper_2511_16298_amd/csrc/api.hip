@@ -35,7 +35,7 @@ ss_status parse_options(const ss_options* o, Options* out) {
   if (o == nullptr) return SS_OK;
   if (o->struct_size < sizeof(ss_options)) return SS_ERR_INVALID_ARGUMENT;
   if ((o->flags & ~SS_FLAG_UNSORTED) != 0) return SS_ERR_UNSUPPORTED;
-  if (o->algorithm > SS_ALGO_DIRECT) return SS_ERR_UNSUPPORTED;
+  if (o->algorithm > SS_ALGO_BITONIC) return SS_ERR_UNSUPPORTED;
   out->flags = o->flags;
   out->algorithm = o->algorithm;
   if (o->radix_bits != 0) out->radix_bits = o->radix_bits;
@@ -88,7 +88,7 @@ T* at(void* ws, size_t off) {
 // histograms | pass look-back] zeroed per call, then the alternate buffers.
 // ---------------------------------------------------------------------------
 struct Layout {
-  uint32_t npasses = 0, bins = 0, count_blocks = 0, pass_blocks = 0, tile = 0;
+  uint32_t npasses = 0, bins = 0, count_blocks = 0, pass_blocks = 0, tile = 0, log_pad = 0;
   size_t scan_lb = 0, hist = 0, pass_lb = 0, scalars = 0, bases = 0, clear_end = 0;
   size_t alt_keys = 0, alt_vals = 0, total = 0;
 };
@@ -96,7 +96,11 @@ struct Layout {
 Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const Options& o) {
   Layout L;
   L.bins = 1u << o.radix_bits;
-  L.npasses = (key_bits + o.radix_bits - 1) / o.radix_bits;
+  const bool bitonic = o.algorithm == SS_ALGO_BITONIC;
+  // the bitonic network sorts in place in the (power-of-two padded) alternate buffers
+  L.npasses = bitonic ? 0u : (key_bits + o.radix_bits - 1) / o.radix_bits;
+  L.log_pad = bitonic ? bitonic_log_size(capacity > 2 ? capacity : 2) : 0u;
+  const size_t alt = bitonic ? (size_t{1} << L.log_pad) : capacity;
   L.count_blocks = n_gauss == 0 ? 1u : (n_gauss + kCountTile - 1) / kCountTile;
   L.tile = o.threads * o.items;
   L.pass_blocks = (capacity + L.tile - 1) / L.tile;
@@ -107,8 +111,8 @@ Layout make_layout(uint32_t n_gauss, uint32_t capacity, uint32_t key_bits, const
   L.hist = off;      off = align_up(off + static_cast<size_t>(kHistCopies) * L.npasses * L.bins * sizeof(uint32_t));
   L.pass_lb = off;   off = align_up(off + static_cast<size_t>(L.npasses) * L.pass_blocks * L.bins * sizeof(uint32_t));
   L.clear_end = off;
-  L.alt_keys = off;  off = align_up(off + static_cast<size_t>(capacity) * sizeof(uint64_t));
-  L.alt_vals = off;  off = align_up(off + static_cast<size_t>(capacity) * sizeof(uint32_t));
+  L.alt_keys = off;  off = align_up(off + alt * sizeof(uint64_t));
+  L.alt_vals = off;  off = align_up(off + alt * sizeof(uint32_t));
   L.total = off;
   return L;
 }
@@ -293,15 +297,22 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   uint32_t* d_status = out->status ? out->status : scal + 0;
   uint32_t* d_num_pairs = out->num_pairs ? out->num_pairs : scal + 1;
   const bool unsorted = (o.flags & SS_FLAG_UNSORTED) != 0;
+  const bool bitonic = o.algorithm == SS_ALGO_BITONIC && !unsorted;
   const uint32_t P = unsorted ? 0 : lay.npasses;
   // dup writes buf[0]; pass p reads buf[p % 2] and writes buf[(p + 1) % 2];
-  // the data ends in buf[P % 2], which must be the caller's output.
+  // the data ends in buf[P % 2], which must be the caller's output.  The
+  // bitonic network instead sorts the padded alternate buffer in place and
+  // its last kernel writes the output.
   uint64_t* bk[2];
   uint32_t* bv[2];
   bk[P % 2] = out->keys;
   bv[P % 2] = out->values;
   bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
   bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
+  if (bitonic) {
+    bk[0] = at<uint64_t>(ws, lay.alt_keys);
+    bv[0] = at<uint32_t>(ws, lay.alt_vals);
+  }
 
   SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, nullptr, nullptr, s); }));
   CountDupArgs a{};
@@ -322,6 +333,15 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   a.nblocks = lay.count_blocks;
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
   if (unsorted) return SS_OK;
+  if (bitonic) {
+    BitonicArgs b{bk[0], bv[0], lay.log_pad, d_num_pairs, 0, d_status, out->keys, out->values, cap};
+    SS_TRY(L.run_group(SS_KERNEL_SORT_PASS, bitonic_launches(lay.log_pad), [&] {
+      return launch_bitonic(b, nullptr, nullptr, ~0ull, s) == hipSuccess ? SS_OK : SS_ERR_HIP;
+    }));
+    return L.run(SS_KERNEL_RANGES, [&] {
+      return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
+    });
+  }
   uint32_t* bases = at<uint32_t>(ws, lay.bases);
   std::vector<const void*> ks(P);
   std::vector<const uint32_t*> vs(P);
@@ -475,8 +495,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   });
 }
 
+// Duplication in index order: the direct radix path, the bitonic network and
+// the unsorted stage.
 bool use_direct(const Options& o) {
-  return o.algorithm == SS_ALGO_DIRECT || (o.flags & SS_FLAG_UNSORTED) != 0;
+  return o.algorithm == SS_ALGO_DIRECT || o.algorithm == SS_ALGO_BITONIC || (o.flags & SS_FLAG_UNSORTED) != 0;
 }
 
 FrameInfo frame_info(const ss_frame* f, const Geometry& g, uint32_t gauss_base, uint32_t tile_base) {
@@ -765,6 +787,16 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
   if (n == 0) return SS_OK;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);
+  if (o.algorithm == SS_ALGO_BITONIC) {
+    // order by (key bits [0, key_bits), value): the stable order when the
+    // values of equal keys increase in input order (e.g. input positions)
+    const uint64_t mask = key_bits == 64 ? ~0ull : (1ull << key_bits) - 1;
+    BitonicArgs b{at<uint64_t>(workspace, lay.alt_keys), at<uint32_t>(workspace, lay.alt_vals), lay.log_pad,
+                  nullptr, n, nullptr, keys_out, values_out, n};
+    return L.run_group(SS_KERNEL_SORT_PASS, bitonic_launches(lay.log_pad), [&] {
+      return launch_bitonic(b, keys_in, values_in, mask, s) == hipSuccess ? SS_OK : SS_ERR_HIP;
+    });
+  }
   SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(workspace, lay.clear_end, nullptr, nullptr, nullptr, s); }));
   HistArgs h{keys_in, n, lay.npasses, at<uint32_t>(workspace, lay.hist)};
   SS_TRY(L.run(SS_KERNEL_HIST, [&] { return launch_hist(h, static_cast<int>(o.radix_bits), s); }));

@@ -170,6 +170,26 @@ struct RenderArgs {
 };
 hipError_t launch_render(const RenderArgs& a, bool exact, hipStream_t s);
 
+// The paper's bitonic network (see bitonic.hip), over a power-of-two padded
+// buffer sorted in place by (key, value).
+struct BitonicArgs {
+  uint64_t* keys;               // [2^log_n] padded buffer
+  uint32_t* vals;
+  uint32_t log_n;
+  const uint32_t* num_pairs;    // device count of valid entries, or NULL (then n_fixed)
+  uint32_t n_fixed;
+  const uint32_t* status;       // or NULL
+  uint64_t* out_keys;           // the last kernel writes the valid entries here
+  uint32_t* out_vals;
+  uint32_t out_capacity;
+};
+uint32_t bitonic_log_size(uint64_t n);          // smallest l >= 1 with 2^l >= n
+uint32_t bitonic_launches(uint32_t log_n);
+// Pads (and, with src_k, first loads src[0, n) with keys masked by key_mask),
+// then sorts and writes the first n entries to out_*.
+hipError_t launch_bitonic(const BitonicArgs& a, const uint64_t* src_k, const uint32_t* src_v, uint64_t key_mask,
+                          hipStream_t s);
+
 // Sort-pass configurations (radix width, items per thread, workgroup size)
 // compiled into the library.
 bool pass_config_supported(int radix_bits, int items, int threads);

@@ -167,10 +167,24 @@ def test_batch_argument_errors():
 
 def test_algorithm_option_validated():
     f = frame(n=10, ptr=1 << 12)
-    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=3))[0] == _abi.SS_ERR_UNSUPPORTED
+    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=4))[0] == _abi.SS_ERR_UNSUPPORTED
     a = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=1))
     b = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=2))
     assert a[0] == b[0] == _abi.SS_OK and a[1] != b[1]
+
+
+def test_bitonic_workspace_holds_the_padded_size():
+    f = frame(n=10, ptr=1 << 12)
+    direct = _abi.ss_workspace_bytes(f, 5000, _abi.make_options(algorithm=_abi.SS_ALGO_DIRECT))[1]
+    bit = _abi.ss_workspace_bytes(f, 5000, _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))
+    assert bit[0] == _abi.SS_OK and bit[1] >= 8192 * 12
+    assert _abi.ss_workspace_bytes(f, 8192, _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))[1] == \
+        _abi.ss_workspace_bytes(f, 5000, _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))[1]
+    assert direct > 0
+    # batches take the radix paths only
+    assert _abi.ss_batch_workspace_bytes([frame(n=10, ptr=1 << 12)], 100,
+                                         _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))[0] == \
+        _abi.SS_ERR_UNSUPPORTED
 
 
 def test_server_and_count_argument_errors():

@@ -29,7 +29,7 @@ def u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT]
+ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT, ss.SS_ALGO_BITONIC]
 
 
 def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False, algorithm=0):
@@ -234,3 +234,16 @@ def test_repeated_runs_are_identical(algo):
             h.update(t.cpu().numpy().tobytes())
         digests.add(h.hexdigest())
     assert len(digests) == 1
+
+
+@pytest.mark.parametrize("n,key_bits", [(1, 45), (4095, 13), (4097, 45), (100_003, 45), (65_536, 64),
+                                        (300_000, 32), (1 << 20, 45)])
+def test_bitonic_sort_pairs_orders_by_key_then_value(n, key_bits):
+    keys, _ = synth.sort_sweep_pairs(n, key_bits, seed=n + key_bits + 1)
+    if n > 10:
+        keys[::3] = keys[0]
+    vals = np.random.default_rng(n).permutation(n).astype(np.uint32)
+    ko, vo = ss.sort_pairs(torch.from_numpy(keys.view(np.int64)).cuda(),
+                           torch.from_numpy(vals.view(np.int32)).cuda(), key_bits, algorithm=ss.SS_ALGO_BITONIC)
+    order = np.lexsort((vals, keys))
+    assert np.array_equal(u64(ko), keys[order]) and np.array_equal(u32(vo), vals[order])

@@ -46,6 +46,25 @@ _P = ctypes.c_void_p
 _U64 = ctypes.c_uint64
 
 
+class _Camera(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_double * 12), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("tan_fovx", ctypes.c_double),
+                ("tan_fovy", ctypes.c_double), ("cam_pos", ctypes.c_double * 3), ("near_plane", ctypes.c_double),
+                ("sh_degree", ctypes.c_uint32)]
+
+
+def camera(view, fx, fy, cx, cy, tan_fovx, tan_fovy, cam_pos, near, sh_degree) -> _Camera:
+    c = _Camera()
+    v = np.asarray(view, np.float64).reshape(12)
+    for i in range(12):
+        c.view[i] = v[i]
+    c.fx, c.fy, c.cx, c.cy, c.tan_fovx, c.tan_fovy = fx, fy, cx, cy, tan_fovx, tan_fovy
+    for i in range(3):
+        c.cam_pos[i] = cam_pos[i]
+    c.near_plane, c.sh_degree = near, sh_degree
+    return c
+
+
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         build(out=path)
@@ -59,8 +78,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.oracle_ranges.argtypes = [_P, _U64, _U64, _P]
     lib.oracle_sort_frame.argtypes = [fp, _U64, _P, _P, _P, _P, _P, _P, _P, _P]
     lib.oracle_render.argtypes = [fp, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
+    lib.oracle_preprocess.argtypes = [ctypes.POINTER(_Camera), ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P]
+    lib.oracle_sh_basis.argtypes = [_P, _P]
+    lib.oracle_sh_basis.restype = None
     for f in (lib.oracle_tile_grid, lib.oracle_count, lib.oracle_scan, lib.oracle_duplicate,
-              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame, lib.oracle_render):
+              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame, lib.oracle_render, lib.oracle_preprocess):
         f.restype = ctypes.c_int
     return lib
 
@@ -218,6 +240,38 @@ def render(width: int, height: int, records: np.ndarray, conic_opacity: np.ndarr
     st = lib().oracle_render(ctypes.byref(fr), _ptr(co), _ptr(cl), _ptr(vals), _ptr(rng), _ptr(bg), int(exact),
                              _ptr(color), _ptr(T), _ptr(k), _ptr(margin))
     return RenderResult(st, color, T, k, margin)
+
+
+@dataclasses.dataclass
+class PreprocessResult:
+    status: int
+    records: np.ndarray        # RECORD-like structured array (mean_x, mean_y, depth, radius)
+    conic_opacity: np.ndarray  # float64 [n, 4]
+    rgb: np.ndarray            # float64 [n, 4]
+    margin: np.ndarray         # float64 [n, 3]: rounding margins of 16x, 16y, 3 sqrt(lambda)
+
+
+def preprocess(cam: _Camera, mean3d_opacity: np.ndarray, cov3d: np.ndarray, sh: np.ndarray) -> PreprocessResult:
+    """3D Gaussians to sort records, conic/opacity and colour (oracle_preprocess)."""
+    m3 = np.ascontiguousarray(mean3d_opacity, dtype=np.float32).reshape(-1, 4)
+    cv = np.ascontiguousarray(cov3d, dtype=np.float32).reshape(-1, 8)
+    shc = np.ascontiguousarray(sh, dtype=np.float32).reshape(-1, 48)
+    n = len(m3)
+    rec = np.zeros(n, dtype=np.dtype([("mean_x", "<i4"), ("mean_y", "<i4"), ("depth", "<f4"), ("radius", "<u4")]))
+    co = np.zeros((n, 4), np.float64)
+    rgb = np.zeros((n, 4), np.float64)
+    mg = np.zeros((n, 3), np.float64)
+    st = lib().oracle_preprocess(ctypes.byref(cam), n, _ptr(m3), _ptr(cv), _ptr(shc), _ptr(rec), _ptr(co), _ptr(rgb),
+                                 _ptr(mg))
+    return PreprocessResult(st, rec, co, rgb, mg)
+
+
+def sh_basis(direction) -> np.ndarray:
+    """The 16 real spherical harmonics (degree <= 3) at a unit direction."""
+    d = np.ascontiguousarray(direction, dtype=np.float64).reshape(3)
+    out = np.zeros(16, np.float64)
+    lib().oracle_sh_basis(_ptr(d), _ptr(out))
+    return out
 
 
 @dataclasses.dataclass

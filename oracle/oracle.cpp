@@ -285,4 +285,146 @@ int oracle_render(const oracle_frame* f, const float* conic_opacity, const float
   return ORACLE_OK;
 }
 
+// Associated Legendre function P_l^m(x), m >= 0, with the Condon-Shortley
+// phase (-1)^m, by the standard recurrences.
+static double assoc_legendre(int l, int m, double x) {
+  double pmm = 1.0;
+  if (m > 0) {
+    const double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+    double f = 1.0;
+    for (int i = 1; i <= m; ++i) {
+      pmm *= -f * s;
+      f += 2.0;
+    }
+  }
+  if (l == m) return pmm;
+  double pmmp1 = x * (2 * m + 1) * pmm;
+  if (l == m + 1) return pmmp1;
+  double pll = 0.0;
+  for (int ll = m + 2; ll <= l; ++ll) {
+    pll = (x * (2 * ll - 1) * pmmp1 - (ll + m - 1) * pmm) / (ll - m);
+    pmm = pmmp1;
+    pmmp1 = pll;
+  }
+  return pll;
+}
+
+static double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+void oracle_sh_basis(const double d[3], double out[16]) {
+  // real SH: Y_l0 = K_l0 P_l^0(cos t); Y_lm = sqrt(2) K_lm cos(m phi) P_l^m(cos t)
+  // and Y_l,-m = sqrt(2) K_lm sin(m phi) P_l^m(cos t), m > 0, with
+  // K_lm = sqrt((2l + 1) / (4 pi) (l - m)! / (l + m)!); cos t = z, phi = atan2(y, x)
+  const double pi = 3.14159265358979323846;
+  const double ct = d[2], phi = std::atan2(d[1], d[0]);
+  int idx = 0;
+  for (int l = 0; l <= 3; ++l) {
+    for (int m = -l; m <= l; ++m) {
+      const int am = std::abs(m);
+      const double K = std::sqrt((2 * l + 1) / (4 * pi) * factorial(l - am) / factorial(l + am));
+      const double P = assoc_legendre(l, am, ct);
+      double y;
+      if (m == 0) y = K * P;
+      else if (m > 0) y = std::sqrt(2.0) * K * std::cos(m * phi) * P;
+      else y = std::sqrt(2.0) * K * std::sin(am * phi) * P;
+      out[idx++] = y;
+    }
+  }
+}
+
+int oracle_preprocess(const oracle_camera* cam, uint32_t n, const float* mean3d_opacity, const float* cov3d,
+                      const float* sh, oracle_gaussian* records, double* conic_opacity, double* rgb,
+                      double* margin) {
+  if (cam == nullptr || cam->sh_degree > 3 || (n > 0 && (mean3d_opacity == nullptr || cov3d == nullptr)))
+    return ORACLE_ERR_INVALID_ARGUMENT;
+  if (cam->sh_degree > 0 || rgb != nullptr)
+    if (n > 0 && sh == nullptr) return ORACLE_ERR_INVALID_ARGUMENT;
+  const double* V = cam->view;
+  for (uint32_t g = 0; g < n; ++g) {
+    const double p[3] = {mean3d_opacity[4 * g], mean3d_opacity[4 * g + 1], mean3d_opacity[4 * g + 2]};
+    const double opacity = mean3d_opacity[4 * g + 3];
+    double t[3];
+    for (int r = 0; r < 3; ++r) t[r] = V[4 * r] * p[0] + V[4 * r + 1] * p[1] + V[4 * r + 2] * p[2] + V[4 * r + 3];
+    oracle_gaussian rec{0, 0, static_cast<float>(t[2]), 0};
+    double co[4] = {0, 0, 0, 0}, col[3] = {0, 0, 0}, mg[3] = {1, 1, 1};
+    bool culled = t[2] <= cam->near_plane;
+    double a = 0, b = 0, c = 0, det = 0, x = 0, y = 0;
+    if (!culled) {
+      x = cam->fx * t[0] / t[2] + cam->cx;
+      y = cam->fy * t[1] / t[2] + cam->cy;
+      // projection Jacobian at t, with x/z and y/z clamped to 1.3 tan(fov/2)
+      const double lx = 1.3 * cam->tan_fovx, ly = 1.3 * cam->tan_fovy;
+      const double tx = std::min(lx, std::max(-lx, t[0] / t[2])) * t[2];
+      const double ty = std::min(ly, std::max(-ly, t[1] / t[2])) * t[2];
+      const double J[2][3] = {{cam->fx / t[2], 0.0, -cam->fx * tx / (t[2] * t[2])},
+                              {0.0, cam->fy / t[2], -cam->fy * ty / (t[2] * t[2])}};
+      const float* cv = cov3d + 8 * g;
+      const double S[3][3] = {{cv[0], cv[1], cv[2]}, {cv[1], cv[3], cv[4]}, {cv[2], cv[4], cv[5]}};
+      double M[2][3];  // J R
+      for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 3; ++k) M[i][k] = J[i][0] * V[k] + J[i][1] * V[4 + k] + J[i][2] * V[8 + k];
+      double C[2][2];  // M S M^T
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          double acc = 0.0;
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) acc += M[i][k] * S[k][l] * M[j][l];
+          C[i][j] = acc;
+        }
+      a = C[0][0] + 0.3;
+      b = C[0][1];
+      c = C[1][1] + 0.3;
+      det = a * c - b * b;
+      if (det == 0.0) culled = true;
+    }
+    if (!culled) {
+      const double mid = 0.5 * (a + c);
+      const double l1 = mid + std::sqrt(std::max(0.1, mid * mid - det));
+      const double l2 = mid - std::sqrt(std::max(0.1, mid * mid - det));
+      const double r3 = 3.0 * std::sqrt(std::max(l1, l2));
+      rec.radius = static_cast<uint32_t>(std::ceil(r3));
+      mg[2] = std::fabs(r3 - std::nearbyint(r3));
+      const double X = std::min(1073741824.0, std::max(-1073741824.0, 16.0 * x));
+      const double Y = std::min(1073741824.0, std::max(-1073741824.0, 16.0 * y));
+      rec.mean_x = static_cast<int32_t>(std::nearbyint(X));   // current rounding mode: half to even
+      rec.mean_y = static_cast<int32_t>(std::nearbyint(Y));
+      mg[0] = std::fabs(std::fabs(X - std::floor(X)) - 0.5);
+      mg[1] = std::fabs(std::fabs(Y - std::floor(Y)) - 0.5);
+      co[0] = c / det;
+      co[1] = -b / det;
+      co[2] = a / det;
+      co[3] = opacity;
+      // colour from the spherical harmonics of the viewing direction
+      double d[3] = {p[0] - cam->cam_pos[0], p[1] - cam->cam_pos[1], p[2] - cam->cam_pos[2]};
+      const double len = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (double& v : d) v /= len;
+      double basis[16];
+      oracle_sh_basis(d, basis);
+      const int nb = (static_cast<int>(cam->sh_degree) + 1) * (static_cast<int>(cam->sh_degree) + 1);
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.5;
+        for (int k = 0; k < nb; ++k) acc += sh[48 * static_cast<size_t>(g) + 3 * k + ch] * basis[k];
+        col[ch] = std::max(0.0, acc);
+      }
+    } else {
+      rec.mean_x = rec.mean_y = 0;
+      rec.radius = 0;
+    }
+    if (records) records[g] = rec;
+    if (conic_opacity)
+      for (int i = 0; i < 4; ++i) conic_opacity[4 * static_cast<size_t>(g) + i] = co[i];
+    if (rgb) {
+      for (int i = 0; i < 3; ++i) rgb[4 * static_cast<size_t>(g) + i] = col[i];
+      rgb[4 * static_cast<size_t>(g) + 3] = 0.0;
+    }
+    if (margin)
+      for (int i = 0; i < 3; ++i) margin[3 * static_cast<size_t>(g) + i] = mg[i];
+  }
+  return ORACLE_OK;
+}
+
 }  // extern "C"

@@ -105,6 +105,47 @@ int oracle_render(const oracle_frame* f, const float* conic_opacity, const float
                   const uint32_t* ranges, const double background[3], int exact, double* out_color,
                   double* out_T, uint32_t* n_contrib, double* margin);
 
+/* Preprocess (the step before the sort; paper: Background, "Preprocessing",
+ * and Design, "Variable Packing" with its input and output group tables):
+ * 3D Gaussians (mean and opacity, 3D covariance, spherical-harmonic colour)
+ * and a pinhole camera in; per Gaussian out the 16-byte record of the sort
+ * (2D mean in 1/16 px, depth, radius), the conic and opacity, and the colour.
+ * It follows 3D Gaussian Splatting (Kerbl et al. 2023), which the paper
+ * builds on:
+ *   t = R p + T (camera frame); culled (radius 0) when t.z <= near;
+ *   pixel = (fx t.x / t.z + cx, fy t.y / t.z + cy);
+ *   2D covariance = J R S R^T J^T + 0.3 I, with the projection's Jacobian J at
+ *   t, its x/z and y/z clamped to 1.3 tan(fov/2) on each axis;
+ *   culled when that covariance is singular; conic = its inverse;
+ *   radius = ceil(3 sqrt(largest eigenvalue)), the eigenvalue taken as
+ *   mid + sqrt(max(0.1, mid^2 - det)), mid = half the trace;
+ *   colour = max(0, 1/2 + sum over SH degrees <= sh_degree of coefficient *
+ *   real spherical harmonic (with the Condon-Shortley phase) of the unit
+ *   direction from the camera centre to p).
+ * mean3d_opacity [n][4]; cov3d [n][8] = xx, xy, xz, yy, yz, zz, -, -;
+ * sh [n][48] = 16 coefficients x RGB, in (l, m = -l..l) order.  Outputs:
+ * records (mean rounded half-to-even to 1/16 px), conic_opacity [n][4],
+ * rgb [n][4] (double), and margin [n][3]: the distance of 16 x and 16 y to
+ * a rounding boundary (in 1/16 px) and of 3 sqrt(eigenvalue) to an integer;
+ * culled Gaussians get radius 0, zero conic and colour.  Arithmetic in
+ * double; any output may be NULL. */
+typedef struct {
+  double view[12];            /* [R | T], row-major 3 x 4 */
+  double fx, fy, cx, cy;      /* focal lengths and principal point, pixels */
+  double tan_fovx, tan_fovy;  /* half-angle tangents */
+  double cam_pos[3];          /* camera centre in world coordinates */
+  double near_plane;
+  uint32_t sh_degree;         /* 0 .. 3 */
+} oracle_camera;
+
+int oracle_preprocess(const oracle_camera* cam, uint32_t n, const float* mean3d_opacity, const float* cov3d,
+                      const float* sh, oracle_gaussian* records, double* conic_opacity, double* rgb,
+                      double* margin);
+
+/* The real spherical harmonics (Condon-Shortley phase) used above, degree
+ * <= 3, at unit direction d: out[16] in (l, m = -l..l) order. */
+void oracle_sh_basis(const double d[3], double out[16]);
+
 #ifdef __cplusplus
 }
 #endif

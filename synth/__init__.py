@@ -221,6 +221,77 @@ def make_render_attrs(records: np.ndarray, seed: int, frame_index: int = 0) -> t
 
 
 # ----------------------------------------------------------------------------
+# 3D scenes (inputs of the preprocessing step)
+# ----------------------------------------------------------------------------
+
+_V_P3, _V_SCALE, _V_QUAT, _V_OPAC3, _V_SH = range(32, 37)
+
+
+@dataclasses.dataclass(frozen=True)
+class Camera:
+    """Pinhole camera looking down +z from the origin (world = camera frame
+    up to ``view``): pixel = focal * (x / z, y / z) + centre."""
+    width: int
+    height: int
+    focal: float
+    near: float = 0.2
+    sh_degree: int = 3
+
+    @property
+    def view(self) -> np.ndarray:
+        """World-to-camera [R | t], 3 x 4 (identity here)."""
+        v = np.zeros((3, 4), np.float64)
+        v[:3, :3] = np.eye(3)
+        return v
+
+    @property
+    def tan_fov(self) -> tuple:
+        return self.width / (2.0 * self.focal), self.height / (2.0 * self.focal)
+
+
+def make_scene(n: int, cam: Camera, seed: int) -> dict:
+    """``n`` 3D Gaussians in front of ``cam``: positions uniform in the view
+    frustum between depth 1 and 50 (10 % placed up to 1.5x beyond the image
+    edges, 2 % behind the near plane), log-normal scales (median 0.0015 z, about
+    2 px on screen),
+    uniformly random rotations (normalised Gaussian quaternions), opacity
+    U(0.05, 0.99), degree-3 SH coefficients N(0, 0.3) with the DC term
+    N(0.5, 0.5).  Returns float32 arrays: mean3d_opacity [n, 4], cov3d [n, 8]
+    (xx, xy, xz, yy, yz, zz, 0, 0) and sh [n, 48] (16 coefficients x RGB)."""
+    key = stream_key(seed, 0, 1 << 24)
+    u = uniform01(stream_key(key, _V_P3), 3 * n).reshape(n, 3)
+    z = np.exp(np.log(1.0) + (np.log(50.0) - np.log(1.0)) * u[:, 2])
+    tx, ty = cam.tan_fov
+    spread = np.where(uniform01(stream_key(key, _V_P3 + 100), n) < 0.1, 1.5, 1.0)
+    x = (2.0 * u[:, 0] - 1.0) * tx * z * spread
+    y = (2.0 * u[:, 1] - 1.0) * ty * z * spread
+    z = np.where(uniform01(stream_key(key, _V_P3 + 200), n) < 0.02, -z, z)
+    sc = 0.0015 * np.abs(z)[:, None] * np.exp(0.5 * normal(stream_key(key, _V_SCALE), 3 * n).reshape(n, 3))
+    q = normal(stream_key(key, _V_QUAT), 4 * n).reshape(n, 4)
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, qx, qy, qz = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.stack([np.stack([1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - w * qz), 2 * (qx * qz + w * qy)], -1),
+                  np.stack([2 * (qx * qy + w * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - w * qx)], -1),
+                  np.stack([2 * (qx * qz - w * qy), 2 * (qy * qz + w * qx), 1 - 2 * (qx * qx + qy * qy)], -1)], 1)
+    M = R * sc[:, None, :]
+    S = M @ np.transpose(M, (0, 2, 1))
+    m3 = np.zeros((n, 4), np.float32)
+    m3[:, 0], m3[:, 1], m3[:, 2] = x, y, z
+    m3[:, 3] = 0.05 + 0.94 * uniform01(stream_key(key, _V_OPAC3), n)
+    cov = np.zeros((n, 8), np.float32)
+    cov[:, 0], cov[:, 1], cov[:, 2] = S[:, 0, 0], S[:, 0, 1], S[:, 0, 2]
+    cov[:, 3], cov[:, 4], cov[:, 5] = S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]
+    sh = (0.3 * normal(stream_key(key, _V_SH), 48 * n)).reshape(n, 16, 3)
+    sh[:, 0, :] = 0.5 + 0.5 * normal(stream_key(key, _V_SH + 100), 3 * n).reshape(n, 3)
+    return {"mean3d_opacity": m3, "cov3d": cov, "sh": sh.reshape(n, 48).astype(np.float32)}
+
+
+#: the preprocessing workload: a full-HD view of 10^6 Gaussians (seed 1006)
+SCENE_CAMERA = Camera(1920, 1080, focal=1400.0)
+SCENE_SEED = 1006
+
+
+# ----------------------------------------------------------------------------
 # the benchmark workloads
 # ----------------------------------------------------------------------------
 

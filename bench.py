@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="fullhd-1m",
                    choices=sorted(synth.FRAME_WORKLOADS) + sorted(synth.SUPPLEMENTARY_WORKLOADS)
-                   + ["batch-64", "serve", "sweep", "render"])
+                   + ["batch-64", "serve", "sweep", "render", "preprocess"])
     p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
     p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
@@ -401,6 +401,108 @@ def bench_render(args):
     print(json.dumps(line), flush=True)
 
 
+# bytes one Gaussian moves through the preprocess kernel at SH degree 3:
+# mean + opacity 16, covariance row 32 (24 used, padded to 16-byte loads),
+# 48 SH floats 192 in; record 16, conic + opacity 16, colour 16 out
+PREPROCESS_BYTES = 16 + 32 + 192 + 48
+
+
+def bench_preprocess(args):
+    """Projection of 10^6 synthetic 3D Gaussians for a full-HD camera (the step
+    before the sort): Gaussians/s with the scene resident in HBM, and the same
+    frame carried on through the sort (preprocess + sort per frame)."""
+    import torch
+    import paper_2511_16298_amd as ss
+    from paper_2511_16298_amd import _abi
+
+    cam = synth.SCENE_CAMERA
+    n = 1_000_000
+    scene = synth.make_scene(n, cam, synth.SCENE_SEED)
+    params = synth.camera_params(cam)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    m3, cv, sh = (torch.from_numpy(scene[k]).to(dev) for k in ("mean3d_opacity", "cov3d", "sh"))
+    c = ss.camera(**params)
+    pre = ss.Preprocessor(n, device=dev)
+    for _ in range(args.warmup):
+        pre(c, m3, cv, sh, stream)
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    ev[0].record(stream)
+    for i in range(K):
+        pre(c, m3, cv, sh, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+    ms = ev[0].elapsed_time(ev[K]) / K
+    # the kernel's own duration: HIP events around each launch, on its stream
+    timer = ss.Timer(max_launches=K + 4)
+    for _ in range(K):
+        pre(c, m3, cv, sh, stream, timer=timer)
+    torch.cuda.synchronize()
+    kms, kn = timer.read(_abi.SS_KERNEL_PREPROCESS)
+    timer.close()
+    kern_us = 1e3 * kms / kn
+    achieved = PREPROCESS_BYTES * n / (kern_us * 1e-6) / 1e9
+    out = pre(c, m3, cv, sh, stream)
+    torch.cuda.synchronize()
+    # the frame carried through the sort: preprocess + depth-first sort
+    recs = out.records
+    _, _, m_t, s_t = ss.count_pairs(recs, cam.width, cam.height)
+    assert int(s_t.item()) == 0
+    M = int(m_t.item()) & 0xFFFFFFFF
+    sorter = ss.FrameSorter(cam.width, cam.height, n, M, device=dev)
+    for _ in range(args.warmup):
+        pre(c, m3, cv, sh, stream)
+        sorter(recs, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        pre(c, m3, cv, sh, stream)
+        sorter(recs, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    chain_ms = e0.elapsed_time(e1) / K
+    st, m_chk = sorter.out.result()
+    assert st == 0 and m_chk == M
+    line = {"metric": "preprocessed Gaussians/s (projection of 3D Gaussians, FP32)", "value": n / (ms * 1e-3),
+            "unit": "Gaussians/s", "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"preprocess scene-1m: N={n} 3D Gaussians (seed {synth.SCENE_SEED}), "
+                                   f"{cam.width}x{cam.height} camera, focal {cam.focal}, SH degree {cam.sh_degree}",
+                       "parallelism": "single GPU"},
+            "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
+            "roofline": {"bound": "hbm", "kernel": "k_preprocess", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                         "bytes_per_launch": PREPROCESS_BYTES * n, "avg_launch_us": kern_us},
+            "frame_with_sort": {"ms_per_frame": chain_ms, "num_pairs": M,
+                                "pairs_per_s": M / (chain_ms * 1e-3)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        oc = oracle.camera(np.asarray(params["view"], np.float64).reshape(3, 4), params["fx"], params["fy"],
+                           params["cx"], params["cy"], params["tan_fovx"], params["tan_fovy"], params["cam_pos"],
+                           params["near_plane"], params["sh_degree"])
+        runs, spent = 0, 0.0
+        while spent < args.cpu_seconds or runs == 0:
+            t = time.perf_counter()
+            o = oracle.preprocess(oc, scene["mean3d_opacity"], scene["cov3d"], scene["sh"])
+            spent += time.perf_counter() - t
+            runs += 1
+        g = out.records.cpu().numpy().view(np.uint32).reshape(-1, 4)
+        same = np.all(g == o.records.view(np.uint32).reshape(-1, 4), axis=1)
+        # records may differ only where the oracle sits next to a rounding boundary
+        near_boundary = np.any(o.margin < 0.01, axis=1) | (np.abs(scene["mean3d_opacity"][:, 2] -
+                                                                  params["near_plane"]) < 1e-3)
+        line["cpu_baseline"] = {"value": runs * n / spent, "unit": "Gaussians/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{runs} whole scene-1m projections ({spent:.1f} s, single-threaded "
+                                          f"FP64 oracle)"}
+        line["records_bit_equal"] = float(same.mean())
+        line["parity_vs_oracle"] = bool(np.all(same | near_boundary))
+    print(json.dumps(line), flush=True)
+
 def bench_sweep(args):
     """Sort alone (step a4 through ss_sort_pairs) over random 45-bit keys, the
     paper's random key-value sweep extended to 10^8 pairs."""
@@ -463,12 +565,12 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
-    if args.workload in ("batch-64", "serve", "sweep", "render"):
+    if args.workload in ("batch-64", "serve", "sweep", "render", "preprocess"):
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
-         "render": bench_render}[args.workload](args)
+         "render": bench_render, "preprocess": bench_preprocess}[args.workload](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "

@@ -330,6 +330,59 @@ typedef struct ss_render_desc {
  * a NULL or misaligned pointer or an unknown flag. */
 ss_status ss_render_frame(const ss_frame* frame, const ss_render_desc* desc, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Preprocessing (the step before the sort; paper: Background,
+ * "Preprocessing", and Design, "Variable Packing" with its input and output
+ * group tables: mean and opacity, 3D covariance and spherical-harmonic
+ * coefficients in; 2D mean, depth and radius together, conic and opacity,
+ * colour out), with the projection rule of 3D Gaussian Splatting that the
+ * paper builds on.  For Gaussian g with world mean p:
+ *   t = R p + T (camera frame); culled when t.z <= near_plane;
+ *   pixel = (fx t.x / t.z + cx, fy t.y / t.z + cy);
+ *   2D covariance = J R S R^T J^T + 0.3 I, where S is the 3D covariance and
+ *   J the Jacobian of the projection at t with t.x / t.z and t.y / t.z first
+ *   clamped to +-1.3 tan_fov; culled when its determinant is 0;
+ *   conic = its inverse (a, b, c) = (C11, -C01, C00) / det;
+ *   radius = ceil(3 sqrt(mid + sqrt(max(0.1, mid^2 - det)))), mid = half the
+ *   trace (3 standard deviations along the major axis);
+ *   colour = max(0, 1/2 + sum over SH degrees l <= sh_degree of coefficient
+ *   x real spherical harmonic Y_lm (with the Condon-Shortley phase) of the
+ *   unit direction from cam_pos to p), per channel.
+ * Record: mean_x/y = 16 x pixel rounded half to even (clamped to +-2^30),
+ * depth = t.z (also for culled Gaussians), radius; culled Gaussians get
+ * mean 0, radius 0, zero conic and colour.  FP32 arithmetic.
+ * ------------------------------------------------------------------------- */
+typedef struct ss_camera {
+  float view[12];            /* [R | T] world to camera, row-major 3 x 4 */
+  float fx, fy, cx, cy;      /* focal lengths and principal point, pixels */
+  float tan_fovx, tan_fovy;  /* tangents of the half field of view (> 0) */
+  float cam_pos[3];          /* camera centre in world coordinates */
+  float near_plane;
+  uint32_t sh_degree;        /* 0 .. 3 */
+} ss_camera;
+
+typedef struct ss_preprocess_desc {
+  uint32_t struct_size;          /* sizeof(ss_preprocess_desc) */
+  uint32_t num_gaussians;        /* N, 0 .. 2^31 - 1 */
+  const float* mean3d_opacity;   /* device [N][4]: x, y, z, opacity (16-B aligned) */
+  const float* cov3d;            /* device [N][8]: xx, xy, xz, yy, yz, zz, unused x2
+                                    (16-B aligned) */
+  const float* sh;               /* device [N][48]: 16 coefficients x RGB in
+                                    (l, m = -l..l) order (16-B aligned); only the
+                                    first (sh_degree + 1)^2 triples are used */
+  ss_gaussian2d* out_records;    /* device [N]: the sort's input records */
+  float* out_conic_opacity;      /* device [N][4]: a, b, c, opacity (render input) */
+  float* out_rgb;                /* device [N][4]: r, g, b, 0 (render input) */
+  ss_timer* timer;               /* optional (kind SS_KERNEL_PREPROCESS) */
+} ss_preprocess_desc;
+
+/* Projects N Gaussians (one thread each; every output element is written).
+ * Inputs must be finite.  The buffers are the caller's; nothing is allocated.
+ * Errors: SS_ERR_INVALID_ARGUMENT for a NULL or misaligned pointer, a size
+ * mismatch (struct_size), N >= 2^31, sh_degree > 3, non-positive tan_fov or a
+ * non-finite camera value; SS_ERR_HIP if the launch fails. */
+ss_status ss_preprocess(const ss_camera* camera, const ss_preprocess_desc* desc, void* stream);
+
 typedef enum ss_kernel_kind {
   SS_KERNEL_CLEAR = 0,      /* zeroes counters and look-back state */
   SS_KERNEL_COUNT_DUP = 1,  /* direct: a1+a2+a3 fused; depth-first: a1 (counts, keys) */
@@ -342,7 +395,8 @@ typedef enum ss_kernel_kind {
   SS_KERNEL_DEPTH_PASS = 7, /* depth-first: one pass of the Gaussian depth sort */
   SS_KERNEL_EXPAND = 8,     /* depth-first: pairs in depth order */
   SS_KERNEL_RENDER = 9,     /* ss_render_frame */
-  SS_KERNEL_KINDS = 10
+  SS_KERNEL_PREPROCESS = 10, /* ss_preprocess */
+  SS_KERNEL_KINDS = 11
 } ss_kernel_kind;
 
 /* Event pool for per-kernel timing.  Create once (host), pass in

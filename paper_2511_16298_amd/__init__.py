@@ -17,7 +17,8 @@ from . import _abi
 from ._abi import (SS_ALGO_AUTO, SS_ALGO_BITONIC, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
-__all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "Renderer", "render_attrs_to_device", "sort_frame",
+__all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "Renderer", "render_attrs_to_device",
+           "Preprocessor", "PreprocessOutput", "camera", "sort_frame",
            "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
            "SS_ALGO_DIRECT", "SS_ALGO_BITONIC"]
@@ -433,6 +434,50 @@ def render_attrs_to_device(conic_opacity, rgb, device="cuda"):
     return (torch.from_numpy(np.ascontiguousarray(conic_opacity, dtype=np.float32)).to(device),
             torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.float32)).to(device))
 
+
+def camera(view, fx: float, fy: float, cx: float, cy: float, tan_fovx: float, tan_fovy: float, cam_pos,
+           near_plane: float = 0.2, sh_degree: int = 3) -> _abi.ss_camera:
+    """A pinhole camera for ``Preprocessor``: ``view`` = [R | T] (3 x 4,
+    world to camera), focal lengths and principal point in pixels, tangents
+    of the half field of view, camera centre in world coordinates."""
+    return _abi.make_camera(view, fx, fy, cx, cy, tan_fovx, tan_fovy, cam_pos, near_plane, sh_degree)
+
+
+@dataclasses.dataclass
+class PreprocessOutput:
+    records: object        # (N, 4) int32: ss_gaussian2d (mean_x, mean_y, depth bits, radius)
+    conic_opacity: object  # (N, 4) float32
+    rgb: object            # (N, 4) float32
+
+
+class Preprocessor:
+    """Pre-allocated outputs for repeated ``ss_preprocess`` calls on up to
+    ``capacity`` Gaussians: the projection of 3D Gaussians to the sort's
+    records and the render's conic, opacity and colour."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        torch = _torch()
+        self.capacity = capacity
+        self.out = PreprocessOutput(torch.empty((capacity, 4), dtype=torch.int32, device=device),
+                                    torch.empty((capacity, 4), dtype=torch.float32, device=device),
+                                    torch.empty((capacity, 4), dtype=torch.float32, device=device))
+
+    def __call__(self, cam: _abi.ss_camera, mean3d_opacity, cov3d, sh, stream=None,
+                 timer: Optional[Timer] = None) -> PreprocessOutput:
+        torch = _torch()
+        n = int(mean3d_opacity.shape[0])
+        if n > self.capacity:
+            raise ValueError(f"{n} Gaussians exceed the capacity {self.capacity}")
+        for t, cols, name in ((mean3d_opacity, 4, "mean3d_opacity"), (cov3d, 8, "cov3d"), (sh, 48, "sh")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != cols or t.shape[0] != n \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous ({n}, {cols}) float32 tensor")
+        o = self.out
+        d = _abi.make_preprocess_desc(n, mean3d_opacity.data_ptr(), cov3d.data_ptr(), sh.data_ptr(),
+                                      o.records.data_ptr(), o.conic_opacity.data_ptr(), o.rgb.data_ptr(),
+                                      timer.handle if timer is not None else None)
+        check(_abi.ss_preprocess(cam, d, _stream_handle(stream)), "ss_preprocess")
+        return PreprocessOutput(o.records[:n], o.conic_opacity[:n], o.rgb[:n])
 
 def copy_bytes(dst, src, nbytes: int, stream=None, timer: Optional[Timer] = None):
     opts = make_options(timer=timer.handle if timer is not None else None)

@@ -33,6 +33,7 @@ SS_KERNEL_DIGIT_BASES = 6
 SS_KERNEL_DEPTH_PASS = 7
 SS_KERNEL_EXPAND = 8
 SS_KERNEL_RENDER = 9
+SS_KERNEL_PREPROCESS = 10
 SS_RENDER_EXACT = 1
 
 SS_ALGO_AUTO = 0
@@ -132,6 +133,19 @@ class ss_render_desc(ctypes.Structure):
                 ("out_contrib", ctypes.c_void_p), ("out_tile_evals", ctypes.c_void_p), ("timer", ctypes.c_void_p)]
 
 
+class ss_camera(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("tan_fovx", ctypes.c_float),
+                ("tan_fovy", ctypes.c_float), ("cam_pos", ctypes.c_float * 3), ("near_plane", ctypes.c_float),
+                ("sh_degree", ctypes.c_uint32)]
+
+
+class ss_preprocess_desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("num_gaussians", ctypes.c_uint32),
+                ("mean3d_opacity", ctypes.c_void_p), ("cov3d", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("out_records", ctypes.c_void_p), ("out_conic_opacity", ctypes.c_void_p),
+                ("out_rgb", ctypes.c_void_p), ("timer", ctypes.c_void_p)]
+
 _SIGNATURES = {
     "ss_abi_version": ([], _U32),
     "ss_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -165,6 +179,7 @@ _SIGNATURES = {
                       ctypes.c_int),
     "ss_copy_bytes": ([_P, _P, _SZ, _P, ctypes.POINTER(ss_options)], ctypes.c_int),
     "ss_render_frame": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_render_desc), _P], ctypes.c_int),
+    "ss_preprocess": ([ctypes.POINTER(ss_camera), ctypes.POINTER(ss_preprocess_desc), _P], ctypes.c_int),
     "ss_timer_create": ([ctypes.POINTER(_P), _U32], ctypes.c_int),
     "ss_timer_reset": ([_P], ctypes.c_int),
     "ss_timer_read": ([_P, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)], ctypes.c_int),
@@ -379,6 +394,36 @@ def make_render_desc(conic_opacity, rgb, values, tile_ranges, out_color, status=
 def ss_render_frame(frame, desc, stream):
     return lib().ss_render_frame(ctypes.byref(frame), ctypes.byref(desc), stream)
 
+
+def make_camera(view, fx, fy, cx, cy, tan_fovx, tan_fovy, cam_pos, near_plane, sh_degree) -> ss_camera:
+    """``view``: 12 floats, [R | T] row-major 3 x 4 (world to camera)."""
+    c = ss_camera()
+    v = [float(x) for x in (view.reshape(-1) if hasattr(view, "reshape") else view)]
+    if len(v) != 12:
+        raise ValueError("view must hold 12 values ([R | T], 3 x 4)")
+    for i in range(12):
+        c.view[i] = v[i]
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    c.tan_fovx, c.tan_fovy = float(tan_fovx), float(tan_fovy)
+    for i in range(3):
+        c.cam_pos[i] = float(cam_pos[i])
+    c.near_plane, c.sh_degree = float(near_plane), int(sh_degree)
+    return c
+
+
+def make_preprocess_desc(n, mean3d_opacity, cov3d, sh, out_records, out_conic_opacity, out_rgb,
+                         timer=None) -> ss_preprocess_desc:
+    d = ss_preprocess_desc()
+    d.struct_size = ctypes.sizeof(ss_preprocess_desc)
+    d.num_gaussians = n
+    d.mean3d_opacity, d.cov3d, d.sh = mean3d_opacity, cov3d, sh
+    d.out_records, d.out_conic_opacity, d.out_rgb, d.timer = out_records, out_conic_opacity, out_rgb, timer
+    return d
+
+
+def ss_preprocess(camera, desc, stream):
+    return lib().ss_preprocess(ctypes.byref(camera) if camera is not None else None,
+                               ctypes.byref(desc) if desc is not None else None, stream)
 
 def ss_copy_bytes(dst, src, nbytes, stream, options=None):
     return lib().ss_copy_bytes(dst, src, nbytes, stream, ctypes.byref(options) if options is not None else None)

@@ -2,6 +2,7 @@
 // workspace layout and the launch sequences of the hot path.
 #include <stdint.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -575,6 +576,40 @@ ss_status ss_render_frame(const ss_frame* frame, const ss_render_desc* desc, voi
   Launcher L(s, desc->timer);
   return L.run(SS_KERNEL_RENDER,
                [&] { return launch_render(a, (desc->flags & SS_RENDER_EXACT) != 0, s); });
+}
+
+ss_status ss_preprocess(const ss_camera* camera, const ss_preprocess_desc* desc, void* stream) {
+  using namespace ss;
+  if (camera == nullptr || desc == nullptr || desc->struct_size < sizeof(ss_preprocess_desc))
+    return SS_ERR_INVALID_ARGUMENT;
+  const ss_camera& c = *camera;
+  if (c.sh_degree > 3 || !(c.tan_fovx > 0.0f) || !(c.tan_fovy > 0.0f)) return SS_ERR_INVALID_ARGUMENT;
+  const float scalars[] = {c.fx, c.fy, c.cx, c.cy, c.tan_fovx, c.tan_fovy, c.near_plane,
+                           c.cam_pos[0], c.cam_pos[1], c.cam_pos[2]};
+  for (float v : scalars)
+    if (!std::isfinite(v)) return SS_ERR_INVALID_ARGUMENT;
+  for (float v : c.view)
+    if (!std::isfinite(v)) return SS_ERR_INVALID_ARGUMENT;
+  const uint32_t n = desc->num_gaussians;
+  if (n > 0x7fffffffu) return SS_ERR_INVALID_ARGUMENT;
+  if (n > 0) {
+    const void* ptrs[] = {desc->mean3d_opacity, desc->cov3d, desc->sh, desc->out_records,
+                          desc->out_conic_opacity, desc->out_rgb};
+    for (const void* q : ptrs)
+      if (q == nullptr || !aligned(q, 16)) return SS_ERR_INVALID_ARGUMENT;
+  }
+  PreprocessArgs a{};
+  a.cam = c;
+  a.n = n;
+  a.mean3d_opacity = desc->mean3d_opacity;
+  a.cov3d = desc->cov3d;
+  a.sh = desc->sh;
+  a.records = desc->out_records;
+  a.conic_opacity = desc->out_conic_opacity;
+  a.rgb = desc->out_rgb;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Launcher L(s, desc->timer);
+  return L.run(SS_KERNEL_PREPROCESS, [&] { return launch_preprocess(a, s); });
 }
 
 const char* ss_status_string(ss_status s) {

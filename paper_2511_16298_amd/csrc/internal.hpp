@@ -170,6 +170,19 @@ struct RenderArgs {
 };
 hipError_t launch_render(const RenderArgs& a, bool exact, hipStream_t s);
 
+// Preprocess: one thread per Gaussian (see preprocess.hip).
+struct PreprocessArgs {
+  ss_camera cam;
+  uint32_t n;
+  const float* mean3d_opacity;  // [N][4]
+  const float* cov3d;           // [N][8]
+  const float* sh;              // [N][48]
+  ss_gaussian2d* records;       // [N]
+  float* conic_opacity;         // [N][4]
+  float* rgb;                   // [N][4]
+};
+hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
+
 // The paper's bitonic network (see bitonic.hip), over a power-of-two padded
 // buffer sorted in place by (key, value).
 struct BitonicArgs {

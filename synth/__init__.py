@@ -286,6 +286,50 @@ def make_scene(n: int, cam: Camera, seed: int) -> dict:
     return {"mean3d_opacity": m3, "cov3d": cov, "sh": sh.reshape(n, 48).astype(np.float32)}
 
 
+def camera_params(cam: Camera, view=None, cam_pos=(0.0, 0.0, 0.0)) -> dict:
+    """The camera as the float32 values a device call receives (principal point
+    at the image centre, fx = fy = focal); both the device path and the CPU
+    check are given exactly these numbers."""
+    tx, ty = cam.tan_fov
+    v = cam.view if view is None else view
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    return {"view": [f(x) for x in np.asarray(v).reshape(12)], "fx": f(cam.focal), "fy": f(cam.focal),
+            "cx": f(cam.width / 2), "cy": f(cam.height / 2), "tan_fovx": f(tx), "tan_fovy": f(ty),
+            "cam_pos": [f(x) for x in cam_pos], "near_plane": f(cam.near), "sh_degree": cam.sh_degree}
+
+
+def pose_scene(scene: dict, seed: int, centre=(1.5, -2.0, 0.7)) -> tuple:
+    """The same Gaussians seen by a rotated camera at ``centre``: a uniformly
+    random rotation R (normalised Gaussian quaternion), world points
+    p_w = R^T p + centre and covariances R^T S R, so that the view [R | -R
+    centre] maps them back in front of the camera.  Returns (scene in world
+    coordinates, float32 view 3 x 4, centre)."""
+    q = normal(stream_key(seed, 77), 4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                  [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                  [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    C = np.asarray(centre, np.float64)
+    view = np.zeros((3, 4))
+    view[:, :3] = R
+    view[:, 3] = -R @ C
+    view = view.astype(np.float32)
+    m3 = scene["mean3d_opacity"].astype(np.float64)
+    out = dict(scene)
+    pw = m3[:, :3] @ R + C          # rows: (R^T p)^T = p^T R
+    out["mean3d_opacity"] = np.concatenate([pw, m3[:, 3:]], 1).astype(np.float32)
+    cv = scene["cov3d"].astype(np.float64)
+    S = np.stack([np.stack([cv[:, 0], cv[:, 1], cv[:, 2]], -1), np.stack([cv[:, 1], cv[:, 3], cv[:, 4]], -1),
+                  np.stack([cv[:, 2], cv[:, 4], cv[:, 5]], -1)], 1)
+    Sw = np.einsum("ji,njk,kl->nil", R, S, R)
+    c8 = np.zeros_like(scene["cov3d"])
+    c8[:, 0], c8[:, 1], c8[:, 2] = Sw[:, 0, 0], Sw[:, 0, 1], Sw[:, 0, 2]
+    c8[:, 3], c8[:, 4], c8[:, 5] = Sw[:, 1, 1], Sw[:, 1, 2], Sw[:, 2, 2]
+    out["cov3d"] = c8
+    return out, view, tuple(float(np.float32(c)) for c in C)
+
+
 #: the preprocessing workload: a full-HD view of 10^6 Gaussians (seed 1006)
 SCENE_CAMERA = Camera(1920, 1080, focal=1400.0)
 SCENE_SEED = 1006

@@ -228,3 +228,39 @@ def test_render_argument_errors_are_synchronous():
     assert call(conic_opacity=None) == bad and call(rgb=None) == bad and call(values=None) == bad
     assert call(conic_opacity=a + 8) == bad and call(rgb=2 * a + 4) == bad
     assert call(fr=frame(0, 32, n=10, ptr=1 << 12)) == bad
+
+
+def test_preprocess_argument_errors_are_synchronous():
+    a = 1 << 20
+    good = dict(mean3d_opacity=a, cov3d=2 * a, sh=3 * a, out_records=4 * a, out_conic_opacity=5 * a, out_rgb=6 * a)
+    view = [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]
+
+    def cam(**kw):
+        c = dict(view=view, fx=1000.0, fy=1000.0, cx=320.0, cy=240.0, tan_fovx=0.3, tan_fovy=0.2,
+                 cam_pos=(0, 0, 0), near_plane=0.2, sh_degree=3)
+        c.update(kw)
+        return _abi.make_camera(**c)
+
+    def call(c=None, n=10, struct_size=None, **kw):
+        args = dict(good)
+        args.update(kw)
+        d = _abi.make_preprocess_desc(n, args["mean3d_opacity"], args["cov3d"], args["sh"], args["out_records"],
+                                      args["out_conic_opacity"], args["out_rgb"])
+        if struct_size is not None:
+            d.struct_size = struct_size
+        return _abi.ss_preprocess(c if c is not None else cam(), d, None)
+
+    bad = _abi.SS_ERR_INVALID_ARGUMENT
+    assert call(struct_size=8) == bad
+    assert _abi.ss_preprocess(None, _abi.make_preprocess_desc(1, a, a, a, a, a, a), None) == bad
+    assert _abi.ss_preprocess(cam(), None, None) == bad
+    for k in good:
+        assert call(**{k: None}) == bad, k
+        assert call(**{k: good[k] + 4}) == bad, k
+    assert call(n=1 << 31) == bad
+    assert call(c=cam(sh_degree=4)) == bad
+    assert call(c=cam(tan_fovx=0.0)) == bad and call(c=cam(tan_fovy=-1.0)) == bad
+    assert call(c=cam(fx=float("inf"))) == bad and call(c=cam(near_plane=float("nan"))) == bad
+    assert call(c=cam(view=view[:11] + [float("nan")])) == bad
+    # nothing to do: no device call, no pointer needed
+    assert call(n=0, **{k: None for k in good}) == _abi.SS_OK

@@ -1,0 +1,206 @@
+"""Preprocess on the GPU (ss_preprocess) against the FP64 oracle.
+
+The kernel computes in FP32, so floating-point outputs are compared within
+bounds derived from FP32 rounding (u = 2^-24, eps = 2u), per Gaussian, from
+the oracle's own values:
+  * conic: perturbing the 2D covariance C by dC moves C^-1 by about
+    C^-1 dC C^-1, so |d conic| <= ||dC|| / lmin^2; the products J R S R^T J^T
+    carry errors of a few eps x lmax, hence 32 eps lmax / lmin^2 (+ 8 eps
+    |conic|).  Opacity is copied: exact.
+  * pixel mean: x = fx t.x / t.z + cx takes four roundings, plus the error of
+    t = R p + T (3 roundings of |R||p| + |T| per component, zero for the
+    identity view) scaled by fx / z (1 + |t.x / t.z|); bound 8 eps (...).  The
+    fixed-point mean (16 x) must then be exact wherever the oracle's distance
+    to a rounding boundary exceeds 16 times that bound, and within 1 elsewhere.
+  * radius: 3 sqrt(l1) has a relative error of a few eps (l1 from a, b, c);
+    exact where the oracle's distance of 3 sqrt(l1) to an integer exceeds
+    64 eps 3 sqrt(l1), within 1 elsewhere.
+  * colour: 1/2 + sum of sh_k Y_k, 16 products whose rounding (and that of
+    the unit direction) stays below 32 eps (1/2 + 1.1 sum |sh_k|), since
+    |Y_k| <= 1.1 for degree <= 3.
+  * depth: exact for the identity view, else 4 eps (|R_z||p| + |T_z|).
+  * culling: exact, except within the depth bound of the near plane.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_16298_amd as ss  # noqa: E402
+
+EPS = float(np.finfo(np.float32).eps)
+
+
+def oracle_camera(p):
+    return oracle.camera(np.asarray(p["view"], np.float64).reshape(3, 4), p["fx"], p["fy"], p["cx"], p["cy"],
+                         p["tan_fovx"], p["tan_fovy"], p["cam_pos"], p["near_plane"], p["sh_degree"])
+
+
+def run_gpu(p, scene, pre=None):
+    dev = "cuda"
+    m3 = torch.from_numpy(np.ascontiguousarray(scene["mean3d_opacity"])).to(dev)
+    cv = torch.from_numpy(np.ascontiguousarray(scene["cov3d"])).to(dev)
+    sh = torch.from_numpy(np.ascontiguousarray(scene["sh"])).to(dev)
+    n = m3.shape[0]
+    if pre is None:
+        pre = ss.Preprocessor(max(n, 1))
+    out = pre(ss.camera(**p), m3, cv, sh)
+    torch.cuda.synchronize()
+    rec = out.records.cpu().numpy().copy().view(np.dtype([("mean_x", "<i4"), ("mean_y", "<i4"), ("depth", "<f4"),
+                                                         ("radius", "<u4")])).reshape(-1)
+    return rec, out.conic_opacity.cpu().numpy().astype(np.float64), out.rgb.cpu().numpy().astype(np.float64)
+
+
+def compare(p, scene, gpu, label):
+    """Every output of every Gaussian against the oracle within the bounds of
+    the module docstring; returns the number of Gaussians whose integers fell
+    in an ambiguous band (and were allowed to differ by one)."""
+    o = oracle.preprocess(oracle_camera(p), scene["mean3d_opacity"], scene["cov3d"], scene["sh"])
+    assert o.status == 0
+    rec, co, rgb = gpu
+    n = len(rec)
+    V = np.asarray(p["view"], np.float64).reshape(3, 4)
+    pts = scene["mean3d_opacity"][:, :3].astype(np.float64)
+    t = pts @ V[:, :3].T + V[:, 3]
+    identity = np.array_equal(V, np.hstack([np.eye(3), np.zeros((3, 1))]))
+    mag = np.abs(pts) @ np.abs(V[:, :3]).T + np.abs(V[:, 3])      # |R||p| + |T| per component
+    # depth and culling
+    tol_z = np.zeros(n) if identity else 4 * EPS * mag[:, 2]
+    assert np.all(np.abs(rec["depth"].astype(np.float64) - o.records["depth"]) <= tol_z), label
+    near = p["near_plane"]
+    sure = np.abs(t[:, 2] - near) > tol_z + 1e-12
+    live_o = o.records["radius"] > 0
+    live_g = rec["radius"] > 0
+    assert np.array_equal(live_o[sure], live_g[sure]), label
+    dead = ~live_o & ~live_g & sure
+    assert not rec["mean_x"][dead].any() and not rec["mean_y"][dead].any(), label
+    assert not co[dead].any() and not rgb[dead].any(), label
+    live = live_o & live_g & sure
+    z = t[live, 2]
+    ambiguous = 0
+    # fixed-point mean
+    for axis, (f, c, col) in enumerate(((p["fx"], p["cx"], "mean_x"), (p["fy"], p["cy"], "mean_y"))):
+        u = t[live, axis] / z
+        pix = f * u + c
+        bound = 8 * EPS * (np.abs(f * u) + np.abs(pix) + f / z * (1 + np.abs(u)) * (mag[live, axis] + np.abs(u) *
+                                                                                    mag[live, 2]))
+        d = np.abs(rec[col][live].astype(np.int64) - o.records[col][live])
+        tight = o.margin[live, axis] <= 16 * bound
+        assert np.all(d[~tight] == 0), (label, col, np.flatnonzero(live)[~tight][d[~tight] != 0][:5])
+        assert np.all(d[tight] <= 1), (label, col)
+        ambiguous += int(np.count_nonzero(d))
+    # 2D covariance of the oracle: eigenvalues, and the radius
+    a, b, c = o.conic_opacity[live, 0], o.conic_opacity[live, 1], o.conic_opacity[live, 2]
+    det = a * c - b * b
+    A, B, C = c / det, -b / det, a / det
+    mid = 0.5 * (A + C)
+    gap = np.sqrt(0.25 * (A - C) ** 2 + B * B)
+    lmax, lmin = mid + gap, mid - gap
+    r3 = 3 * np.sqrt(mid + np.sqrt(np.maximum(0.1, gap * gap)))
+    d = np.abs(rec["radius"][live].astype(np.int64) - o.records["radius"][live].astype(np.int64))
+    tight = o.margin[live, 2] <= 64 * EPS * r3
+    assert np.all(d[~tight] == 0), (label, "radius")
+    assert np.all(d[tight] <= 1), (label, "radius")
+    ambiguous += int(np.count_nonzero(d))
+    # conic and opacity
+    tol = 32 * EPS * lmax / lmin ** 2
+    for k in range(3):
+        err = np.abs(co[live, k] - o.conic_opacity[live, k])
+        assert np.all(err <= tol + 8 * EPS * np.abs(o.conic_opacity[live, k])), (label, "conic", k, err.max())
+    assert np.array_equal(co[live, 3], o.conic_opacity[live, 3]), label
+    # colour
+    nb = (p["sh_degree"] + 1) ** 2
+    shl = np.abs(scene["sh"][live].astype(np.float64).reshape(-1, 16, 3)[:, :nb, :]).sum(1)
+    tol_c = 32 * EPS * (0.5 + 1.1 * shl)
+    assert np.all(np.abs(rgb[live, :3] - o.rgb[live, :3]) <= tol_c), (label, "rgb")
+    assert not rgb[live, 3].any()
+    return ambiguous
+
+
+def test_preprocess_full_scene():
+    """The preprocessing workload: 10^6 Gaussians, full-HD camera at the
+    origin (the benchmark's launch), every Gaussian compared."""
+    cam = synth.SCENE_CAMERA
+    scene = synth.make_scene(1_000_000, cam, synth.SCENE_SEED)
+    p = synth.camera_params(cam)
+    print("preprocess full scene n=1e6", flush=True)
+    amb = compare(p, scene, run_gpu(p, scene), "full")
+    assert amb < 2000, amb     # boundary cases are rare (about 0.1 %)
+
+
+@pytest.mark.parametrize("n", [100_003, 1, 255, 257])
+def test_preprocess_posed_camera(n):
+    """A rotated and translated camera (the view's R and T exercised) with
+    ragged sizes."""
+    cam = synth.SCENE_CAMERA
+    scene, view, centre = synth.pose_scene(synth.make_scene(n, cam, 4100 + n), seed=4200 + n)
+    p = synth.camera_params(cam, view=view, cam_pos=centre)
+    print(f"preprocess posed n={n}", flush=True)
+    compare(p, scene, run_gpu(p, scene), f"posed {n}")
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_preprocess_sh_degrees(degree):
+    """Only the first (degree + 1)^2 coefficient triples count."""
+    cam = dataclasses.replace(synth.SCENE_CAMERA, sh_degree=degree)
+    scene = synth.make_scene(4097, cam, 4300 + degree)
+    p = synth.camera_params(cam)
+    print(f"preprocess sh degree {degree}", flush=True)
+    compare(p, scene, run_gpu(p, scene), f"degree {degree}")
+    if degree < 3:
+        # garbage (NaN) beyond the used coefficients changes nothing
+        noisy = dict(scene)
+        sh = scene["sh"].copy().reshape(-1, 16, 3)
+        sh[:, (degree + 1) ** 2:, :] = np.nan
+        noisy["sh"] = sh.reshape(-1, 48)
+        a = run_gpu(p, scene)
+        b = run_gpu(p, noisy)
+        assert np.array_equal(a[2], b[2])
+
+
+def test_preprocess_empty_and_reuse():
+    """N = 0 launches nothing; a second, smaller call on the same outputs
+    returns views of its own size."""
+    cam = synth.SCENE_CAMERA
+    p = synth.camera_params(cam)
+    pre = ss.Preprocessor(5000)
+    empty = {"mean3d_opacity": np.zeros((0, 4), np.float32), "cov3d": np.zeros((0, 8), np.float32),
+             "sh": np.zeros((0, 48), np.float32)}
+    rec, co, rgb = run_gpu(p, empty, pre)
+    assert len(rec) == 0 and co.shape == (0, 4)
+    for n in (5000, 1234):
+        scene = synth.make_scene(n, cam, 4400 + n)
+        compare(p, scene, run_gpu(p, scene, pre), f"reuse {n}")
+
+
+def test_preprocess_then_sort_matches_oracle_chain():
+    """Preprocess feeding the sort on the device: wherever no Gaussian sits on
+    a rounding boundary (those are dropped from the scene using the oracle's
+    margins), the records are bit-identical and so is the whole sorted
+    frame."""
+    cam = synth.SCENE_CAMERA
+    scene = synth.make_scene(300_000, cam, 4500)
+    p = synth.camera_params(cam)
+    o = oracle.preprocess(oracle_camera(p), scene["mean3d_opacity"], scene["cov3d"], scene["sh"])
+    keep = np.all(o.margin > 0.05, axis=1) & (np.abs(scene["mean3d_opacity"][:, 2] - p["near_plane"]) > 1e-3)
+    sub = {k: np.ascontiguousarray(v[keep]) for k, v in scene.items()}
+    o = oracle.preprocess(oracle_camera(p), sub["mean3d_opacity"], sub["cov3d"], sub["sh"])
+    rec, _, _ = run_gpu(p, sub)
+    assert np.array_equal(rec.view(np.uint32).reshape(-1, 4), o.records.view(np.uint32).reshape(-1, 4))
+    dev = torch.from_numpy(rec.view(np.int32).reshape(-1, 4).copy()).cuda()
+    _, _, m, s = ss.count_pairs(dev, cam.width, cam.height)
+    assert int(s.item()) == 0
+    sorter = ss.FrameSorter(cam.width, cam.height, len(rec), int(m.item()))
+    out = sorter(dev)
+    st, M = out.result()
+    want = oracle.sort_frame(cam.width, cam.height, o.records)
+    assert st == 0 and M == want.num_pairs
+    assert np.array_equal(out.keys.cpu().numpy().view(np.uint64)[:M], want.keys)
+    assert np.array_equal(out.values.cpu().numpy().view(np.uint32)[:M], want.values)
+    assert np.array_equal(out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), want.ranges)

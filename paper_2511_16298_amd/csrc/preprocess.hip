@@ -13,6 +13,15 @@
 //   colour = max(0, 1/2 + sum of SH coefficients times the real harmonics
 //     (Condon-Shortley phase) of the direction from the camera to p).
 // One thread per Gaussian; a memory-bound stream of 240 bytes in and 48 out.
+// The 192 bytes of SH coefficients per Gaussian are the bulk.  Loaded one
+// row per lane they would touch 64 rows 192 bytes apart per instruction; each
+// wave instead reads its 64 rows in 96-byte runs (six 16-byte loads per lane
+// per half row, 1 KB per instruction), transposes them through LDS one half
+// row (24 floats) at a time, rows padded to 28 floats (16-byte aligned, and
+// 16 consecutive rows start in distinct bank groups, so the 16-byte row reads
+// do not conflict), and every lane reads its own row back.  All loads of a
+// wave are issued before its first wait; 28 KB of LDS and 90 VGPRs leave
+// five waves per SIMD.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -49,11 +58,50 @@ __device__ __forceinline__ float det2(float a, float b, float c) {
   return fmaf(a, c, -w) + e;
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kHalf = 6;          // float4 per half row
+constexpr uint32_t kRowSlots = 7;      // float4 per padded LDS row
+
+__global__ __launch_bounds__(kThreads) void k_preprocess(PreprocessArgs a) {
+  __shared__ float4 lds[kThreads / kWave][kWave * kRowSlots];
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t wave_first = g - lane;
+  const uint32_t nb = (a.cam.sh_degree + 1) * (a.cam.sh_degree + 1);
+  float4 po = make_float4(0.f, 0.f, 0.f, 0.f), s0 = po, s1 = po;
+  if (g < a.n) {
+    po = reinterpret_cast<const float4*>(a.mean3d_opacity)[g];
+    s0 = reinterpret_cast<const float4*>(a.cov3d)[2 * static_cast<size_t>(g)];
+    s1 = reinterpret_cast<const float4*>(a.cov3d)[2 * static_cast<size_t>(g) + 1];
+  }
+  // half h of the wave's rows: its float4 f = 64 q + lane (q < 6) is part
+  // f % 6 of row f / 6; only parts holding a coefficient below nb are loaded
+  const float4* src = reinterpret_cast<const float4*>(a.sh) + static_cast<size_t>(wave_first) * 12;
+  float4 ld[2 * kHalf];
+#pragma unroll
+  for (uint32_t h = 0; h < 2; ++h)
+#pragma unroll
+    for (uint32_t q = 0; q < kHalf; ++q) {
+      const uint32_t f = kWave * q + lane, row = f / kHalf, part = f % kHalf;
+      ld[kHalf * h + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (wave_first + row < a.n && 4 * (kHalf * h + part) < 3 * nb)
+        ld[kHalf * h + q] = src[row * 12 + kHalf * h + part];
+    }
+  float4 shr[2 * kHalf];
+#pragma unroll
+  for (uint32_t h = 0; h < 2; ++h) {
+#pragma unroll
+    for (uint32_t q = 0; q < kHalf; ++q) {
+      const uint32_t f = kWave * q + lane, row = f / kHalf, part = f % kHalf;
+      lds[wave][row * kRowSlots + part] = ld[kHalf * h + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < kHalf; ++q) shr[kHalf * h + q] = lds[wave][lane * kRowSlots + q];
+    __syncthreads();
+  }
   if (g >= a.n) return;
   const ss_camera& c = a.cam;
-  const float4 po = reinterpret_cast<const float4*>(a.mean3d_opacity)[g];
   const float tx0 = c.view[0] * po.x + c.view[1] * po.y + c.view[2] * po.z + c.view[3];
   const float ty0 = c.view[4] * po.x + c.view[5] * po.y + c.view[6] * po.z + c.view[7];
   const float tz = c.view[8] * po.x + c.view[9] * po.y + c.view[10] * po.z + c.view[11];
@@ -79,8 +127,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a) {
       M[0][k] = j00 * c.view[k] + j02 * c.view[8 + k];
       M[1][k] = j11 * c.view[4 + k] + j12 * c.view[8 + k];
     }
-    const float4 s0 = reinterpret_cast<const float4*>(a.cov3d)[2 * g];
-    const float4 s1 = reinterpret_cast<const float4*>(a.cov3d)[2 * g + 1];
     const float S[3][3] = {{s0.x, s0.y, s0.z}, {s0.y, s0.w, s1.x}, {s0.z, s1.x, s1.y}};
     float MS[2][3];
 #pragma unroll
@@ -120,15 +166,10 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a) {
                           -kY3c * dy * (4.0f * zz - xx - yy), kY3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy),
                           -kY3c * dx * (4.0f * zz - xx - yy), kY3e * dz * (xx - yy),
                           -kY3a * dx * (xx - 3.0f * yy)};
-    const uint32_t nb = (c.sh_degree + 1) * (c.sh_degree + 1);
-    // 16 coefficients x 3 channels = 12 aligned 16-byte loads; only those
-    // holding a coefficient below nb are issued
-    const float4* sh4 = reinterpret_cast<const float4*>(a.sh) + static_cast<size_t>(g) * 12;
     float v[48];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      float4 t4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (static_cast<uint32_t>(4 * q) < 3 * nb) t4 = sh4[q];
+    for (uint32_t q = 0; q < 12; ++q) {
+      const float4 t4 = shr[q];
       v[4 * q] = t4.x;
       v[4 * q + 1] = t4.y;
       v[4 * q + 2] = t4.z;
@@ -153,7 +194,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a) {
 
 hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_preprocess, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_preprocess, dim3((a.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

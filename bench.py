@@ -76,6 +76,15 @@ def source_hash(path: str = PASS_SOURCE) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def dominant_kernel(workload: str):
+    """(kernel-name prefix, name filter, source file) of the kernel a
+    workload's roofline is quoted on: the projection kernel for the
+    preprocessing workload, else the 64-bit-key (tile) sort pass."""
+    if workload == "preprocess":
+        return "k_preprocess", "", os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "preprocess.hip")
+    return PASS_KERNEL, "unsigned long", PASS_SOURCE
+
+
 def _rows(pattern: str):
     files = sorted(glob.glob(pattern))
     if not files:
@@ -91,7 +100,7 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     lines = [f"# rocprofv3 kernel statistics, workload {workload}",
              "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
              f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline",
-             f"pass-kernel source sha256[:16]: {source_hash()}", "",
+             f"{dominant_kernel(workload)[0]} source sha256[:16]: {source_hash(dominant_kernel(workload)[2])}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
         name = r["Name"]
@@ -120,8 +129,9 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     wc, wby = per_kernel("write")
     kib = copy_mib * 1024.0
     f_scale, w_scale = kib / (sum(fc) / len(fc)), kib / (sum(wc) / len(wc))
-    # the measured kernel: the 64-bit-key (tile) sort pass
-    tile = [k for k in fby if k.startswith(PASS_KERNEL) and "unsigned long" in k]
+    # the measured kernel
+    kname, kfilter, ksrc = dominant_kernel(workload)
+    tile = [k for k in fby if k.startswith(kname) and kfilter in k]
     assert len(tile) == 1, tile
     fp, wp = fby[tile[0]], wby[tile[0]]
     fetch = sum(fp) / len(fp) * f_scale * 1024.0
@@ -130,16 +140,17 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
                   "fetch_bytes_per_launch": round(sum(fby[k]) / len(fby[k]) * f_scale * 1024.0),
                   "write_bytes_per_launch": round(sum(wby[k]) / len(wby[k]) * w_scale * 1024.0)}
               for k in sorted(fby) if k in wby and not k.startswith("at::") and "rocclr" not in k}
-    rec = {"kernel": tile[0], "workload": workload, "source_sha256_16": source_hash(),
+    wl = "" if workload == "fullhd-1m" else f"--workload {workload} "
+    rec = {"kernel": tile[0], "workload": workload, "source_sha256_16": source_hash(ksrc),
            "copy_calibration_mib": copy_mib, "fetch_scale": f_scale, "write_scale": w_scale,
            "dispatches": len(fp), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "traffic_bytes_per_launch": fetch + write, "per_kernel": others,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py "
-                        f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
+                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py "
-                        f"--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}"]}
-    with open(os.path.join(PROFILES, f"{PASS_KERNEL}_{workload}_traffic.txt"), "w") as f:
-        f.write("# HBM traffic of one tile sort pass (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
+                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}"]}
+    with open(os.path.join(PROFILES, f"{kname}_{workload}_traffic.txt"), "w") as f:
+        f.write(f"# HBM traffic of one {kname} launch (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
                 "# the scales make a plain copy of copy_calibration_mib MiB read and write exactly that),\n"
                 "# and the same per launch for every kernel of the step\n")
         f.write(json.dumps(rec, indent=1) + "\n")
@@ -147,16 +158,31 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
 
 
 def profiled_traffic(workload: str):
-    """Traffic per pass launch from the committed profile, if it was taken on
-    the current pass-kernel source; else None."""
-    path = os.path.join(PROFILES, f"{PASS_KERNEL}_{workload}_traffic.txt")
+    """Traffic per launch of the workload's roofline kernel from the committed
+    profile, if it was taken on that kernel's current source; else None."""
+    kname, _, ksrc = dominant_kernel(workload)
+    path = os.path.join(PROFILES, f"{kname}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     rec = json.loads(text[text.index("{"):])
-    if rec.get("source_sha256_16") != source_hash():
+    if rec.get("source_sha256_16") != source_hash(ksrc):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def calibration_copy(args, dev, stream):
+    """One streaming copy of --copy-mib MiB (traffic-counter calibration)."""
+    if not args.copy_mib:
+        return
+    import torch
+    import paper_2511_16298_amd as ss
+    nb = args.copy_mib << 20
+    a = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    ss.copy_bytes(b, a, nb, stream)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def pct(a, q):
@@ -425,6 +451,7 @@ def bench_preprocess(args):
     m3, cv, sh = (torch.from_numpy(scene[k]).to(dev) for k in ("mean3d_opacity", "cov3d", "sh"))
     c = ss.camera(**params)
     pre = ss.Preprocessor(n, device=dev)
+    calibration_copy(args, dev, stream)
     for _ in range(args.warmup):
         pre(c, m3, cv, sh, stream)
     torch.cuda.synchronize()
@@ -476,7 +503,7 @@ def bench_preprocess(args):
                        "parallelism": "single GPU"},
             "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
             "roofline": {"bound": "hbm", "kernel": "k_preprocess", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": profiled_traffic("preprocess"),
                          "bytes_per_launch": PREPROCESS_BYTES * n, "avg_launch_us": kern_us},
             "frame_with_sort": {"ms_per_frame": chain_ms, "num_pairs": M,
                                 "pairs_per_s": M / (chain_ms * 1e-3)}}
@@ -597,13 +624,7 @@ def main():
     rb = args.radix_bits or 8
     passes = -(-key_bits // rb)
     stream = torch.cuda.current_stream()
-    if args.copy_mib:
-        nb = args.copy_mib << 20
-        a = torch.ones(nb // 4, dtype=torch.int32, device=dev)
-        b = torch.empty_like(a)
-        ss.copy_bytes(b, a, nb, stream)
-        torch.cuda.synchronize()
-        del a, b
+    calibration_copy(args, dev, stream)
 
     print(f"# workload {args.workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
           f"T={tx * ty}, key bits {key_bits}", file=sys.stderr, flush=True)

@@ -14,14 +14,14 @@
 //     (Condon-Shortley phase) of the direction from the camera to p).
 // One thread per Gaussian; a memory-bound stream of 240 bytes in and 48 out.
 // The 192 bytes of SH coefficients per Gaussian are the bulk.  Loaded one
-// row per lane they would touch 64 rows 192 bytes apart per instruction; each
-// wave instead reads its 64 rows in 96-byte runs (six 16-byte loads per lane
-// per half row, 1 KB per instruction), transposes them through LDS one half
-// row (24 floats) at a time, rows padded to 28 floats (16-byte aligned, and
-// 16 consecutive rows start in distinct bank groups, so the 16-byte row reads
-// do not conflict), and every lane reads its own row back.  All loads of a
-// wave are issued before its first wait; 28 KB of LDS and 90 VGPRs leave
-// five waves per SIMD.
+// row per lane they would touch 64 rows 192 bytes apart per instruction;
+// each wave instead reads its 64 rows as two contiguous 6-KB blocks of 32
+// rows (1 KB per load instruction, and no cache line shared between the
+// blocks, so every line is fetched once), transposes each block through LDS
+// with rows padded to 13 float4 (16 consecutive rows start in distinct bank
+// groups, so the 16-byte row reads do not conflict), and the block's 32 lanes
+// read their rows back.  All loads of a wave are issued before its first
+// wait; 26 KB of LDS and 94 VGPRs leave five waves per SIMD.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -59,11 +59,11 @@ __device__ __forceinline__ float det2(float a, float b, float c) {
 }
 
 constexpr uint32_t kThreads = 256;
-constexpr uint32_t kHalf = 6;          // float4 per half row
-constexpr uint32_t kRowSlots = 7;      // float4 per padded LDS row
+constexpr uint32_t kStageRows = 32;    // SH rows per LDS stage
+constexpr uint32_t kRowSlots = 13;     // float4 per padded LDS row (12 + 1)
 
 __global__ __launch_bounds__(kThreads) void k_preprocess(PreprocessArgs a) {
-  __shared__ float4 lds[kThreads / kWave][kWave * kRowSlots];
+  __shared__ float4 lds[kThreads / kWave][kStageRows * kRowSlots];
   const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
   const uint32_t wave_first = g - lane;
@@ -74,30 +74,31 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(PreprocessArgs a) {
     s0 = reinterpret_cast<const float4*>(a.cov3d)[2 * static_cast<size_t>(g)];
     s1 = reinterpret_cast<const float4*>(a.cov3d)[2 * static_cast<size_t>(g) + 1];
   }
-  // half h of the wave's rows: its float4 f = 64 q + lane (q < 6) is part
-  // f % 6 of row f / 6; only parts holding a coefficient below nb are loaded
+  // stage s holds rows 32 s .. 32 s + 31 of the wave, a contiguous 6-KB
+  // block: its float4 f = 64 q + lane (q < 6) is part f % 12 of local row f / 12
   const float4* src = reinterpret_cast<const float4*>(a.sh) + static_cast<size_t>(wave_first) * 12;
-  float4 ld[2 * kHalf];
+  float4 ld[12];
 #pragma unroll
-  for (uint32_t h = 0; h < 2; ++h)
+  for (uint32_t st = 0; st < 2; ++st)
 #pragma unroll
-    for (uint32_t q = 0; q < kHalf; ++q) {
-      const uint32_t f = kWave * q + lane, row = f / kHalf, part = f % kHalf;
-      ld[kHalf * h + q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (wave_first + row < a.n && 4 * (kHalf * h + part) < 3 * nb)
-        ld[kHalf * h + q] = src[row * 12 + kHalf * h + part];
+    for (uint32_t q = 0; q < 6; ++q) {
+      const uint32_t f = kWave * q + lane, row = kStageRows * st + f / 12, part = f % 12;
+      ld[6 * st + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (wave_first + row < a.n && 4 * part < 3 * nb) ld[6 * st + q] = src[384 * st + f];
     }
-  float4 shr[2 * kHalf];
+  float4 shr[12];
 #pragma unroll
-  for (uint32_t h = 0; h < 2; ++h) {
+  for (uint32_t st = 0; st < 2; ++st) {
 #pragma unroll
-    for (uint32_t q = 0; q < kHalf; ++q) {
-      const uint32_t f = kWave * q + lane, row = f / kHalf, part = f % kHalf;
-      lds[wave][row * kRowSlots + part] = ld[kHalf * h + q];
+    for (uint32_t q = 0; q < 6; ++q) {
+      const uint32_t f = kWave * q + lane;
+      lds[wave][(f / 12) * kRowSlots + f % 12] = ld[6 * st + q];
     }
     __syncthreads();
+    if (lane / kStageRows == st) {
 #pragma unroll
-    for (uint32_t q = 0; q < kHalf; ++q) shr[kHalf * h + q] = lds[wave][lane * kRowSlots + q];
+      for (uint32_t q = 0; q < 12; ++q) shr[q] = lds[wave][(lane % kStageRows) * kRowSlots + q];
+    }
     __syncthreads();
   }
   if (g >= a.n) return;

@@ -60,8 +60,9 @@ def parse():
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
-    p.add_argument("--algorithm", default="depth-first", choices=["depth-first", "direct", "bitonic"],
-                   help="frame sort algorithm (frames, sweep)")
+    p.add_argument("--algorithm", default="depth-first", choices=["depth-first", "direct", "bitonic", "bitonic-key32"],
+                   help="frame sort algorithm (frames, sweep); bitonic-key32 = the paper's normalised "
+                        "32-bit float key (lossy within a tile, frames only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle baseline (whole frames until exceeded)")
@@ -617,9 +618,10 @@ def main():
     assert int(s_t.item()) == 0
     M = int(m_t.item()) & 0xFFFFFFFF
     algo = {"depth-first": ss.SS_ALGO_DEPTH_FIRST, "direct": ss.SS_ALGO_DIRECT,
-            "bitonic": ss.SS_ALGO_BITONIC}[args.algorithm]
+            "bitonic": ss.SS_ALGO_BITONIC, "bitonic-key32": ss.SS_ALGO_BITONIC}[args.algorithm]
+    key32 = args.algorithm == "bitonic-key32"
     sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev,
-                            workgroup_size=args.wg, algorithm=algo)
+                            workgroup_size=args.wg, algorithm=algo, key32=key32)
     tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
     rb = args.radix_bits or 8
     passes = -(-key_bits // rb)
@@ -721,7 +723,8 @@ def main():
         frames, spent, parity = 0, 0.0, True
         while spent < args.cpu_seconds or frames == 0:
             t = time.perf_counter()
-            res = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+            res = (oracle.sort_frame_key32(spec.width, spec.height, rec) if key32
+                   else oracle.sort_frame(spec.width, spec.height, rec, stages=False))
             spent += time.perf_counter() - t
             frames += 1
             if frames == 1:
@@ -731,6 +734,11 @@ def main():
                                 "sample": f"{frames} whole {args.workload} frames ({spent:.1f} s, "
                                           f"single-threaded oracle, {os.cpu_count()} host CPUs visible)"}
         line["parity_vs_oracle"] = bool(parity)
+        if key32:
+            # how lossy the normalised key is on this frame: pairs whose position
+            # differs from the exact (tile, depth, index) order
+            ex = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+            line["key32_pairs_out_of_exact_order"] = float(np.mean(ex.values != vals_gpu))
     print(json.dumps(line), flush=True)
 
 

@@ -94,7 +94,7 @@ typedef struct ss_options {
   uint32_t struct_size;
   uint32_t radix_bits;     /* 0 = default (8); supported: 4, 6, 8 */
   uint32_t items_per_thread; /* 0 = default (16); supported: 8, 12, 16 */
-  uint32_t flags;          /* 0, or SS_FLAG_UNSORTED */
+  uint32_t flags;          /* 0, SS_FLAG_UNSORTED or SS_FLAG_KEY32_LOSSY */
   ss_timer* timer;         /* optional: record HIP events around every kernel */
   uint32_t workgroup_size; /* sort-pass threads: 0 = default (512 where
                               supported, else 256); 512 needs radix_bits 8
@@ -128,6 +128,20 @@ typedef struct ss_options {
  * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no
  * ranges.  For stage-by-stage verification. */
 #define SS_FLAG_UNSORTED 1u
+/* The paper's key normalisation (Design, "Sorting Optimizations in Context of
+ * 3DGS": the 64-bit key replaced by one 32-bit float holding 20 bits of tile
+ * number and the depth brought below 2^10), with SS_ALGO_BITONIC in
+ * ss_sort_frame only: the network orders the pairs by (k, value) with
+ * k = FP32(tile * 2^10 + min(depth, 1024 - 2^-14)) rounded toward zero, so k
+ * stays inside [tile * 2^10, (tile + 1) * 2^10) and the tiles stay in order;
+ * depths closer than one unit in the last place of k (2^(e - 23), e the
+ * binary exponent of k: 1/8 for tile 1000, 1 for tile 8000) are not
+ * separated and keep index order.  This is lossy: the order inside a tile is
+ * the exact order only up to that quantum.  Output keys are the exact 64-bit
+ * keys (tile << 32 | depth bits) in that order; ranges as usual.  Needs
+ * T <= 2^20 (else SS_ERR_UNSUPPORTED); any other algorithm, ss_sort_pairs,
+ * batches or SS_FLAG_UNSORTED with it are SS_ERR_UNSUPPORTED. */
+#define SS_FLAG_KEY32_LOSSY 2u
 
 /* Library identification. */
 uint32_t ss_abi_version(void);

@@ -306,3 +306,48 @@ def sort_batch(frames: Sequence[tuple]) -> BatchResult:
     cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
     return BatchResult(ms, pair_base, tile_base, cat(keys, np.uint64), cat(vals, np.uint32),
                        cat(rngs, np.uint64).reshape(-1, 2).astype(np.uint32))
+
+
+# ----------------------------------------------------------------------------
+# The paper's key normalisation (Design, "Sorting Optimizations in Context of
+# 3DGS"): the 64-bit (tile, depth) key replaced by one 32-bit float holding 20
+# bits of tile number and the depth brought below 2^10.  Reading: k = FP32
+# value of tile * 2^10 + min(depth, largest float below 2^10), rounded toward
+# zero (so k never reaches the next tile's first key); pairs ordered by
+# (k, Gaussian index).
+
+#: largest float32 below 2^10
+KEY32_DEPTH_CAP = np.float32(1024.0) - np.float32(2.0 ** -14)
+
+
+def key32_normalized(keys: np.ndarray) -> np.ndarray:
+    """Bits (uint32) of the normalised float key of each 64-bit frame key.
+
+    The sum is formed in float64 and then rounded toward zero to float32.
+    That equals rounding the exact sum toward zero: tile * 2^10 and every
+    float32 at or below 2^30 + 2^10 are float64 values, and float64 rounding
+    is monotonic, so it can only land on a float32 value F that exceeds the
+    exact sum if the exact sum lies within half a float64 unit below F; but
+    F - tile * 2^10 - depth is a multiple of the last bit of depth, which is
+    at least 2^-23 of depth and far larger than that."""
+    k = np.asarray(keys, dtype=np.uint64)
+    tile = (k >> np.uint64(32)).astype(np.float64)
+    depth = (k & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32)
+    d = np.minimum(depth, KEY32_DEPTH_CAP).astype(np.float64)
+    exact = tile * 1024.0 + d
+    f = exact.astype(np.float32)                                  # nearest
+    f = np.where(f.astype(np.float64) > exact, np.nextafter(f, np.float32(0)), f)  # toward zero
+    return f.astype(np.float32).view(np.uint32)
+
+
+def sort_frame_key32(width: int, height: int, records: np.ndarray) -> FrameResult:
+    """The frame sorted by the normalised 32-bit key: the frame's pairs (from
+    ``sort_frame``) reordered by (k, value); keys stay the exact 64-bit keys,
+    ranges are recomputed from them (k keeps the tiles in order)."""
+    r = sort_frame(width, height, records, stages=False)
+    if r.status != OK:
+        return r
+    k32 = key32_normalized(r.keys)
+    order = np.lexsort((r.values, k32))      # primary k32, then value
+    keys, values = r.keys[order], r.values[order]
+    return dataclasses.replace(r, keys=keys, values=values, ranges=ranges(keys, r.num_tiles))

@@ -118,15 +118,16 @@ class FrameSorter:
 
     def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
                  radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
-                 device="cuda", unsorted: bool = False, workgroup_size: int = 0, algorithm: int = 0):
+                 device="cuda", unsorted: bool = False, workgroup_size: int = 0, algorithm: int = 0,
+                 key32: bool = False):
         torch = _torch()
         self.width, self.height = width, height
         self.num_gaussians = num_gaussians
         self.capacity = int(pair_capacity)
         self.tiles_x, self.tiles_y, self.key_bits = geometry(width, height)
         self.num_tiles = self.tiles_x * self.tiles_y
-        self.options = make_options(radix_bits, items_per_thread,
-                                    flags=_abi.SS_FLAG_UNSORTED if unsorted else 0,
+        flags = (_abi.SS_FLAG_UNSORTED if unsorted else 0) | (_abi.SS_FLAG_KEY32_LOSSY if key32 else 0)
+        self.options = make_options(radix_bits, items_per_thread, flags=flags,
                                     workgroup_size=workgroup_size, algorithm=algorithm)
         probe = ss_frame()
         probe.width, probe.height, probe.tile_px, probe.num_gaussians = width, height, 16, num_gaussians

@@ -22,6 +22,9 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) &
 
 // Counter words at the start of the workspace.
 
+// the normalised 32-bit key holds 20 bits of tile number
+constexpr uint64_t kKey32MaxTiles = uint64_t{1} << 20;
+
 struct Options {
   uint32_t radix_bits = kDefaultRadix;
   uint32_t items = kDefaultItems;
@@ -35,8 +38,12 @@ ss_status parse_options(const ss_options* o, Options* out) {
   *out = Options{};
   if (o == nullptr) return SS_OK;
   if (o->struct_size < sizeof(ss_options)) return SS_ERR_INVALID_ARGUMENT;
-  if ((o->flags & ~SS_FLAG_UNSORTED) != 0) return SS_ERR_UNSUPPORTED;
+  if ((o->flags & ~(SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY)) != 0) return SS_ERR_UNSUPPORTED;
   if (o->algorithm > SS_ALGO_BITONIC) return SS_ERR_UNSUPPORTED;
+  // the normalised 32-bit key belongs to the bitonic network and needs the sort
+  if ((o->flags & SS_FLAG_KEY32_LOSSY) != 0 &&
+      (o->algorithm != SS_ALGO_BITONIC || (o->flags & SS_FLAG_UNSORTED) != 0))
+    return SS_ERR_UNSUPPORTED;
   out->flags = o->flags;
   out->algorithm = o->algorithm;
   if (o->radix_bits != 0) out->radix_bits = o->radix_bits;
@@ -299,6 +306,7 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   uint32_t* d_num_pairs = out->num_pairs ? out->num_pairs : scal + 1;
   const bool unsorted = (o.flags & SS_FLAG_UNSORTED) != 0;
   const bool bitonic = o.algorithm == SS_ALGO_BITONIC && !unsorted;
+  const bool key32 = (o.flags & SS_FLAG_KEY32_LOSSY) != 0;
   const uint32_t P = unsorted ? 0 : lay.npasses;
   // dup writes buf[0]; pass p reads buf[p % 2] and writes buf[(p + 1) % 2];
   // the data ends in buf[P % 2], which must be the caller's output.  The
@@ -310,9 +318,15 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   bv[P % 2] = out->values;
   bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
   bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
-  if (bitonic) {
+  if (bitonic && !key32) {
     bk[0] = at<uint64_t>(ws, lay.alt_keys);
     bv[0] = at<uint32_t>(ws, lay.alt_vals);
+  }
+  // key32: the pairs are duplicated into the caller's output, normalised from
+  // there into the padded buffer, and written back with their exact keys
+  if (key32) {
+    bk[0] = out->keys;
+    bv[0] = out->values;
   }
 
   SS_TRY(L.run(SS_KERNEL_CLEAR, [&] { return launch_clear(ws, lay.clear_end, d_status, nullptr, nullptr, s); }));
@@ -335,9 +349,11 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_dup(a, static_cast<int>(o.radix_bits), true, s); }));
   if (unsorted) return SS_OK;
   if (bitonic) {
-    BitonicArgs b{bk[0], bv[0], lay.log_pad, d_num_pairs, 0, d_status, out->keys, out->values, cap};
+    BitonicArgs b{at<void>(ws, lay.alt_keys), at<uint32_t>(ws, lay.alt_vals), lay.log_pad, d_num_pairs, 0,
+                  d_status, out->keys, out->values, cap, key32, frame->gaussians};
     SS_TRY(L.run_group(SS_KERNEL_SORT_PASS, bitonic_launches(lay.log_pad), [&] {
-      return launch_bitonic(b, nullptr, nullptr, ~0ull, s) == hipSuccess ? SS_OK : SS_ERR_HIP;
+      return launch_bitonic(b, key32 ? out->keys : nullptr, key32 ? out->values : nullptr, ~0ull, s) == hipSuccess
+                 ? SS_OK : SS_ERR_HIP;
     }));
     return L.run(SS_KERNEL_RANGES, [&] {
       return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
@@ -646,8 +662,12 @@ ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity, cons
   Options o;
   SS_TRY(parse_options(options, &o));
   if (pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
-  *bytes = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
-                         : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o).total;
+  const size_t sort = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
+                                    : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o).total;
+  // ss_count_pairs runs in any workspace sized here (its own layout can be
+  // the larger one, e.g. for N = 0)
+  const size_t count = make_layout(frame->num_gaussians, 0, g.key_bits, Options{}).total;
+  *bytes = sort > count ? sort : count;
   return SS_OK;
 }
 
@@ -686,6 +706,7 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   Options o;
   SS_TRY(parse_options(options, &o));
   if (out == nullptr || out->tile_ranges == nullptr) return SS_ERR_INVALID_ARGUMENT;
+  if ((o.flags & SS_FLAG_KEY32_LOSSY) != 0 && g.num_tiles > kKey32MaxTiles) return SS_ERR_UNSUPPORTED;
   const uint32_t cap = out->pair_capacity;
   if (cap > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
   if (cap > 0 && (out->keys == nullptr || out->values == nullptr)) return SS_ERR_INVALID_ARGUMENT;
@@ -816,6 +837,7 @@ ss_status ss_sort_pairs(const uint64_t* keys_in, const uint32_t* values_in, uint
     return SS_ERR_INVALID_ARGUMENT;
   Options o;
   SS_TRY(parse_options(options, &o));
+  if ((o.flags & SS_FLAG_KEY32_LOSSY) != 0) return SS_ERR_UNSUPPORTED;  // needs frame keys
   const Layout lay = make_layout(0, n, key_bits, o);
   if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total)
     return SS_ERR_WORKSPACE;

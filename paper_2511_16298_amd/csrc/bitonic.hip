@@ -16,6 +16,16 @@
 // The network sorts a power-of-two padded array.  Elements compare as
 // (key, value) pairs, so for the frame's pairs -- unique (tile, Gaussian) --
 // the result is the stable order of the radix paths, bit for bit.
+//
+// The paper's key normalisation (Design, "Sorting Optimizations in Context
+// of 3DGS": the 64-bit key becomes one 32-bit float, 20 bits of tile number
+// and the depth brought below 2^10) is the 32-bit-key instantiation: key =
+// tile * 2^10 + min(depth, largest float below 2^10), rounded toward zero in
+// FP32 so that no key reaches the next tile's; positive floats order like
+// their bit patterns, so the network compares the bits.  Depths closer than
+// one unit in the last place of the sum share a key and fall back to index
+// order.  The last kernel rebuilds the exact 64-bit key of each pair from its
+// tile and its Gaussian's depth.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -29,14 +39,19 @@ constexpr uint32_t kLocalItems = kChunk / kLocalThreads;
 constexpr uint32_t kGlobalThreads = 256;
 constexpr uint32_t kMaxFuse = 3;
 
-__device__ __forceinline__ bool greater(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
+// largest FP32 value below 2^10 (0x447FFFFF)
+constexpr float kDepthCap = 1023.99993896484375f;
+
+template <typename K>
+__device__ __forceinline__ bool greater(K ka, uint32_t va, K kb, uint32_t vb) {
   return ka > kb || (ka == kb && va > vb);
 }
 
 // Order (a, b) ascending (or descending) in place.
-__device__ __forceinline__ void cmp_swap(uint64_t& ka, uint32_t& va, uint64_t& kb, uint32_t& vb, bool asc) {
+template <typename K>
+__device__ __forceinline__ void cmp_swap(K& ka, uint32_t& va, K& kb, uint32_t& vb, bool asc) {
   if (greater(ka, va, kb, vb) == asc) {
-    const uint64_t tk = ka;
+    const K tk = ka;
     ka = kb;
     kb = tk;
     const uint32_t tv = va;
@@ -45,26 +60,53 @@ __device__ __forceinline__ void cmp_swap(uint64_t& ka, uint32_t& va, uint64_t& k
   }
 }
 
+// The normalised 32-bit key of a frame key (tile << 32 | depth bits): FP32
+// tile * 1024 (exact below 2^20 tiles) plus the capped depth, rounded toward
+// zero: the rounded-to-nearest sum, stepped down one unit when it exceeds the
+// exact sum (whose error the two-sum identity gives exactly).
+__device__ __forceinline__ uint32_t lossy_key32(uint64_t key) {
+  const float t = static_cast<float>(static_cast<uint32_t>(key >> 32)) * 1024.0f;
+  const float d = fminf(__uint_as_float(static_cast<uint32_t>(key)), kDepthCap);
+  const float sum = t + d;
+  const float bv = sum - t;
+  const float err = (t - (sum - bv)) + (d - bv);
+  const uint32_t bits = __float_as_uint(sum);
+  return err < 0.0f ? bits - 1 : bits;
+}
+
+template <typename K>
+__device__ __forceinline__ K* key_buf(const BitonicArgs& a) {
+  return static_cast<K*>(a.keys);
+}
+template <typename K>
+__device__ __forceinline__ K key_max() {
+  return static_cast<K>(~K{0});
+}
+
 __device__ __forceinline__ uint32_t valid_count(const BitonicArgs& a) {
   return a.num_pairs ? *a.num_pairs : a.n_fixed;
 }
 
-// Fill the padded buffer: entries [0, n) from the source (when given, with the
-// key masked to key_mask), [n, 2^log_n) with the largest pair.
+// Fill the padded buffer: entries [0, n) from the source (when given; 64-bit
+// keys masked to key_mask, 32-bit keys normalised), [n, 2^log_n) with the
+// largest pair.
+template <typename K>
 __global__ __launch_bounds__(256) void k_bitonic_load(BitonicArgs a, const uint64_t* __restrict__ src_k,
                                                       const uint32_t* __restrict__ src_v, uint64_t key_mask) {
   if (a.status && *a.status != SS_OK) return;
   const uint32_t n = valid_count(a);
   const uint64_t size = 1ull << a.log_n;
+  K* keys = key_buf<K>(a);
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < size;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     if (i < n) {
       if (src_k) {
-        a.keys[i] = src_k[i] & key_mask;
+        if constexpr (sizeof(K) == 8) keys[i] = src_k[i] & key_mask;
+        else keys[i] = lossy_key32(src_k[i]);
         a.vals[i] = src_v[i];
       }
     } else {
-      a.keys[i] = ~0ull;
+      keys[i] = key_max<K>();
       a.vals[i] = ~0u;
     }
   }
@@ -73,11 +115,15 @@ __global__ __launch_bounds__(256) void k_bitonic_load(BitonicArgs a, const uint6
 // Stages s0..s1 inside one chunk of the array; for each stage the steps whose
 // partner distance is below the chunk.  Chunks shorter than kChunk happen
 // only when the whole array is shorter.  With `final` the chunk is written to
-// the caller's output (entries below the valid count) instead of back.
+// the caller's output (entries below the valid count) instead of back; 32-bit
+// keys leave as the exact 64-bit key (tile from the normalised key, depth bits
+// from the Gaussian's record).
+template <typename K>
 __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, uint32_t s0, uint32_t s1,
                                                                  bool final_pass) {
-  __shared__ uint64_t sk[kChunk];
+  __shared__ K sk[kChunk];
   __shared__ uint32_t sv[kChunk];
+  K* keys = key_buf<K>(a);
   if (a.status && *a.status != SS_OK) return;
   const uint32_t tid = threadIdx.x;
   const uint32_t clog = a.log_n < kChunkLog ? a.log_n : kChunkLog;
@@ -87,7 +133,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, 
   for (uint32_t m = 0; m < kLocalItems; ++m) {
     const uint32_t i = m * kLocalThreads + tid;
     if (i < csize) {
-      sk[i] = a.keys[base + i];
+      sk[i] = keys[base + i];
       sv[i] = a.vals[base + i];
     }
   }
@@ -101,7 +147,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, 
         const uint32_t lo = ((q >> b) << (b + 1)) | (q & ((1u << b) - 1));
         const uint32_t hi = lo | (1u << b);
         const bool asc = (((base + lo) >> s) & 1) == 0;
-        uint64_t k0 = sk[lo], k1 = sk[hi];
+        K k0 = sk[lo], k1 = sk[hi];
         uint32_t v0 = sv[lo], v1 = sv[hi];
         cmp_swap(k0, v0, k1, v1, asc);
         sk[lo] = k0;
@@ -118,7 +164,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, 
     for (uint32_t m = 0; m < kLocalItems; ++m) {
       const uint32_t i = m * kLocalThreads + tid;
       if (i < csize && base + i < n && base + i < a.out_capacity) {
-        a.out_keys[base + i] = sk[i];
+        if constexpr (sizeof(K) == 8) {
+          a.out_keys[base + i] = sk[i];
+        } else {
+          // floor(key) lies in [tile * 1024, tile * 1024 + 1023]
+          const uint32_t tile = static_cast<uint32_t>(__uint_as_float(sk[i])) >> 10;
+          a.out_keys[base + i] = (static_cast<uint64_t>(tile) << 32) |
+                                 __float_as_uint(a.gaussians[sv[i]].depth);
+        }
         a.out_vals[base + i] = sv[i];
       }
     }
@@ -127,7 +180,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, 
     for (uint32_t m = 0; m < kLocalItems; ++m) {
       const uint32_t i = m * kLocalThreads + tid;
       if (i < csize) {
-        a.keys[base + i] = sk[i];
+        keys[base + i] = sk[i];
         a.vals[base + i] = sv[i];
       }
     }
@@ -137,20 +190,21 @@ __global__ __launch_bounds__(kLocalThreads) void k_bitonic_local(BitonicArgs a, 
 // Steps j_hi, j_hi - 1, ..., j_hi - t + 1 of stage s (partner distances of
 // at least one chunk).  Thread g owns the 2^t elements i0 + m 2^(j_hi - t),
 // m < 2^t, where i0 is g with t zero bits inserted at bit j_hi - t.
-template <uint32_t T>
+template <typename K, uint32_t T>
 __global__ __launch_bounds__(kGlobalThreads) void k_bitonic_global(BitonicArgs a, uint32_t s, uint32_t j_hi) {
   constexpr uint32_t E = 1u << T;
   if (a.status && *a.status != SS_OK) return;
+  K* keys = key_buf<K>(a);
   const uint64_t g = static_cast<uint64_t>(blockIdx.x) * kGlobalThreads + threadIdx.x;
   if (g >= (1ull << (a.log_n - T))) return;
   const uint32_t blo = j_hi - T;
   const uint64_t i0 = ((g >> blo) << (blo + T)) | (g & ((1ull << blo) - 1));
   const bool asc = ((i0 >> s) & 1) == 0;
-  uint64_t k[E];
+  K k[E];
   uint32_t v[E];
 #pragma unroll
   for (uint32_t m = 0; m < E; ++m) {
-    k[m] = a.keys[i0 + (static_cast<uint64_t>(m) << blo)];
+    k[m] = keys[i0 + (static_cast<uint64_t>(m) << blo)];
     v[m] = a.vals[i0 + (static_cast<uint64_t>(m) << blo)];
   }
 #pragma unroll
@@ -161,7 +215,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_bitonic_global(BitonicArgs a
   }
 #pragma unroll
   for (uint32_t m = 0; m < E; ++m) {
-    a.keys[i0 + (static_cast<uint64_t>(m) << blo)] = k[m];
+    keys[i0 + (static_cast<uint64_t>(m) << blo)] = k[m];
     a.vals[i0 + (static_cast<uint64_t>(m) << blo)] = v[m];
   }
 }
@@ -186,31 +240,42 @@ uint32_t bitonic_launches(uint32_t log_n) {
   return n;
 }
 
-hipError_t launch_bitonic(const BitonicArgs& a, const uint64_t* src_k, const uint32_t* src_v, uint64_t key_mask,
+namespace {
+
+template <typename K>
+hipError_t launch_network(const BitonicArgs& a, const uint64_t* src_k, const uint32_t* src_v, uint64_t key_mask,
                           hipStream_t s) {
   const uint64_t size = 1ull << a.log_n;
   const uint32_t load_grid = grid_for(size, 256) < 4096 ? grid_for(size, 256) : 4096;
-  hipLaunchKernelGGL(k_bitonic_load, dim3(load_grid), dim3(256), 0, s, a, src_k, src_v, key_mask);
+  hipLaunchKernelGGL(k_bitonic_load<K>, dim3(load_grid), dim3(256), 0, s, a, src_k, src_v, key_mask);
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   const uint32_t clog = a.log_n < kChunkLog ? a.log_n : kChunkLog;
   const uint32_t chunks = static_cast<uint32_t>(size >> clog);
-  hipLaunchKernelGGL(k_bitonic_local, dim3(chunks), dim3(kLocalThreads), 0, s, a, 1u, clog, a.log_n == clog);
+  hipLaunchKernelGGL(k_bitonic_local<K>, dim3(chunks), dim3(kLocalThreads), 0, s, a, 1u, clog, a.log_n == clog);
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   for (uint32_t st = clog + 1; st <= a.log_n; ++st) {
     uint32_t j = st;
     while (j > clog) {
       const uint32_t t = j - clog < kMaxFuse ? j - clog : kMaxFuse;
       const uint32_t grid = grid_for(size >> t, kGlobalThreads);
-      if (t == 3) hipLaunchKernelGGL(k_bitonic_global<3>, dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
-      else if (t == 2) hipLaunchKernelGGL(k_bitonic_global<2>, dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
-      else hipLaunchKernelGGL(k_bitonic_global<1>, dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
+      if (t == 3) hipLaunchKernelGGL((k_bitonic_global<K, 3>), dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
+      else if (t == 2) hipLaunchKernelGGL((k_bitonic_global<K, 2>), dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
+      else hipLaunchKernelGGL((k_bitonic_global<K, 1>), dim3(grid), dim3(kGlobalThreads), 0, s, a, st, j);
       if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
       j -= t;
     }
-    hipLaunchKernelGGL(k_bitonic_local, dim3(chunks), dim3(kLocalThreads), 0, s, a, st, st, st == a.log_n);
+    hipLaunchKernelGGL(k_bitonic_local<K>, dim3(chunks), dim3(kLocalThreads), 0, s, a, st, st, st == a.log_n);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_bitonic(const BitonicArgs& a, const uint64_t* src_k, const uint32_t* src_v, uint64_t key_mask,
+                          hipStream_t s) {
+  return a.key32 ? launch_network<uint32_t>(a, src_k, src_v, key_mask, s)
+                 : launch_network<uint64_t>(a, src_k, src_v, key_mask, s);
 }
 
 }  // namespace ss

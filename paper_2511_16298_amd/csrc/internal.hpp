@@ -186,7 +186,7 @@ hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
 // The paper's bitonic network (see bitonic.hip), over a power-of-two padded
 // buffer sorted in place by (key, value).
 struct BitonicArgs {
-  uint64_t* keys;               // [2^log_n] padded buffer
+  void* keys;                   // [2^log_n] padded buffer: uint64_t, or uint32_t when key32
   uint32_t* vals;
   uint32_t log_n;
   const uint32_t* num_pairs;    // device count of valid entries, or NULL (then n_fixed)
@@ -195,11 +195,14 @@ struct BitonicArgs {
   uint64_t* out_keys;           // the last kernel writes the valid entries here
   uint32_t* out_vals;
   uint32_t out_capacity;
+  bool key32;                   // the paper's normalised 32-bit float key (source keys are frame keys)
+  const ss_gaussian2d* gaussians; // key32: the frame's records, to rebuild the exact output keys
 };
 uint32_t bitonic_log_size(uint64_t n);          // smallest l >= 1 with 2^l >= n
 uint32_t bitonic_launches(uint32_t log_n);
-// Pads (and, with src_k, first loads src[0, n) with keys masked by key_mask),
-// then sorts and writes the first n entries to out_*.
+// Pads (and, with src_k, first loads src[0, n) with keys masked by key_mask,
+// or normalised to 32 bits when key32), then sorts and writes the first n
+// entries to out_*.
 hipError_t launch_bitonic(const BitonicArgs& a, const uint64_t* src_k, const uint32_t* src_v, uint64_t key_mask,
                           hipStream_t s);
 

@@ -100,7 +100,7 @@ def test_sort_frame_argument_errors_are_synchronous():
     o = fake_out(cap=_abi.SS_MAX_PAIR_CAPACITY + 1)
     assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
     # options
-    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 2, 0), (0, 0, 0, 128),
+    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 4, 0), (0, 0, 0, 128),
                            (6, 0, 0, 512), (0, 12, 0, 512)]:
         opt = _abi.make_options(rb, it, flags=fl, workgroup_size=wg)
         assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, opt) == _abi.SS_ERR_UNSUPPORTED
@@ -264,3 +264,29 @@ def test_preprocess_argument_errors_are_synchronous():
     assert call(c=cam(view=view[:11] + [float("nan")])) == bad
     # nothing to do: no device call, no pointer needed
     assert call(n=0, **{k: None for k in good}) == _abi.SS_OK
+
+
+def test_key32_option_rules():
+    """The normalised 32-bit key: bitonic frames only, at most 2^20 tiles."""
+    f = frame(n=10, ptr=1 << 12)
+    K, U = _abi.SS_FLAG_KEY32_LOSSY, _abi.SS_FLAG_UNSORTED
+    for algo in (_abi.SS_ALGO_AUTO, _abi.SS_ALGO_DEPTH_FIRST, _abi.SS_ALGO_DIRECT):
+        assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(flags=K, algorithm=algo))[0] == \
+            _abi.SS_ERR_UNSUPPORTED
+    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(flags=K | U, algorithm=_abi.SS_ALGO_BITONIC))[0] == \
+        _abi.SS_ERR_UNSUPPORTED
+    st, need = _abi.ss_workspace_bytes(f, 100, _abi.make_options(flags=K, algorithm=_abi.SS_ALGO_BITONIC))
+    assert st == _abi.SS_OK
+    assert need == _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))[1]
+    opt = _abi.make_options(flags=K, algorithm=_abi.SS_ALGO_BITONIC)
+    # 2^21 tiles: more than the key's 20 tile bits
+    big = frame(w=16 * 2048, h=16 * 1024, n=10, ptr=1 << 12)
+    st, need_big = _abi.ss_workspace_bytes(big, 100, opt)
+    assert st == _abi.SS_OK
+    assert _abi.ss_sort_frame(big, fake_out(), 4 << 20, need_big, None, opt) == _abi.SS_ERR_UNSUPPORTED
+    # sort-only keys carry no (tile, depth) structure
+    st, need_p = _abi.ss_sort_pairs_workspace_bytes(1000, 45, _abi.make_options(algorithm=_abi.SS_ALGO_BITONIC))
+    assert st == _abi.SS_OK
+    a, b, c, d = 1 << 20, 2 << 20, 3 << 20, 4 << 20
+    assert _abi.ss_sort_pairs(a, b, 1000, 45, c, d, 8 << 20, need_p, None, opt) == _abi.SS_ERR_UNSUPPORTED
+

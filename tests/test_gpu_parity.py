@@ -32,14 +32,15 @@ def u32(t):
 ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT, ss.SS_ALGO_BITONIC]
 
 
-def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False, algorithm=0):
+def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False, algorithm=0,
+              key32=False):
     d = ss.records_to_device(rec)
     if capacity is None:
         _, _, m, s = ss.count_pairs(d, W, H)
         assert int(s.item()) == 0
         capacity = int(m.item()) & 0xFFFFFFFF
     sorter = ss.FrameSorter(W, H, len(rec), capacity, radix_bits, items, stages=stages, unsorted=unsorted,
-                            algorithm=algorithm)
+                            algorithm=algorithm, key32=key32)
     out = sorter(d)
     st, m = out.result()
     res = {"status": st, "M": m}
@@ -247,3 +248,51 @@ def test_bitonic_sort_pairs_orders_by_key_then_value(n, key_bits):
                            torch.from_numpy(vals.view(np.int32)).cuda(), key_bits, algorithm=ss.SS_ALGO_BITONIC)
     order = np.lexsort((vals, keys))
     assert np.array_equal(u64(ko), keys[order]) and np.array_equal(u32(vo), vals[order])
+
+
+def assert_same_key32(W, H, rec, g):
+    """The paper's normalised 32-bit key order (bitonic network), bit for bit
+    against the oracle's definition of it; counts and offsets as usual."""
+    o = oracle.sort_frame_key32(W, H, rec)
+    assert o.status == 0
+    assert g["status"] == 0, _abi.status_string(g["status"])
+    assert g["M"] == o.num_pairs
+    assert np.array_equal(g["keys"], o.keys)
+    assert np.array_equal(g["values"], o.values)
+    assert np.array_equal(g["ranges"], o.ranges)
+    if len(rec):
+        e = oracle.sort_frame(W, H, rec)
+        assert np.array_equal(g["tiles_touched"], e.tiles_touched)
+        assert np.array_equal(g["offsets"], e.offsets.astype(np.uint32))
+
+
+def test_key32_tiny_and_boundary_frames():
+    import key32_pins
+    rs = np.random.default_rng(2025)
+    frames = [pins.random_tiny_frame(rs) for _ in range(40)] + [key32_pins.high_tile_frame()]
+    for case, (W, H, rec) in enumerate(frames):
+        print(f"key32 case {case}: {W}x{H} n={len(rec)}", flush=True)
+        assert_same_key32(W, H, rec, gpu_frame(W, H, rec, algorithm=ss.SS_ALGO_BITONIC, key32=True))
+
+
+@pytest.mark.parametrize("name", ["small-256x256", "fullhd-1m"])
+def test_key32_workloads(name):
+    spec, seed = synth.workload(name)
+    rec = synth.make_frame(spec, seed)
+    print(f"key32 workload {name}", flush=True)
+    assert_same_key32(spec.width, spec.height, rec,
+                      gpu_frame(spec.width, spec.height, rec, algorithm=ss.SS_ALGO_BITONIC, key32=True))
+
+
+@pytest.mark.parametrize("n", [0, 1, 37])
+def test_count_pairs_in_the_sort_workspace(n):
+    """ss_count_pairs runs in the workspace ss_workspace_bytes reports for
+    capacity 0 (N = 0 included, where its own layout is the larger one)."""
+    rec = synth.make_frame(synth.scaled(synth.SMALL, n), 77)[:n]
+    d = ss.records_to_device(rec)
+    tt, off, m, s = ss.count_pairs(d, 256, 256)
+    assert int(s.item()) == 0
+    o = oracle.sort_frame(256, 256, rec)
+    assert int(m.item()) == o.num_pairs
+    if n:
+        assert np.array_equal(u32(tt)[:n], o.tiles_touched)

@@ -267,6 +267,9 @@ struct PassChain {
   const uint32_t* hist;       // pass p's totals at hist + p * bins, copies hist_stride apart
   uint32_t hist_stride;
   uint32_t* lookback;         // [npasses][nblocks][bins]
+  uint32_t last_bits;         // significant bits of the last pass's digit when fewer
+                              // than radix_bits (keys known to be below 2^(shift0 +
+                              // radix_bits (npasses - 1) + last_bits)), else 0
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -288,7 +291,17 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.hist_stride = c.hist_stride;
       a.publish_passes = c.bases != nullptr && p == 0 ? c.npasses : 0u;
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
-      if (launch_pass(a, static_cast<int>(c.key_bytes), static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
+      // the last pass ranks only its significant digit bits where a narrower
+      // pass exists (its digits above them are empty; the histogram, base and
+      // look-back layouts stay those of radix_bits)
+      int rb = static_cast<int>(c.radix_bits);
+      if (p + 1 == c.npasses && c.last_bits != 0 && c.last_bits < c.radix_bits) {
+        const int narrow = narrow_pass_bits(static_cast<int>(c.last_bits), static_cast<int>(c.key_bytes),
+                                            static_cast<int>(c.radix_bits), static_cast<int>(c.cfg.items),
+                                            static_cast<int>(c.cfg.threads));
+        if (narrow != 0) rb = narrow;
+      }
+      if (launch_pass(a, static_cast<int>(c.key_bytes), rb, static_cast<int>(c.cfg.items),
                       static_cast<int>(c.cfg.threads), c.nblocks, s) != hipSuccess)
         return SS_ERR_HIP;
     }
@@ -372,7 +385,7 @@ ss_status run_direct(Launcher& L, const ss_frame* frame, const Geometry& g, cons
   }
   PassChain c{P, 8, 0, o.radix_bits, PassCfg{o.items, o.threads}, lay.pass_blocks, ks.data(), vs.data(),
               kd.data(), vd.data(), d_num_pairs, 0, d_status, bases, a.hist, lay.npasses * lay.bins,
-              at<uint32_t>(ws, lay.pass_lb)};
+              at<uint32_t>(ws, lay.pass_lb), g.key_bits - o.radix_bits * (P - 1)};
   SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   return L.run(SS_KERNEL_RANGES, [&] {
     return launch_ranges(out->keys, d_num_pairs, d_status, cap, g.num_tiles, out->tile_ranges, s);
@@ -504,7 +517,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       vd[p] = bv[(p + 1) % 2];
     }
     PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                d_status, bases_t, e.hist, P * lay.tbins, at<uint32_t>(ws, lay.lb_t)};
+                d_status, bases_t, e.hist, P * lay.tbins, at<uint32_t>(ws, lay.lb_t),
+                lay.tile_bits - o.radix_bits * (P - 1)};
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   }
   return L.run(SS_KERNEL_RANGES, [&] {

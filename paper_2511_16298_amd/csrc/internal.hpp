@@ -152,6 +152,9 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s);
+// The compiled digit width (>= bits) that a pass of this shape can use when
+// its digit has only `bits` significant bits, or 0 (use radix_bits).
+int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads);
 
 // Render (see render.hip).
 struct RenderArgs {

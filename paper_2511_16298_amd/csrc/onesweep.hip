@@ -279,6 +279,13 @@ bool pass_config_supported(int radix_bits, int items, int threads) {
   return rb_ok && it_ok && th_ok;
 }
 
+int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads) {
+  // compiled narrow widths: 64-bit keys, 8-bit passes of 512 threads
+  if (key_bytes != 8 || radix_bits != 8 || threads != 512 || (items != 8 && items != 16)) return 0;
+  if (bits <= 4) return 4;
+  return bits < 8 ? bits : 0;
+}
+
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
                        hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
@@ -289,6 +296,10 @@ hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int ite
   SS_PASS_CASE(uint64_t, 6, 16, 256) SS_PASS_CASE(uint64_t, 6, 12, 256) SS_PASS_CASE(uint64_t, 6, 8, 256)
   SS_PASS_CASE(uint64_t, 4, 16, 256) SS_PASS_CASE(uint64_t, 4, 12, 256) SS_PASS_CASE(uint64_t, 4, 8, 256)
   SS_PASS_CASE(uint64_t, 8, 16, 512) SS_PASS_CASE(uint64_t, 8, 8, 512)
+  SS_PASS_CASE(uint64_t, 7, 16, 512) SS_PASS_CASE(uint64_t, 7, 8, 512)
+  SS_PASS_CASE(uint64_t, 6, 16, 512) SS_PASS_CASE(uint64_t, 6, 8, 512)
+  SS_PASS_CASE(uint64_t, 5, 16, 512) SS_PASS_CASE(uint64_t, 5, 8, 512)
+  SS_PASS_CASE(uint64_t, 4, 16, 512) SS_PASS_CASE(uint64_t, 4, 8, 512)
   SS_PASS_CASE(uint32_t, 8, 16, 256) SS_PASS_CASE(uint32_t, 8, 12, 256) SS_PASS_CASE(uint32_t, 8, 8, 256)
   SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512)
 #undef SS_PASS_CASE

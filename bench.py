@@ -48,7 +48,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="fullhd-1m",
                    choices=sorted(synth.FRAME_WORKLOADS) + sorted(synth.SUPPLEMENTARY_WORKLOADS)
-                   + ["batch-64", "serve", "sweep", "render", "preprocess"])
+                   + ["batch-64", "serve", "sweep", "render", "preprocess", "shard-large-6m"])
+    p.add_argument("--bands", type=int, default=8, help="tile-row bands = GPUs of the sharded frame (shard-*)")
     p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
     p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
@@ -140,6 +141,22 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     wp = [v for k in tile for v in wby[k]]
     fetch = sum(fp) / len(fp) * f_scale * 1024.0
     write = sum(wp) / len(wp) * w_scale * 1024.0
+    # the whole frame step: every kernel launched at least once per frame
+    # (launches per frame = its calls / the calls of the per-frame count
+    # kernel in the timing run), its measured bytes and its time
+    calls = {short_name(r["Name"]): (int(r["Calls"]), float(r["AverageNs"])) for r in stats}
+    per_frame = calls.get("k_count_keys", (0, 0.0))[0]
+    step = None
+    if per_frame and workload != "preprocess":
+        b = t_ns = 0.0
+        for k, (c, avg) in calls.items():
+            if c < per_frame or k not in fby or k not in wby or k.startswith("at::") or "rocclr" in k:
+                continue
+            lpf = c / per_frame
+            b += lpf * (sum(fby[k]) / len(fby[k]) * f_scale + sum(wby[k]) / len(wby[k]) * w_scale) * 1024.0
+            t_ns += lpf * avg
+        step = {"bytes_per_frame": b, "kernel_us_per_frame": t_ns / 1e3,
+                "GB/s": b / t_ns, "frac_of_peak": b / t_ns / PEAK_HBM_GBS}
     others = {k: {"dispatches": len(fby[k]),
                   "fetch_bytes_per_launch": round(sum(fby[k]) / len(fby[k]) * f_scale * 1024.0),
                   "write_bytes_per_launch": round(sum(wby[k]) / len(wby[k]) * w_scale * 1024.0)}
@@ -148,7 +165,7 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     rec = {"kernel": " + ".join(tile), "workload": workload, "source_sha256_16": source_hash(ksrc),
            "copy_calibration_mib": copy_mib, "fetch_scale": f_scale, "write_scale": w_scale,
            "dispatches": len(fp), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-           "traffic_bytes_per_launch": fetch + write, "per_kernel": others,
+           "traffic_bytes_per_launch": fetch + write, "per_kernel": others, "step_measured": step,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py "
                         f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py "
@@ -159,6 +176,28 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
                 "# and the same per launch for every kernel of the step\n")
         f.write(json.dumps(rec, indent=1) + "\n")
     print(json.dumps(rec))
+
+
+def profiled_record(workload: str):
+    """The committed traffic record of the workload's roofline kernel, if it
+    was taken on that kernel's current source; else None."""
+    kname, _, ksrc = dominant_kernel(workload)
+    path = os.path.join(PROFILES, f"{kname}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    rec = json.loads(text[text.index("{"):])
+    return rec if rec.get("source_sha256_16") == source_hash(ksrc) else None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def profiled_traffic(workload: str):
@@ -366,6 +405,91 @@ def bench_serve(args):
 
 
 RENDER_FLOPS_PER_EVAL = 18   # dy 1, quadratic form 4, scale 1, exp 1, alpha 1, cap 1, T 2, weight 1, colour 6
+
+
+def bench_shard(args):
+    """One GPU's share of the heavy-tailed frame sharded over --bands GPUs by
+    tile-row bands (the design for more than one GPU: every GPU counts all N
+    Gaussians, sorts them by depth, and expands and sorts only its band's
+    pairs).  Each band runs alone on this GPU, in the launch configuration of
+    the whole frame; the slowest band bounds the sharded frame."""
+    import torch
+    import paper_2511_16298_amd as ss
+    from paper_2511_16298_amd import _abi
+
+    spec, seed = synth.workload("large-6m")
+    rec = synth.make_frame(spec, seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+
+    def timed(sorter, d):
+        for _ in range(W):
+            sorter(d, stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        ev[0].record(stream)
+        for i in range(K):
+            sorter(d, stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        st, m = sorter.out.result()
+        assert st == 0
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(K)], m
+
+    def sorter_for(h, d, drop):
+        _, _, m_t, s_t = ss.count_pairs(d, spec.width, h)
+        assert int(s_t.item()) == 0
+        return ss.FrameSorter(spec.width, h, int(d.shape[0]), int(m_t.item()) & 0xFFFFFFFF, device=dev,
+                              drop_culled=drop)
+
+    d_full = ss.records_to_device(rec, dev)
+    full_ms, m_full = timed(sorter_for(spec.height, d_full, False), d_full)
+    del d_full
+    rows = []
+    slowest = None
+    for h, r0, rb in synth.band_frames(rec, spec.width, spec.height, args.bands):
+        d = ss.records_to_device(rb, dev)
+        # most of the frame's Gaussians miss a band: the depth sort drops them
+        srt = sorter_for(h, d, True)
+        ms, m = timed(srt, d)
+        rows.append({"first_tile_row": r0, "height": h, "num_pairs": m, "p50_ms": pct(ms, 50), "p99_ms": pct(ms, 99)})
+        if slowest is None or pct(ms, 50) > slowest[0]:
+            timer = ss.Timer(max_launches=K * 12 + 16)
+            for _ in range(K):
+                srt(d, stream, timer=timer)
+            torch.cuda.synchronize()
+            pms, pn = timer.read(_abi.SS_KERNEL_SORT_PASS)
+            timer.close()
+            slowest = (pct(ms, 50), m, h, r0, rb, 1e3 * pms / pn)
+        del d, srt
+    t_band, m_band, h_band, r0_band, rec_band, pass_us = slowest
+    assert sum(r["num_pairs"] for r in rows) == m_full
+    achieved = 24.0 * m_band / (pass_us * 1e-6) / 1e9
+    line = {"metric": f"sorted key-value pairs/s of one GPU's share (1 of {args.bands} tile-row bands)",
+            "value": m_band / (t_band * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": t_band, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"shard-large-6m: large-6m ({spec.width}x{spec.height}, N={len(rec)}, "
+                                   f"M={m_full}) cut into {args.bands} bands of whole tile rows; the slowest "
+                                   f"band (tile rows from {r0_band}, {h_band} px) on one GPU",
+                       "parallelism": f"one GPU's band of {args.bands}", "flags": "SS_FLAG_DROP_CULLED"},
+            "bands": rows,
+            "whole_frame_p50_ms": pct(full_ms, 50),
+            "sharded_frame_bound_ms": t_band,
+            "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                         "bytes_per_launch": 24.0 * m_band, "avg_launch_us": pass_us}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        o = oracle.sort_frame(spec.width, h_band, rec_band, stages=False)
+        spent = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": o.num_pairs / spent, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the slowest band once ({spent:.1f} s, single-threaded oracle on "
+                                          f"{cpu_model()})"}
+    print(json.dumps(line), flush=True)
 
 
 def bench_render(args):
@@ -596,12 +720,12 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
-    if args.workload in ("batch-64", "serve", "sweep", "render", "preprocess"):
+    if args.workload in ("batch-64", "serve", "sweep", "render", "preprocess", "shard-large-6m"):
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
-         "render": bench_render, "preprocess": bench_preprocess}[args.workload](args)
+         "render": bench_render, "preprocess": bench_preprocess, "shard-large-6m": bench_shard}[args.workload](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sort of one frame runs on one device and "
@@ -716,7 +840,13 @@ def main():
                        "direct_path_bytes": direct_bytes},
         "kernels": kern,
         "instrumented_ms_per_step": instr_ms_per_step,
+        "host_wall_us_per_step": wall / K * 1e6,
     }
+    prof = profiled_record(args.workload)
+    if prof and prof.get("step_measured") and args.algorithm == "depth-first" and not args.radix_bits:
+        # whole-step HBM bytes measured by the counters (committed profile of
+        # this source) over the summed kernel time of the step
+        line["step_measured"] = prof["step_measured"]
 
     if not args.no_cpu_baseline:
         import oracle
@@ -735,7 +865,8 @@ def main():
                           and np.array_equal(res.values, vals_gpu) and np.array_equal(res.ranges, rng_gpu))
         line["cpu_baseline"] = {"value": frames * M / spent, "unit": "pairs/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{frames} whole {args.workload} frames ({spent:.1f} s, "
-                                          f"single-threaded oracle, {os.cpu_count()} host CPUs visible)"}
+                                          f"single-threaded oracle on {cpu_model()}, "
+                                          f"{os.cpu_count()} host CPUs visible)"}
         line["parity_vs_oracle"] = bool(parity)
         if key32:
             # how lossy the normalised key is on this frame: pairs whose position

@@ -94,7 +94,7 @@ typedef struct ss_options {
   uint32_t struct_size;
   uint32_t radix_bits;     /* 0 = default (8); supported: 4, 6, 8 */
   uint32_t items_per_thread; /* 0 = default (16); supported: 8, 12, 16 */
-  uint32_t flags;          /* 0, SS_FLAG_UNSORTED or SS_FLAG_KEY32_LOSSY */
+  uint32_t flags;          /* SS_FLAG_* (0 = none) */
   ss_timer* timer;         /* optional: record HIP events around every kernel */
   uint32_t workgroup_size; /* sort-pass threads: 0 = default (512 where
                               supported, else 256); 512 needs radix_bits 8
@@ -142,6 +142,14 @@ typedef struct ss_options {
  * T <= 2^20 (else SS_ERR_UNSUPPORTED); any other algorithm, ss_sort_pairs,
  * batches or SS_FLAG_UNSORTED with it are SS_ERR_UNSUPPORTED. */
 #define SS_FLAG_KEY32_LOSSY 2u
+/* Depth-first path (frames and batches): the first pass of the Gaussian depth
+ * sort drops the Gaussians that touch no tile, when they are more than 1/16
+ * of all, and the later passes and the duplication step handle only the rest.
+ * Same output.  Pays off for frames where many Gaussians fall outside the
+ * image, such as one GPU's band of a frame split by tile rows (every GPU
+ * sees all Gaussians); on frames with few culled Gaussians the extra decision
+ * costs a few microseconds.  No effect on the other algorithms. */
+#define SS_FLAG_DROP_CULLED 4u
 
 /* Library identification. */
 uint32_t ss_abi_version(void);

@@ -119,14 +119,15 @@ class FrameSorter:
     def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
                  radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
                  device="cuda", unsorted: bool = False, workgroup_size: int = 0, algorithm: int = 0,
-                 key32: bool = False):
+                 key32: bool = False, drop_culled: bool = False):
         torch = _torch()
         self.width, self.height = width, height
         self.num_gaussians = num_gaussians
         self.capacity = int(pair_capacity)
         self.tiles_x, self.tiles_y, self.key_bits = geometry(width, height)
         self.num_tiles = self.tiles_x * self.tiles_y
-        flags = (_abi.SS_FLAG_UNSORTED if unsorted else 0) | (_abi.SS_FLAG_KEY32_LOSSY if key32 else 0)
+        flags = ((_abi.SS_FLAG_UNSORTED if unsorted else 0) | (_abi.SS_FLAG_KEY32_LOSSY if key32 else 0)
+                 | (_abi.SS_FLAG_DROP_CULLED if drop_culled else 0))
         self.options = make_options(radix_bits, items_per_thread, flags=flags,
                                     workgroup_size=workgroup_size, algorithm=algorithm)
         probe = ss_frame()
@@ -176,12 +177,13 @@ class BatchSorter:
     ``[(width, height, num_gaussians), ...]`` (one segmented sort)."""
 
     def __init__(self, shapes, pair_capacity: int, radix_bits: int = 0, items_per_thread: int = 0,
-                 workgroup_size: int = 0, device="cuda", plan_workspace: bool = False):
+                 workgroup_size: int = 0, device="cuda", plan_workspace: bool = False, drop_culled: bool = False):
         import numpy as np
         torch = _torch()
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
         self.capacity = int(pair_capacity)
-        self.options = make_options(radix_bits, items_per_thread, workgroup_size=workgroup_size)
+        self.options = make_options(radix_bits, items_per_thread, workgroup_size=workgroup_size,
+                                    flags=_abi.SS_FLAG_DROP_CULLED if drop_culled else 0)
         tiles = [geometry(w, h)[0] * geometry(w, h)[1] for (w, h, _) in self.shapes]
         self.tile_base = np.concatenate([[0], np.cumsum(tiles)[:-1]]).astype(np.int64)
         self.num_tiles = int(sum(tiles))

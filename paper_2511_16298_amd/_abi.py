@@ -44,6 +44,7 @@ SS_MAX_BATCH_FRAMES = 256
 
 SS_FLAG_UNSORTED = 1
 SS_FLAG_KEY32_LOSSY = 2
+SS_FLAG_DROP_CULLED = 4
 
 SS_MAX_IMAGE_PX = 1048560
 SS_MAX_PAIR_CAPACITY = (1 << 30) - 1

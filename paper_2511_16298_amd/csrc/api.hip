@@ -38,7 +38,7 @@ ss_status parse_options(const ss_options* o, Options* out) {
   *out = Options{};
   if (o == nullptr) return SS_OK;
   if (o->struct_size < sizeof(ss_options)) return SS_ERR_INVALID_ARGUMENT;
-  if ((o->flags & ~(SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY)) != 0) return SS_ERR_UNSUPPORTED;
+  if ((o->flags & ~(SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY | SS_FLAG_DROP_CULLED)) != 0) return SS_ERR_UNSUPPORTED;
   if (o->algorithm > SS_ALGO_BITONIC) return SS_ERR_UNSUPPORTED;
   // the normalised 32-bit key belongs to the bitonic network and needs the sort
   if ((o->flags & SS_FLAG_KEY32_LOSSY) != 0 &&
@@ -172,7 +172,7 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
   L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
   size_t off = 0;
-  L.scalars = off;   off = align_up(off + 4 * sizeof(uint32_t));
+  L.scalars = off;   off = align_up(off + 8 * sizeof(uint32_t));  // status, M, offsets' M and status, live
   L.bad = off;       off = align_up(off + sizeof(uint32_t));
   L.totals = off;    off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
   L.ck_blocks = (n + kCountKeysTile - 1) / kCountKeysTile;
@@ -270,6 +270,10 @@ struct PassChain {
   uint32_t last_bits;         // significant bits of the last pass's digit when fewer
                               // than radix_bits (keys known to be below 2^(shift0 +
                               // radix_bits (npasses - 1) + last_bits)), else 0
+  // the Gaussian depth sort: the culled count's histogram words (the first
+  // pass may drop the culled), and where it stores the count it keeps
+  const uint32_t* culled;
+  uint32_t* kept;
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -290,6 +294,15 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.hist = c.hist ? c.hist + static_cast<size_t>(p) * bins : nullptr;
       a.hist_stride = c.hist_stride;
       a.publish_passes = c.bases != nullptr && p == 0 ? c.npasses : 0u;
+      if (c.kept != nullptr) {
+        if (p == 0) {
+          a.culled = c.culled;
+          a.kept = c.kept;
+        } else {
+          a.num_pairs = c.kept;
+          a.n_total = c.n_fixed;
+        }
+      }
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       // the last pass ranks only its significant digit bits where a narrower
       // pass exists (its digits above them are empty; the histogram, base and
@@ -464,16 +477,21 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   ck.block_total = at<unsigned long long>(ws, lay.block_total);
   ck.block_frame = at<uint32_t>(ws, lay.block_frame);
   ck.bad = at<uint32_t>(ws, lay.bad);
+  // with SS_FLAG_DROP_CULLED: Gaussians the depth sort keeps, stored by its first pass
+  uint32_t* live = (o.flags & SS_FLAG_DROP_CULLED) != 0 ? scal + 4 : nullptr;
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
 
-  // stable sort of the N Gaussians by depth: key -> alt -> key -> alt -> key
+  // stable sort of the Gaussians by depth: key -> alt -> key -> alt -> key;
+  // culled ones (no pairs) sort last, or, with SS_FLAG_DROP_CULLED and when
+  // they are many, the first pass drops them and the others sort the rest
   {
     const void* ks[4] = {key, key_alt, key, key_alt};
     const uint32_t* vs[4] = {val, val_alt, val, val_alt};
     void* kd[4] = {key_alt, key, key_alt, key};
     uint32_t* vd[4] = {val_alt, val, val_alt, val};
     PassChain c{4, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
-                nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d)};
+                nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d), 0,
+                live ? ck.hist + 3 * 256 + 255 : nullptr, live};  // digit 255 of the top byte: culled only
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
 
@@ -489,6 +507,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.table = table;
   e.n_frames = lay.n_frames;
   e.n = lay.n;
+  e.n_sorted = live;
   e.key = key;
   e.val = val;
   e.rect = ck.rect;

@@ -21,6 +21,7 @@ namespace {
 
 constexpr uint32_t kCountKeysThreads = 256;
 constexpr uint32_t kCountKeysItems = kCountKeysTile / kCountKeysThreads;
+constexpr unsigned long long kCulledOne = 1ull << 48;  // culled count, above the pair count
 constexpr uint32_t kExpandThreads = 512;
 constexpr uint32_t kExpandPer = kExpandTile / kExpandThreads;  // Gaussians per thread
 constexpr uint32_t kChunk = 4096;                             // pairs per expansion round
@@ -97,16 +98,26 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
       a.rect[g] = rect;
       a.key[g] = key;
       a.val[g] = g;
+      // culled keys (0xFFFFFFFF) all hit digit 255: counted per thread and
+      // added once per workgroup below instead of contending in LDS
+      if (cnt != 0) {
 #pragma unroll
-      for (uint32_t p = 0; p < 4; ++p) atomicAdd(&s_hist[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+        for (uint32_t p = 0; p < 4; ++p) atomicAdd(&s_hist[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+      } else {
+        tsum += kCulledOne;
+      }
     }
     if (a.tiles_touched) a.tiles_touched[g] = cnt;
     if (!one_frame && cnt) atomicAdd(&s_fm[f], static_cast<unsigned long long>(cnt));
     tsum += cnt;
   }
   const bool any_bad = __syncthreads_or(bad);
-  unsigned long long btotal;
-  block_exclusive_scan<unsigned long long, kCountKeysThreads>(tsum, s_tmp, btotal);
+  // one scan sums the pairs (below 2^44: 2,048 Gaussians of at most 2^32
+  // tiles) and, from bit 48, the culled Gaussians (at most 2,048)
+  unsigned long long both;
+  block_exclusive_scan<unsigned long long, kCountKeysThreads>(tsum, s_tmp, both);
+  const unsigned long long btotal = both & (kCulledOne - 1);
+  const uint32_t culled = static_cast<uint32_t>(both >> 48);
   if (tid == 0) {
     a.block_total[blockIdx.x] = one_frame ? btotal : 0ull;
     a.block_frame[blockIdx.x] = frame_of(s_tab, a.n_frames, base);
@@ -116,6 +127,9 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
     for (uint32_t f = tid; f < a.n_frames; f += kCountKeysThreads)
       if (s_fm[f]) atomicAdd(&a.totals[1 + f], s_fm[f]);
   if (a.rect == nullptr) return;
+  if (tid == 0 && culled != 0)
+    for (uint32_t p = 0; p < 4; ++p) s_hist[p * 256 + 255] += culled;
+  __syncthreads();
   uint32_t* gh = a.hist + static_cast<size_t>(blockIdx.x % kHistCopies) * 4 * 256;
   for (uint32_t i = tid; i < 4 * 256; i += kCountKeysThreads) {
     const uint32_t v = s_hist[i];
@@ -231,6 +245,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   __syncthreads();
   const uint32_t ticket = blockIdx.x;   // look-back order (see common.hpp)
   const uint32_t base = ticket * kExpandTile;
+  const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;  // Gaussians the depth sort kept
 
   // ---- Gaussians of this workgroup: striped loads, per-Gaussian info ----
 #pragma unroll
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     const uint32_t i = j * kExpandThreads + tid;
     const uint32_t pos = base + i;
     uint32_t cnt = 0;
-    const uint32_t g = pos < a.n ? a.val[pos] : 0xFFFFFFFFu;
+    const uint32_t g = pos < n_sorted ? a.val[pos] : 0xFFFFFFFFu;
     if (g < a.n) {  // a sorted index is always < n; the test only keeps reads in bounds
       const uint64_t r = a.rect[g];
       const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);

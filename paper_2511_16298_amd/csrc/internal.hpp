@@ -52,6 +52,18 @@ struct PassArgs {
   uint32_t hist_stride;
   uint32_t publish_passes;
   uint32_t* lookback;         // zeroed [nblocks][bins]
+  // The Gaussian depth sort's handling of culled Gaussians (key 0xFFFFFFFF,
+  // digit 255 of every pass; no other key has a top byte of 255, since depths
+  // are positive).  First pass (culled != NULL: the last pass's digit-255
+  // histogram word of copy 0, copies hist_stride apart): C = their sum; when
+  // C > n / 16 the pass drops the culled, writing the n - C others densely
+  // from position 0, and tile 0 stores what it keeps (n - C, or n) in *kept.
+  // Later passes (n_total != 0): their items are *num_pairs (the kept count)
+  // and the totals of digit 255 (histograms of all n_total keys) shrink by
+  // the n_total - *num_pairs dropped ones.
+  const uint32_t* culled;
+  uint32_t* kept;
+  uint32_t n_total;
 };
 
 struct HistArgs {
@@ -118,7 +130,8 @@ struct PairTotalsArgs {
 struct ExpandArgs {
   const FrameInfo* table;
   uint32_t n_frames;
-  uint32_t n;               // sorted Gaussians
+  uint32_t n;               // Gaussians (bound of the indices)
+  const uint32_t* n_sorted; // device count of the depth-sorted (live) Gaussians, or NULL (then n)
   const uint32_t* key;      // sorted depth keys
   const uint32_t* val;      // sorted global indices
   const uint64_t* rect;     // by global index

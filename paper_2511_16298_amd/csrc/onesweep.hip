@@ -35,17 +35,18 @@ struct PassSmem {
   uint32_t gofs[1 << RB];
   unsigned long long tmp[THREADS / kWave];
   uint32_t timeout;
+  uint32_t drop;     // 32-bit keys: this pass drops culled Gaussians
 };
 
-// The tile body.  FULL: every one of the TILE slots holds a pair (all tiles
-// but the last), so no per-item bounds tests are needed.
+// The tile body, in two parts: the loads, then ranking and scatter.  FULL:
+// every one of the TILE slots holds a pair (all tiles but the last, unless
+// items are dropped), so no per-item bounds tests are needed.
 template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
-__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
-                                          uint32_t base, uint32_t n) {
-  constexpr int WAVES = THREADS / kWave;
+__device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t base,
+                                          uint32_t n, uint32_t dropped, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
+                                          uint32_t (&dg)[ITEMS]) {
   constexpr int BINS = 1 << RB;
   constexpr uint32_t DMASK = BINS - 1;
-  constexpr int TILE = THREADS * ITEMS;
   const int tid = threadIdx.x;
   // 32-bit keys: global total of digit tid (summed over the histogram
   // copies), whose exclusive prefix over the digits is the digit's first
@@ -56,6 +57,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
       uint32_t gtot = 0;
 #pragma unroll
       for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + tid];
+      // culled Gaussians dropped by an earlier pass (all of digit 255)
+      if (tid == BINS - 1) gtot -= dropped;
       sm.gofs[tid] = gtot;
     }
   }
@@ -65,9 +68,6 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   const uint32_t lane = lane_id();
   const uint32_t wave = tid / kWave;
   const uint32_t seg = base + wave * (kWave * ITEMS);
-  K k[ITEMS];
-  uint32_t v[ITEMS];
-  uint32_t dg[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t idx = seg + j * kWave + lane;
@@ -81,6 +81,21 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
       dg[j] = BINS;  // not a pair
     }
   }
+}
+
+template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
+__device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
+                                          uint32_t base, uint32_t n, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
+                                          uint32_t (&dg)[ITEMS]) {
+  constexpr int WAVES = THREADS / kWave;
+  constexpr int BINS = 1 << RB;
+  constexpr uint32_t DMASK = BINS - 1;
+  constexpr int TILE = THREADS * ITEMS;
+  const int tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = tid / kWave;
+  (void)lane;
+  (void)DMASK;
 
   // ---- stable rank inside the wave ----
   // peers = lanes whose digit equals this lane's: for every digit bit b,
@@ -130,6 +145,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
     st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
   }
   uint32_t gbase, lexcl;
+  uint32_t tile_pairs = 0;  // 32-bit keys: valid items of the tile (some may be dropped)
   if constexpr (sizeof(K) == 4) {
     // one scan for both prefixes over the digits: the global digit bases
     // (high word) and this tile's digit starts (low word); neither carries
@@ -139,6 +155,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
         (static_cast<unsigned long long>(gtot) << 32) | bcnt, sm.tmp, total);
     gbase = static_cast<uint32_t>(both >> 32);
     lexcl = static_cast<uint32_t>(both);
+    tile_pairs = static_cast<uint32_t>(total);
   } else {
     uint32_t total;
     lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, reinterpret_cast<uint32_t*>(sm.tmp), total);
@@ -182,7 +199,11 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
 
   // ---- write keys: LDS slot i goes to global position gofs[digit] + i ----
   K* __restrict__ kout = static_cast<K*>(a.kout);
-  const uint32_t valid_n = FULL ? TILE : ((n - base) < static_cast<uint32_t>(TILE) ? (n - base) : TILE);
+  // pairs held in LDS: the whole tile, or the valid ones of a partial tile
+  // (the tail; with 32-bit keys also a tile with dropped items)
+  const uint32_t valid_n = FULL ? TILE
+                           : sizeof(K) == 4 ? tile_pairs
+                                            : ((n - base) < static_cast<uint32_t>(TILE) ? (n - base) : TILE);
   uint32_t dst[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -212,6 +233,16 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   }
 }
 
+template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
+                                          uint32_t base, uint32_t n, uint32_t dropped) {
+  K k[ITEMS];
+  uint32_t v[ITEMS];
+  uint32_t dg[ITEMS];
+  pass_load<K, RB, ITEMS, THREADS, FULL>(a, sm, base, n, dropped, k, v, dg);
+  pass_rest<K, RB, ITEMS, THREADS, FULL>(a, sm, t, base, n, k, v, dg);
+}
+
 // The extra workgroup of a chain's first 64-bit pass: digit bases of
 // publish_passes passes from the histogram copies, published with bit 31 set
 // (the current pass's first, since this launch's tiles need those now).
@@ -232,7 +263,9 @@ __device__ __forceinline__ void publish_bases(const PassArgs& a, uint32_t* s_tmp
   }
 }
 
-template <typename K, int RB, int ITEMS, int THREADS>
+// DROP (32-bit keys, the depth sort's first pass): may drop the culled
+// Gaussians (the decision is known only after the loads).
+template <typename K, int RB, int ITEMS, int THREADS, bool DROP>
 __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   constexpr int TILE = THREADS * ITEMS;
   __shared__ PassSmem<K, RB, ITEMS, THREADS> sm;
@@ -257,16 +290,57 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   }
   const uint32_t base = t * TILE;
   if (base >= n) return;  // uniform over the workgroup
-  if (n - base >= static_cast<uint32_t>(TILE))
-    pass_tile<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n);
-  else
-    pass_tile<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n);
+  if constexpr (!DROP) {
+    const uint32_t dropped = sizeof(K) == 4 && a.n_total != 0 ? a.n_total - n : 0u;
+    if (n - base >= static_cast<uint32_t>(TILE))
+      pass_tile<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n, dropped);
+    else
+      pass_tile<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n, dropped);
+  } else {
+    // the loads go out before the drop decision (one thread's reads of the
+    // culled count), which only marks the culled as not pairs
+    K k[ITEMS];
+    uint32_t v[ITEMS];
+    uint32_t dg[ITEMS];
+    pass_load<K, RB, ITEMS, THREADS, false>(a, sm, base, n, 0u, k, v, dg);
+    if (tid == 0) {
+      // drop when the culled are more than n / 16 (the same decision in
+      // every workgroup)
+      uint32_t c = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < kHistCopies; ++i) c += a.culled[static_cast<size_t>(i) * a.hist_stride];
+      const bool d = static_cast<unsigned long long>(c) * 16 > n;
+      if (t == 0) st_agent(a.kept, d ? n - c : n);
+      sm.drop = d;
+    }
+    __syncthreads();
+    if (sm.drop) {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (k[j] == 0xFFFFFFFFu) dg[j] = 1u << RB;  // culled Gaussian: not a pair
+    }
+    // a full tile that drops nothing is ranked without validity tests where
+    // the second variant fits the registers (up to 12 items per thread)
+    if constexpr (ITEMS <= 12) {
+      if (n - base >= static_cast<uint32_t>(TILE) && !sm.drop) {
+        pass_rest<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n, k, v, dg);
+        return;
+      }
+    }
+    pass_rest<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n, k, v, dg);
+  }
 }
 
 template <typename K, int RB, int ITEMS, int THREADS>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
   const uint32_t grid = nblocks + (sizeof(K) == 8 && a.publish_passes != 0 ? 1u : 0u);
-  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS>), dim3(grid), dim3(THREADS), 0, s, a);
+  if constexpr (sizeof(K) == 4) {
+    if (a.culled != nullptr) {
+      hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, true>), dim3(grid), dim3(THREADS), 0, s, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, false>), dim3(grid), dim3(THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -286,6 +286,28 @@ def make_scene(n: int, cam: Camera, seed: int) -> dict:
     return {"mean3d_opacity": m3, "cov3d": cov, "sh": sh.reshape(n, 48).astype(np.float32)}
 
 
+def band_frames(records: np.ndarray, width: int, height: int, bands: int) -> list:
+    """One frame cut into ``bands`` bands of whole tile rows (as equal as the
+    row count allows), each as a frame of its own: the same records with
+    mean_y moved up by the band's first pixel row, so that the band's tiles
+    are tiles 0 .. of the cut frame and everything else falls outside it.
+    Returns [(band_height, first_tile_row, records)].  Sorting band b and
+    adding first_tile_row * tiles_x to its tile ids gives the band's share of
+    the whole frame's output."""
+    ty = -(-height // 16)
+    bounds = [ty * b // bands for b in range(bands + 1)]
+    out = []
+    for b in range(bands):
+        r0, r1 = bounds[b], bounds[b + 1]
+        if r1 == r0:
+            continue
+        rec = np.array(records, copy=True)
+        rec["mean_y"] = rec["mean_y"].astype(np.int64) - 256 * r0
+        h = min(16 * r1, height) - 16 * r0
+        out.append((h, r0, rec))
+    return out
+
+
 def camera_params(cam: Camera, view=None, cam_pos=(0.0, 0.0, 0.0)) -> dict:
     """The camera as the float32 values a device call receives (principal point
     at the image centre, fx = fy = focal); both the device path and the CPU

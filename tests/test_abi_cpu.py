@@ -100,7 +100,7 @@ def test_sort_frame_argument_errors_are_synchronous():
     o = fake_out(cap=_abi.SS_MAX_PAIR_CAPACITY + 1)
     assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
     # options
-    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 4, 0), (0, 0, 0, 128),
+    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 8, 0), (0, 0, 0, 128),
                            (6, 0, 0, 512), (0, 12, 0, 512)]:
         opt = _abi.make_options(rb, it, flags=fl, workgroup_size=wg)
         assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, opt) == _abi.SS_ERR_UNSUPPORTED

@@ -296,3 +296,27 @@ def test_count_pairs_in_the_sort_workspace(n):
     assert int(m.item()) == o.num_pairs
     if n:
         assert np.array_equal(u32(tt)[:n], o.tiles_touched)
+
+
+@pytest.mark.parametrize("n", [200_000, 3_000_000])
+@pytest.mark.parametrize("culled_fraction", [0.0, 0.03, 0.5, 0.97, 1.0])
+def test_culled_gaussians_with_and_without_dropping(culled_fraction, n):
+    """Frames whose culled share (radius 0) is below and above the point
+    (1/16) where SS_FLAG_DROP_CULLED makes the depth sort drop them, for both
+    depth-tile shapes (below and above 2^21 Gaussians): the output is the same
+    with and without the flag (culled Gaussians have no pairs)."""
+    spec, seed = synth.workload("fullhd-1m")
+    rec = synth.make_frame(synth.scaled(spec, n), 4600)
+    rs = np.random.default_rng(4601)
+    rec["radius"][rs.random(len(rec)) < culled_fraction] = 0
+    print(f"culled {culled_fraction} n={n}", flush=True)
+    o = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+    d = ss.records_to_device(rec)
+    for drop in (False, True):
+        s = ss.FrameSorter(spec.width, spec.height, len(rec), o.num_pairs, drop_culled=drop)
+        s(d)
+        st, m = s.out.result()
+        assert st == 0 and m == o.num_pairs, drop
+        assert np.array_equal(u64(s.out.keys)[:m], o.keys), drop
+        assert np.array_equal(u32(s.out.values)[:m], o.values), drop
+        assert np.array_equal(u32(s.out.tile_ranges).reshape(-1, 2), o.ranges), drop

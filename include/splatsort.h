@@ -330,7 +330,7 @@ ss_status ss_copy_bytes(void* d_dst, const void* d_src, size_t bytes, void* stre
 typedef struct ss_render_desc {
   uint32_t struct_size;         /* sizeof(ss_render_desc) */
   uint32_t flags;               /* SS_RENDER_* */
-  const float* conic_opacity;   /* device [N][4]: a, b, c, opacity (16-B aligned) */
+  const float* conic_opacity;   /* device [N][4]: a, b, c, opacity in [0, 1] (16-B aligned) */
   const float* rgb;             /* device [N][4]: r, g, b, unused (16-B aligned) */
   const uint32_t* values;       /* device: the frame's sorted Gaussian indices */
   const uint32_t* tile_ranges;  /* device [2T]: the frame's tile ranges */

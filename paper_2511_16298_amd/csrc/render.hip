@@ -18,6 +18,10 @@ constexpr uint32_t kRenderWaves = 4;  // tiles per workgroup
 constexpr float kMaxAlpha = 0.99f;
 constexpr float kMinAlpha = 1.0f / 255.0f;
 constexpr float kMinT = 1e-4f;
+// opacity * exp(-q / 2) = 2^(log2(opacity) - q log2(e) / 2): the factor is
+// folded into the conic and log2(opacity) into the dx term once per
+// Gaussian, so a pixel evaluates 2^p, p = log2(o) + a' dx^2 + 2 b' dx dy + c' dy^2
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 
 __device__ __forceinline__ float bcast(float v, uint32_t lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -62,10 +66,10 @@ __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
       gy = static_cast<float>(m.y) * (1.0f / 16.0f);
       const float4 co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
       const float4 cl = reinterpret_cast<const float4*>(a.rgb)[gi];
-      ca = co.x;
-      cbv = co.y;
-      cc = co.z;
-      op = co.w;
+      ca = -kHalfLog2e * co.x;
+      cbv = -kHalfLog2e * co.y;
+      cc = -kHalfLog2e * co.z;
+      op = __builtin_amdgcn_logf(co.w);  // log2(opacity); opacity in (0, 1]
       r = cl.x;
       g = cl.y;
       bl = cl.z;
@@ -76,16 +80,17 @@ __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
       const float Gx = bcast(gx, j), Gy = bcast(gy, j);
       const float A = bcast(ca, j), B = bcast(cbv, j), C = bcast(cc, j), O = bcast(op, j);
       const float R = bcast(r, j), Gc = bcast(g, j), Bl = bcast(bl, j);
-      // q = A dx^2 + 2 B dx dy + C dy^2 = qa + dy (2 B dx + C dy): the dx
-      // terms are shared by the lane's four pixels (one column)
+      // p = log2(o) - q log2(e) / 2 with q = A dx^2 + 2 B dx dy + C dy^2, as
+      // (log2(o) + A' dx^2) + dy (2 B' dx + C' dy): the dx terms are shared
+      // by the lane's four pixels (one column); q >= 0 is p <= log2(o)
       const float dx = Gx - sx;
-      const float qa = A * dx * dx;
+      const float qa = fmaf(A * dx, dx, O);
       const float qb = 2.0f * B * dx;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const float dy = Gy - sy[k];
-        const float q = fmaf(dy, fmaf(C, dy, qb), qa);
-        const float e = O * __expf(-0.5f * q);
+        const float q = fmaf(dy, fmaf(C, dy, qb), qa);  // = p
+        const float e = __builtin_amdgcn_exp2f(q);
         if (EXACT) {
           const float w = e * T[k];
           cr[k] = fmaf(R, w, cr[k]);
@@ -96,7 +101,9 @@ __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
         } else {
           const float alpha = fminf(kMaxAlpha, e);
           if (STATS) evals += T[k] > 0.0f ? 1u : 0u;
-          const float ae = (q >= 0.0f && alpha >= kMinAlpha && T[k] > 0.0f) ? alpha : 0.0f;
+          // a stopped pixel needs no test here: its T is negative, so is
+          // next, which reads as a stop again and leaves it unchanged
+          const float ae = (q <= O && alpha >= kMinAlpha) ? alpha : 0.0f;
           const float next = fmaf(-ae, T[k], T[k]);
           const bool stop = next < kMinT;         // also true for a pixel already stopped
           const float w = stop ? 0.0f : ae * T[k];

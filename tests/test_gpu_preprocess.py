@@ -4,17 +4,22 @@ The kernel computes in FP32, so floating-point outputs are compared within
 bounds derived from FP32 rounding (u = 2^-24, eps = 2u), per Gaussian, from
 the oracle's own values:
   * conic: perturbing the 2D covariance C by dC moves C^-1 by about
-    C^-1 dC C^-1, so |d conic| <= ||dC|| / lmin^2; the products J R S R^T J^T
-    carry errors of a few eps x lmax, hence 32 eps lmax / lmin^2 (+ 8 eps
-    |conic|).  Opacity is copied: exact.
+    C^-1 dC C^-1, so |d conic| <= ||dC|| / lmin^2.  The products
+    J R S R^T J^T round relative to the size of their terms, not of their
+    result (a Gaussian stretched along the viewing ray has large terms that
+    cancel), so ||dC|| <= a few eps (||J||_F^2 ||S||_F + lmax) (R is
+    orthonormal); bound 32 eps (||J||_F^2 ||S||_F + lmax) / lmin^2 (+ 8 eps
+    |conic|), with ||J||_F^2 = (fx / z)^2 (1 + ux^2) + (fy / z)^2 (1 + uy^2)
+    at the clamped u = t.xy / z.  Opacity is copied: exact.
   * pixel mean: x = fx t.x / t.z + cx takes four roundings, plus the error of
     t = R p + T (3 roundings of |R||p| + |T| per component, zero for the
     identity view) scaled by fx / z (1 + |t.x / t.z|); bound 8 eps (...).  The
     fixed-point mean (16 x) must then be exact wherever the oracle's distance
     to a rounding boundary exceeds 16 times that bound, and within 1 elsewhere.
-  * radius: 3 sqrt(l1) has a relative error of a few eps (l1 from a, b, c);
-    exact where the oracle's distance of 3 sqrt(l1) to an integer exceeds
-    64 eps 3 sqrt(l1), within 1 elsewhere.
+  * radius: 3 sqrt(l1) moves by 3 dl1 / (2 sqrt(l1)) with dl1 of the order
+    of ||dC|| above; exact where the oracle's distance of 3 sqrt(l1) to an
+    integer exceeds 32 eps 3 sqrt(l1) (||J||_F^2 ||S||_F + l1) / l1, within
+    1 elsewhere.
   * colour: 1/2 + sum of sh_k Y_k, 16 products whose rounding (and that of
     the unit direction) stays below 32 eps (1/2 + 1.1 sum |sh_k|), since
     |Y_k| <= 1.1 for degree <= 3.
@@ -102,14 +107,22 @@ def compare(p, scene, gpu, label):
     mid = 0.5 * (A + C)
     gap = np.sqrt(0.25 * (A - C) ** 2 + B * B)
     lmax, lmin = mid + gap, mid - gap
-    r3 = 3 * np.sqrt(mid + np.sqrt(np.maximum(0.1, gap * gap)))
+    l1 = mid + np.sqrt(np.maximum(0.1, gap * gap))
+    r3 = 3 * np.sqrt(l1)
+    # size of the terms of J R S R^T J^T: ||J||_F^2 ||S||_F
+    tan = np.array([p["tan_fovx"], p["tan_fovy"]])
+    u = np.clip(t[live, :2] / z[:, None], -1.3 * tan, 1.3 * tan)
+    j2 = (p["fx"] / z) ** 2 * (1 + u[:, 0] ** 2) + (p["fy"] / z) ** 2 * (1 + u[:, 1] ** 2)
+    cv = scene["cov3d"][live].astype(np.float64)
+    s_f = np.sqrt(cv[:, 0] ** 2 + cv[:, 3] ** 2 + cv[:, 5] ** 2 + 2 * (cv[:, 1] ** 2 + cv[:, 2] ** 2 + cv[:, 4] ** 2))
+    terms = j2 * s_f
     d = np.abs(rec["radius"][live].astype(np.int64) - o.records["radius"][live].astype(np.int64))
-    tight = o.margin[live, 2] <= 64 * EPS * r3
+    tight = o.margin[live, 2] <= 32 * EPS * r3 * (terms + l1) / l1
     assert np.all(d[~tight] == 0), (label, "radius")
     assert np.all(d[tight] <= 1), (label, "radius")
     ambiguous += int(np.count_nonzero(d))
     # conic and opacity
-    tol = 32 * EPS * lmax / lmin ** 2
+    tol = 32 * EPS * (terms + lmax) / lmin ** 2
     for k in range(3):
         err = np.abs(co[live, k] - o.conic_opacity[live, k])
         assert np.all(err <= tol + 8 * EPS * np.abs(o.conic_opacity[live, k])), (label, "conic", k, err.max())
@@ -204,3 +217,37 @@ def test_preprocess_then_sort_matches_oracle_chain():
     assert np.array_equal(out.keys.cpu().numpy().view(np.uint64)[:M], want.keys)
     assert np.array_equal(out.values.cpu().numpy().view(np.uint32)[:M], want.values)
     assert np.array_equal(out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), want.ranges)
+
+
+def test_preprocess_extreme_shapes():
+    """Scales from 1e-6 to 1 of the depth, anisotropy up to 1e4, random
+    rotations: footprints from well below a pixel (the 0.3 dilation
+    dominates) to hundreds of pixels, and conics whose two eigenvalues are
+    far apart; the bounds scale with lmax / lmin^2 and hold throughout."""
+    cam = synth.SCENE_CAMERA
+    n = 20_000
+    rs = np.random.default_rng(4700)
+    z = np.exp(rs.uniform(np.log(0.5), np.log(60.0), n))
+    tx, ty = cam.tan_fov
+    x = rs.uniform(-1.2, 1.2, n) * tx * z
+    y = rs.uniform(-1.2, 1.2, n) * ty * z
+    base = np.exp(rs.uniform(np.log(1e-6), np.log(1.0), n)) * z
+    aniso = np.exp(rs.uniform(0.0, np.log(1e4), (n, 3)))
+    sc = base[:, None] / aniso
+    q = rs.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, qx, qy, qz = q.T
+    R = np.stack([np.stack([1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - w * qz), 2 * (qx * qz + w * qy)], -1),
+                  np.stack([2 * (qx * qy + w * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - w * qx)], -1),
+                  np.stack([2 * (qx * qz - w * qy), 2 * (qy * qz + w * qx), 1 - 2 * (qx * qx + qy * qy)], -1)], 1)
+    M = R * sc[:, None, :]
+    S = M @ np.transpose(M, (0, 2, 1))
+    scene = {"mean3d_opacity": np.stack([x, y, z, rs.uniform(0.05, 0.99, n)], 1).astype(np.float32),
+             "cov3d": np.zeros((n, 8), np.float32),
+             "sh": (0.3 * rs.normal(size=(n, 48))).astype(np.float32)}
+    c = scene["cov3d"]
+    c[:, 0], c[:, 1], c[:, 2] = S[:, 0, 0], S[:, 0, 1], S[:, 0, 2]
+    c[:, 3], c[:, 4], c[:, 5] = S[:, 1, 1], S[:, 1, 2], S[:, 2, 2]
+    p = synth.camera_params(cam)
+    print("preprocess extreme shapes", flush=True)
+    compare(p, scene, run_gpu(p, scene), "extreme")

@@ -84,6 +84,8 @@ def dominant_kernel(workload: str):
     preprocessing workload, else the 64-bit-key (tile) sort pass."""
     if workload == "preprocess":
         return "k_preprocess", "", os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "preprocess.hip")
+    if workload == "render":
+        return "k_render", "", os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "render.hip")
     return PASS_KERNEL, "unsigned long", PASS_SOURCE
 
 

@@ -40,7 +40,8 @@ struct PassSmem {
 
 // The tile body, in two parts: the loads, then ranking and scatter.  FULL:
 // every one of the TILE slots holds a pair (all tiles but the last, unless
-// items are dropped), so no per-item bounds tests are needed.
+// items are dropped), so no per-item bounds tests are needed.  `dropped`
+// (32-bit keys): culled items an earlier pass dropped, all of digit 255.
 template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
 __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t base,
                                           uint32_t n, uint32_t dropped, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
@@ -92,10 +93,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   constexpr uint32_t DMASK = BINS - 1;
   constexpr int TILE = THREADS * ITEMS;
   const int tid = threadIdx.x;
-  const uint32_t lane = lane_id();
   const uint32_t wave = tid / kWave;
-  (void)lane;
-  (void)DMASK;
 
   // ---- stable rank inside the wave ----
   // peers = lanes whose digit equals this lane's: for every digit bit b,

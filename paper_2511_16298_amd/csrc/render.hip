@@ -4,10 +4,11 @@
 // unrolled).  On MI355X one wave64 owns one tile: lane l holds the four
 // pixels l, l + 64, l + 128, l + 192 of the tile (rows l/16, l/16 + 4, ...).
 // Every 64 list entries the lanes load one Gaussian each (mean, conic and
-// opacity, colour); the wave then walks them in order, each Gaussian's nine
-// values broadcast from its lane with readlane (no LDS, no barrier), and
-// every lane blends its four pixels.  The wave leaves the list as soon as all
-// 256 pixels have stopped.
+// opacity, colour) and store its nine per-Gaussian values in the wave's own
+// LDS slots; the wave then walks them in order, all lanes reading the same
+// slot (a broadcast read, on the LDS pipe rather than the vector ALU), and
+// every lane blends its four pixels.  The wave leaves the list once all 256
+// pixels have stopped, tested every fourth Gaussian.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -23,8 +24,64 @@ constexpr float kMinT = 1e-4f;
 // Gaussian, so a pixel evaluates 2^p, p = log2(o) + a' dx^2 + 2 b' dx dy + c' dy^2
 constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 
-__device__ __forceinline__ float bcast(float v, uint32_t lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+// A tile's Gaussian batch in LDS: 64 slots of nine values.
+struct RenderSlots {
+  float4 geo[kWave];   // mean x, mean y, -log2(e)/2 * (conic a, conic b)
+  float4 mix[kWave];   // -log2(e)/2 * conic c, log2(opacity), red, green
+  float blue[kWave];
+};
+
+// Gaussians blended between two tests of the wave's live pixels.  A batch's
+// slots past its last entry hold a Gaussian that changes no pixel (opacity 0:
+// log2 = -inf, so 2^p = 0), so every batch walks whole groups; a stopped pixel
+// is left unchanged by further Gaussians, so testing once a group only adds
+// work, never changes the image.
+constexpr uint32_t kGroup = 4;
+
+// Blends the Gaussian of slot j into the lane's four pixels.  `counted`
+// (uniform): slot j holds a list entry, not padding (for the statistics).
+template <bool EXACT, bool STATS>
+__device__ __forceinline__ void blend(const RenderSlots& sl, uint32_t j, bool counted, float sx, const float (&sy)[4],
+                                      float (&T)[4], float (&cr)[4], float (&cg)[4], float (&cb)[4], uint32_t (&n)[4],
+                                      uint32_t& evals) {
+  const float4 g0 = sl.geo[j], g1 = sl.mix[j];
+  const float Gx = g0.x, Gy = g0.y, A = g0.z, B = g0.w, C = g1.x, O = g1.y;
+  const float R = g1.z, Gc = g1.w, Bl = sl.blue[j];
+  // p = log2(o) - q log2(e) / 2 with q = A dx^2 + 2 B dx dy + C dy^2, as
+  // (log2(o) + A' dx^2) + dy (2 B' dx + C' dy): the dx terms are shared by
+  // the lane's four pixels (one column); q >= 0 is p <= log2(o)
+  const float dx = Gx - sx;
+  const float qa = fmaf(A * dx, dx, O);
+  const float qb = 2.0f * B * dx;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float dy = Gy - sy[k];
+    const float q = fmaf(dy, fmaf(C, dy, qb), qa);  // = p
+    const float e = __builtin_amdgcn_exp2f(q);
+    if (EXACT) {
+      const float w = e * T[k];
+      cr[k] = fmaf(R, w, cr[k]);
+      cg[k] = fmaf(Gc, w, cg[k]);
+      cb[k] = fmaf(Bl, w, cb[k]);
+      T[k] = fmaf(-e, T[k], T[k]);
+      if (STATS) n[k] += counted ? 1u : 0u;
+    } else {
+      const float alpha = fminf(kMaxAlpha, e);
+      if (STATS) evals += counted && T[k] > 0.0f ? 1u : 0u;
+      // a stopped pixel needs no test here: its T is negative, so is next,
+      // which reads as a stop again and leaves it unchanged
+      const float ae = (q <= O && alpha >= kMinAlpha) ? alpha : 0.0f;
+      const float next = fmaf(-ae, T[k], T[k]);
+      const bool stop = next < kMinT;  // also true for a pixel already stopped
+      const float w = stop ? 0.0f : ae * T[k];
+      cr[k] = fmaf(R, w, cr[k]);
+      cg[k] = fmaf(Gc, w, cg[k]);
+      cb[k] = fmaf(Bl, w, cb[k]);
+      T[k] = stop ? -fabsf(T[k]) : next;
+      if (STATS) n[k] += w != 0.0f ? 1u : 0u;
+    }
+  }
+  if (EXACT && STATS) evals += counted ? 4u : 0u;
 }
 
 // EXACT: no thresholds.  STATS: also count the Gaussians composited per pixel
@@ -33,10 +90,14 @@ __device__ __forceinline__ float bcast(float v, uint32_t lane) {
 // branches, and the lanes never diverge.
 template <bool EXACT, bool STATS>
 __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
+  __shared__ RenderSlots slots[kRenderWaves];
   if (a.status && *a.status != SS_OK) return;
   const uint32_t lane = lane_id();
-  const uint32_t tile = blockIdx.x * kRenderWaves + threadIdx.x / kWave;
-  if (tile >= a.tiles_x * a.tiles_y) return;  // uniform over the wave
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // uniform over the wave: the list bounds are scalar loads
+  const uint32_t tile = blockIdx.x * kRenderWaves + wave;
+  if (tile >= a.tiles_x * a.tiles_y) return;
+  RenderSlots& sl = slots[wave];
   const uint32_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
 
@@ -56,71 +117,41 @@ __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
   }
   uint32_t evals = 0;
 
-  for (uint32_t b = start; b < end; b += kWave) {
-    // one Gaussian per lane
-    float gx = 0.f, gy = 0.f, ca = 0.f, cbv = 0.f, cc = 0.f, op = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+  bool live = true;
+  for (uint32_t b = start; b < end && live; b += kWave) {
+    // one Gaussian per lane into the wave's slots; padding past the end
+    float4 geo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 mix = make_float4(0.0f, -__builtin_inff(), 0.0f, 0.0f);
+    float blue = 0.0f;
     if (b + lane < end) {
       const uint32_t gi = a.values[b + lane];
       const int2 m = *reinterpret_cast<const int2*>(a.gaussians + gi);
-      gx = static_cast<float>(m.x) * (1.0f / 16.0f);
-      gy = static_cast<float>(m.y) * (1.0f / 16.0f);
       const float4 co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
       const float4 cl = reinterpret_cast<const float4*>(a.rgb)[gi];
-      ca = -kHalfLog2e * co.x;
-      cbv = -kHalfLog2e * co.y;
-      cc = -kHalfLog2e * co.z;
-      op = __builtin_amdgcn_logf(co.w);  // log2(opacity); opacity in (0, 1]
-      r = cl.x;
-      g = cl.y;
-      bl = cl.z;
+      geo = make_float4(static_cast<float>(m.x) * (1.0f / 16.0f), static_cast<float>(m.y) * (1.0f / 16.0f),
+                        -kHalfLog2e * co.x, -kHalfLog2e * co.y);
+      // log2(opacity); opacity in (0, 1]
+      mix = make_float4(-kHalfLog2e * co.z, __builtin_amdgcn_logf(co.w), cl.x, cl.y);
+      blue = cl.z;
     }
+    sl.geo[lane] = geo;
+    sl.mix[lane] = mix;
+    sl.blue[lane] = blue;
+    // the slots are this wave's alone and its LDS accesses complete in
+    // order, so the reads below see the stores above without a barrier
+    __builtin_amdgcn_wave_barrier();
     const uint32_t count = end - b < kWave ? end - b : kWave;
-    bool any_live = true;
-    for (uint32_t j = 0; j < count && any_live; ++j) {
-      const float Gx = bcast(gx, j), Gy = bcast(gy, j);
-      const float A = bcast(ca, j), B = bcast(cbv, j), C = bcast(cc, j), O = bcast(op, j);
-      const float R = bcast(r, j), Gc = bcast(g, j), Bl = bcast(bl, j);
-      // p = log2(o) - q log2(e) / 2 with q = A dx^2 + 2 B dx dy + C dy^2, as
-      // (log2(o) + A' dx^2) + dy (2 B' dx + C' dy): the dx terms are shared
-      // by the lane's four pixels (one column); q >= 0 is p <= log2(o)
-      const float dx = Gx - sx;
-      const float qa = fmaf(A * dx, dx, O);
-      const float qb = 2.0f * B * dx;
+    for (uint32_t j = 0; j < count; j += kGroup) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float dy = Gy - sy[k];
-        const float q = fmaf(dy, fmaf(C, dy, qb), qa);  // = p
-        const float e = __builtin_amdgcn_exp2f(q);
-        if (EXACT) {
-          const float w = e * T[k];
-          cr[k] = fmaf(R, w, cr[k]);
-          cg[k] = fmaf(Gc, w, cg[k]);
-          cb[k] = fmaf(Bl, w, cb[k]);
-          T[k] = fmaf(-e, T[k], T[k]);
-          if (STATS) ++n[k];
-        } else {
-          const float alpha = fminf(kMaxAlpha, e);
-          if (STATS) evals += T[k] > 0.0f ? 1u : 0u;
-          // a stopped pixel needs no test here: its T is negative, so is
-          // next, which reads as a stop again and leaves it unchanged
-          const float ae = (q <= O && alpha >= kMinAlpha) ? alpha : 0.0f;
-          const float next = fmaf(-ae, T[k], T[k]);
-          const bool stop = next < kMinT;         // also true for a pixel already stopped
-          const float w = stop ? 0.0f : ae * T[k];
-          cr[k] = fmaf(R, w, cr[k]);
-          cg[k] = fmaf(Gc, w, cg[k]);
-          cb[k] = fmaf(Bl, w, cb[k]);
-          T[k] = stop ? -fabsf(T[k]) : next;
-          if (STATS) n[k] += w != 0.0f ? 1u : 0u;
-        }
-      }
-      if (EXACT) {
-        if (STATS) evals += 4;
-      } else {
-        any_live = ballot(fmaxf(fmaxf(T[0], T[1]), fmaxf(T[2], T[3])) > 0.0f) != 0;
+      for (uint32_t u = 0; u < kGroup; ++u)
+        blend<EXACT, STATS>(sl, j + u, j + u < count, sx, sy, T, cr, cg, cb, n, evals);
+      if (!EXACT) {
+        live = ballot(fmaxf(fmaxf(T[0], T[1]), fmaxf(T[2], T[3])) > 0.0f) != 0;
+        if (!live) break;
       }
     }
-    if (!any_live) break;
+    // the next batch's stores follow this batch's reads
+    __builtin_amdgcn_wave_barrier();
   }
 
   const uint32_t W = a.width, H = a.height;

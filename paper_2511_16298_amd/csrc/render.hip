@@ -87,9 +87,12 @@ __device__ __forceinline__ void blend(const RenderSlots& sl, uint32_t j, bool co
 // EXACT: no thresholds.  STATS: also count the Gaussians composited per pixel
 // and the evaluations per tile.  A pixel that has stopped keeps its T with the
 // sign bit set (T > 0 means live), so the thresholds cost selects, not
-// branches, and the lanes never diverge.
+// branches, and the lanes never diverge.  The plain kernels are held to 64
+// VGPRs, eight waves per SIMD: a full-HD frame's 8,160 tile waves are then all
+// resident at once, which beats both fewer resident waves and fewer registers
+// spent on the next batch's loads.
 template <bool EXACT, bool STATS>
-__global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
+__global__ __launch_bounds__(kRenderWaves * kWave) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 8, 8))) void k_render(RenderArgs a) {
   __shared__ RenderSlots slots[kRenderWaves];
   if (a.status && *a.status != SS_OK) return;
   const uint32_t lane = lane_id();
@@ -117,26 +120,35 @@ __global__ __launch_bounds__(kRenderWaves * kWave) void k_render(RenderArgs a) {
   }
   uint32_t evals = 0;
 
+  // The next batch's Gaussians are loaded while the wave walks the current
+  // one, so the gathers' latency hides behind the blending.
+  int2 m = make_int2(0, 0);
+  float4 co = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cl = co;
+  if (start + lane < end) {
+    const uint32_t gi = a.values[start + lane];
+    m = *reinterpret_cast<const int2*>(a.gaussians + gi);
+    co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
+    cl = reinterpret_cast<const float4*>(a.rgb)[gi];
+  }
   bool live = true;
   for (uint32_t b = start; b < end && live; b += kWave) {
     // one Gaussian per lane into the wave's slots; padding past the end
-    float4 geo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float4 mix = make_float4(0.0f, -__builtin_inff(), 0.0f, 0.0f);
-    float blue = 0.0f;
-    if (b + lane < end) {
-      const uint32_t gi = a.values[b + lane];
-      const int2 m = *reinterpret_cast<const int2*>(a.gaussians + gi);
-      const float4 co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
-      const float4 cl = reinterpret_cast<const float4*>(a.rgb)[gi];
-      geo = make_float4(static_cast<float>(m.x) * (1.0f / 16.0f), static_cast<float>(m.y) * (1.0f / 16.0f),
-                        -kHalfLog2e * co.x, -kHalfLog2e * co.y);
-      // log2(opacity); opacity in (0, 1]
-      mix = make_float4(-kHalfLog2e * co.z, __builtin_amdgcn_logf(co.w), cl.x, cl.y);
-      blue = cl.z;
+    const bool valid = b + lane < end;
+    sl.geo[lane] = make_float4(valid ? static_cast<float>(m.x) * (1.0f / 16.0f) : 0.0f,
+                               valid ? static_cast<float>(m.y) * (1.0f / 16.0f) : 0.0f,
+                               valid ? -kHalfLog2e * co.x : 0.0f, valid ? -kHalfLog2e * co.y : 0.0f);
+    // log2(opacity); opacity in (0, 1]
+    sl.mix[lane] = make_float4(valid ? -kHalfLog2e * co.z : 0.0f,
+                               valid ? __builtin_amdgcn_logf(co.w) : -__builtin_inff(), valid ? cl.x : 0.0f,
+                               valid ? cl.y : 0.0f);
+    sl.blue[lane] = valid ? cl.z : 0.0f;
+    const uint32_t nb = b + kWave;
+    if (nb + lane < end) {
+      const uint32_t gi = a.values[nb + lane];
+      m = *reinterpret_cast<const int2*>(a.gaussians + gi);
+      co = reinterpret_cast<const float4*>(a.conic_opacity)[gi];
+      cl = reinterpret_cast<const float4*>(a.rgb)[gi];
     }
-    sl.geo[lane] = geo;
-    sl.mix[lane] = mix;
-    sl.blue[lane] = blue;
     // the slots are this wave's alone and its LDS accesses complete in
     // order, so the reads below see the stores above without a barrier
     __builtin_amdgcn_wave_barrier();

@@ -122,3 +122,40 @@ def test_failed_sort_writes_nothing():
     r(d, cod, cld, out.values, out.tile_ranges, bad)
     torch.cuda.synchronize()
     assert bool(torch.all(r.out.color == -7.0))
+
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("name", ["small-256x256", "fullhd-1m"])
+def test_plain_variant_matches_counting_variant(name, exact):
+    """The kernel without the per-pixel and per-tile counters (the one a
+    caller gets when it asks for neither) does the same arithmetic in the same
+    order as the counting kernel, which the tests above compare with the
+    oracle: colour and T must agree bit for bit.  The threshold-mode
+    evaluation counts are bounded by the composited counts below and by 256
+    evaluations per list entry above."""
+    spec, seed = synth.FRAME_WORKLOADS[name]
+    rec = synth.make_frame(spec, seed)
+    co, cl = synth.make_render_attrs(rec, seed)
+    d = ss.records_to_device(rec)
+    out = ss.sort_frame(d, spec.width, spec.height)
+    st, _ = out.result()
+    assert st == 0
+    cod, cld = ss.render_attrs_to_device(co, cl)
+    bg = (0.1, 0.2, 0.3)
+    plain = ss.Renderer(spec.width, spec.height, want_T=True)
+    counting = ss.Renderer(spec.width, spec.height, want_T=True, want_contrib=True, want_tile_evals=True)
+    a = plain(d, cod, cld, out.values, out.tile_ranges, out.status, bg, exact)
+    b = counting(d, cod, cld, out.values, out.tile_ranges, out.status, bg, exact)
+    torch.cuda.synchronize()
+    assert torch.equal(a.color.view(torch.int32), b.color.view(torch.int32))
+    assert torch.equal(a.T.view(torch.int32), b.T.view(torch.int32))
+    if not exact:
+        tx, ty, _ = ss.geometry(spec.width, spec.height)
+        contrib = b.contrib.cpu().numpy().view(np.uint32).astype(np.int64)
+        pad = np.zeros((ty * 16, tx * 16), np.int64)
+        pad[:spec.height, :spec.width] = contrib
+        per_tile = pad.reshape(ty, 16, tx, 16).sum(axis=(1, 3)).reshape(-1)
+        evals = b.tile_evals.cpu().numpy().view(np.uint32).astype(np.int64)
+        rng = out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+        assert np.all(evals >= per_tile)
+        assert np.all(evals <= 256 * (rng[:, 1] - rng[:, 0]))

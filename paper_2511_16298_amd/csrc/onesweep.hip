@@ -12,8 +12,8 @@
 namespace ss {
 namespace {
 
-// Workgroup of 256 threads (4 waves), ITEMS pairs per thread.  Pairs are
-// loaded wave-striped: wave w owns the contiguous segment
+// Workgroup of THREADS threads (256 or 512: 4 or 8 waves), ITEMS pairs per
+// thread.  Pairs are loaded wave-striped: wave w owns the contiguous segment
 // [w * 64 * ITEMS, (w + 1) * 64 * ITEMS) of the tile and lane l holds elements
 // j * 64 + l, so every load instruction reads 64 consecutive pairs.
 //
@@ -25,8 +25,9 @@ namespace {
 // the input order inside the wave; waves are then offset by the counts of
 // earlier waves, and digits by a workgroup scan.  The tile is permuted into
 // digit order in LDS -- keys first, then values through the same buffer, to
-// keep LDS small enough for four workgroups per CU -- and written out so that
-// runs of one digit land on consecutive addresses.
+// keep LDS small (160 KB per CU holds four 256 x 16 tiles of 64-bit keys, or
+// two 512 x 16 ones) -- and written out so that runs of one digit land on
+// consecutive addresses.
 template <typename K, int RB, int ITEMS, int THREADS>
 struct PassSmem {
   K buf[THREADS * ITEMS];  // keys, then values (as uint32)

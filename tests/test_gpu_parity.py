@@ -168,6 +168,26 @@ def test_pair_counts_around_tile_sizes(m, algo):
     assert_same(1920, 1080, rec, gpu_frame(1920, 1080, rec, algorithm=algo))
 
 
+# (tiles_x, tiles_y, width and height trimmed by so many px): tile counts just
+# below, at and above powers of two, where the number of tile-digit passes and
+# the width of the last (narrowed) pass change: 255 / 256 / 257 tiles (one or
+# two 8-bit passes, the second with 1 significant bit), 4,095 / 4,096 / 4,097,
+# 65,535 / 65,536 / 65,792, and 16,777,215 / 16,781,312 (three or four passes).
+TILE_GRIDS = [(15, 17, 0), (16, 16, 5), (257, 1, 3), (63, 65, 7), (64, 64, 0), (17, 241, 9),
+              (255, 257, 0), (256, 256, 1), (257, 256, 0), (4097, 4095, 11), (4097, 4096, 0)]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("grid", TILE_GRIDS, ids=lambda g: f"{g[0]}x{g[1]}")
+def test_tile_counts_around_powers_of_two(grid, algo):
+    tx, ty, trim = grid
+    W, H = 16 * tx - trim, 16 * ty - trim
+    n = 30_000 if tx * ty > 4096 else 6_000
+    rec = synth.make_frame(synth.FrameSpec(W, H, n, radius_cap=48), 4000 + tx + ty)
+    print(f"tile grid {tx}x{ty} ({W}x{H} px), N={n}, algorithm {algo}", flush=True)
+    assert_same(W, H, rec, gpu_frame(W, H, rec, stages=False, algorithm=algo), stages=False)
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 def test_device_errors(algo):
     spec, seed = synth.FRAME_WORKLOADS["small-256x256"]

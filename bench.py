@@ -870,6 +870,25 @@ def main():
                                           f"single-threaded oracle on {cpu_model()}, "
                                           f"{os.cpu_count()} host CPUs visible)"}
         line["parity_vs_oracle"] = bool(parity)
+        if not key32:
+            # the same oracle steps on all the host threads this job may use
+            # (OpenMP count/duplicate, parallel-mode stable sort), checked
+            # against the plain oracle's result before it is timed
+            threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+            mt = oracle.sort_frame_mt(spec.width, spec.height, rec, threads)
+            same = (mt.status == res.status and np.array_equal(mt.keys, res.keys)
+                    and np.array_equal(mt.values, res.values) and np.array_equal(mt.ranges, res.ranges))
+            mframes, mspent = 0, 0.0
+            while mspent < args.cpu_seconds / 4 or mframes < 3:
+                t = time.perf_counter()
+                oracle.sort_frame_mt(spec.width, spec.height, rec, threads)
+                mspent += time.perf_counter() - t
+                mframes += 1
+            line["cpu_baseline_parallel"] = {
+                "value": mframes * M / mspent, "unit": "pairs/s", "cores": threads, "kind": "oracle-threaded",
+                "same_result_as_oracle": bool(same),
+                "sample": f"{mframes} whole {args.workload} frames ({mspent:.1f} s, oracle steps with OpenMP "
+                          f"count/duplicate and a parallel-mode stable sort on {threads} threads)"}
         if key32:
             # how lossy the normalised key is on this frame: pairs whose position
             # differs from the exact (tile, depth, index) order

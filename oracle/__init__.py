@@ -29,7 +29,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_CAPACITY, ERR_OVERFLOW, ERR_INVALID_INPUT = 0, 1, 
 
 def build(src: str = SRC_PATH, out: str = LIB_PATH, extra=()) -> str:
     """Compile the oracle into a shared library (g++, C++17)."""
-    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
            "-I", HERE, *extra, src, "-o", out + ".tmp"]
     subprocess.check_call(cmd)
     os.replace(out + ".tmp", out)
@@ -77,12 +77,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.oracle_sort.argtypes = [_P, _P, _U64]
     lib.oracle_ranges.argtypes = [_P, _U64, _U64, _P]
     lib.oracle_sort_frame.argtypes = [fp, _U64, _P, _P, _P, _P, _P, _P, _P, _P]
+    lib.oracle_sort_frame_mt.argtypes = [fp, _U64, _P, _P, _P, _P, ctypes.c_int]
     lib.oracle_render.argtypes = [fp, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
     lib.oracle_preprocess.argtypes = [ctypes.POINTER(_Camera), ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P]
     lib.oracle_sh_basis.argtypes = [_P, _P]
     lib.oracle_sh_basis.restype = None
     for f in (lib.oracle_tile_grid, lib.oracle_count, lib.oracle_scan, lib.oracle_duplicate,
-              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame, lib.oracle_render, lib.oracle_preprocess):
+              lib.oracle_sort, lib.oracle_ranges, lib.oracle_sort_frame, lib.oracle_sort_frame_mt, lib.oracle_render,
+              lib.oracle_preprocess):
         f.restype = ctypes.c_int
     return lib
 
@@ -211,6 +213,33 @@ def sort_frame(width: int, height: int, records: np.ndarray, tile_px: int = 16,
                        cnt if cnt is not None else empty, off if off is not None else empty,
                        uk[:mm] if uk is not None else empty, uv[:mm] if uv is not None else empty,
                        k[:mm], v[:mm], r)
+
+
+def sort_frame_mt(width: int, height: int, records: np.ndarray, threads: int,
+                  capacity: Optional[int] = None) -> FrameResult:
+    """``sort_frame`` (without the stage outputs) on ``threads`` host threads
+    (oracle_sort_frame_mt): the CPU timing baseline beside the GPU, the same
+    result."""
+    fr, rec = _frame(width, height, records, 16)
+    n = len(rec)
+    tx, ty = tile_grid(width, height, 16)
+    if capacity is None:
+        cnt = np.zeros(n, np.uint32)
+        st = lib().oracle_count(ctypes.byref(fr), _ptr(cnt), None)
+        if st != OK:
+            return FrameResult(st, tx, ty, 0, *(np.zeros(0),) * 7)
+        capacity = min(int(cnt.astype(np.uint64).sum()), 0xFFFFFFFF)
+    cap = int(capacity)
+    k = np.zeros(cap, np.uint64)
+    v = np.zeros(cap, np.uint32)
+    r = np.zeros((tx * ty, 2), np.uint32)
+    m_out = ctypes.c_uint64()
+    st = lib().oracle_sort_frame_mt(ctypes.byref(fr), cap, _ptr(k), _ptr(v), _ptr(r), ctypes.addressof(m_out),
+                                    int(threads))
+    m = int(m_out.value)
+    mm = min(m, cap)
+    empty = np.zeros(0)
+    return FrameResult(st, tx, ty, m, empty, empty, empty, empty, k[:mm], v[:mm], r)
 
 
 @dataclasses.dataclass

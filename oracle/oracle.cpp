@@ -3,6 +3,8 @@
 // loads or calls this file; the tests, the smoke check and the benchmark's
 // CPU baseline do.  It is written to be read against the paper, not to be
 // fast: one thread, plain loops, std::exclusive_scan and std::stable_sort.
+// (oracle_sort_frame_mt repeats the same steps on several threads, only to
+// time the CPU beside the GPU; it defines nothing.)
 //
 // Paper passages followed (arXiv 2511.16298):
 //  * Background, "Duplication with Tiles": the image is cut into 16x16 tiles,
@@ -33,10 +35,13 @@
 //    pairs of lower tiles, so the ranges partition [0, M).
 #include "oracle.h"
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <parallel/algorithm>
 #include <vector>
 
 namespace {
@@ -235,6 +240,63 @@ int oracle_sort_frame(const oracle_frame* f, uint64_t capacity,
   if (keys) std::copy(k.begin(), k.end(), keys);
   if (values) std::copy(v.begin(), v.end(), values);
 
+  if (ranges) oracle_ranges(k.data(), m, static_cast<uint64_t>(tiles_x) * tiles_y, ranges);
+  return ORACLE_OK;
+}
+
+// The same steps on several host threads, for timing the CPU beside the GPU
+// only (the tests check it against oracle_sort_frame before it is timed):
+// the count and duplicate loops split over the Gaussians with OpenMP (each
+// Gaussian writes its own segment [offsets[g], offsets[g] + count[g])), the
+// scan and the range scan stay sequential, and the sort is libstdc++'s
+// parallel-mode stable sort.  The result is the same pairs in the same order.
+int oracle_sort_frame_mt(const oracle_frame* f, uint64_t capacity, uint64_t* keys, uint32_t* values,
+                         uint32_t* ranges, uint64_t* num_pairs, int threads) {
+  uint32_t tiles_x, tiles_y;
+  int st = oracle_tile_grid(f, &tiles_x, &tiles_y);
+  if (st != ORACLE_OK || num_pairs == nullptr || threads < 1) return ORACLE_ERR_INVALID_ARGUMENT;
+  omp_set_num_threads(threads);
+  const int64_t n = f->num_gaussians;
+
+  std::vector<uint32_t> cnt(n);
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t g = 0; g < n; ++g) {
+    const oracle_gaussian& G = f->gaussians[g];
+    cnt[g] = static_cast<uint32_t>(rect_area(G, overlap_rect(G, tiles_x, tiles_y)));
+    if (cnt[g] > 0 && !depth_ok(G.depth)) bad = 1;
+  }
+  if (bad) return ORACLE_ERR_INVALID_INPUT;
+
+  std::vector<uint64_t> off(n);
+  uint64_t m = 0;
+  oracle_scan(cnt.data(), static_cast<uint32_t>(n), off.data(), &m);
+  *num_pairs = m;
+  if (m > 0xFFFFFFFFull) return ORACLE_ERR_OVERFLOW;
+  if (m > capacity) return ORACLE_ERR_CAPACITY;
+
+  std::vector<Pair> pairs(m);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t g = 0; g < n; ++g) {
+    if (cnt[g] == 0) continue;
+    const oracle_gaussian& G = f->gaussians[g];
+    const Rect r = overlap_rect(G, tiles_x, tiles_y);
+    uint64_t pos = off[g];
+    for (int64_t ty = r.y0; ty < r.y1; ++ty)
+      for (int64_t tx = r.x0; tx < r.x1; ++tx) {
+        const uint64_t t = static_cast<uint64_t>(tiles_x) * static_cast<uint64_t>(ty) + static_cast<uint64_t>(tx);
+        pairs[pos++] = Pair{(t << 32) | depth_bits(G.depth), static_cast<uint32_t>(g)};
+      }
+  }
+  __gnu_parallel::stable_sort(pairs.begin(), pairs.end(),
+                              [](const Pair& x, const Pair& y) { return x.key < y.key; });
+  std::vector<uint64_t> k(m);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < static_cast<int64_t>(m); ++i) {
+    k[i] = pairs[i].key;
+    if (keys) keys[i] = pairs[i].key;
+    if (values) values[i] = pairs[i].value;
+  }
   if (ranges) oracle_ranges(k.data(), m, static_cast<uint64_t>(tiles_x) * tiles_y, ranges);
   return ORACLE_OK;
 }

@@ -142,6 +142,13 @@ int oracle_preprocess(const oracle_camera* cam, uint32_t n, const float* mean3d_
                       const float* sh, oracle_gaussian* records, double* conic_opacity, double* rgb,
                       double* margin);
 
+/* oracle_sort_frame on `threads` host threads (OpenMP count and duplicate
+ * loops, parallel-mode stable sort), for timing the CPU beside the GPU only.
+ * Outputs keys, values (may be NULL) and ranges (may be NULL) as
+ * oracle_sort_frame does, with the same statuses. */
+int oracle_sort_frame_mt(const oracle_frame* f, uint64_t capacity, uint64_t* keys, uint32_t* values,
+                         uint32_t* ranges, uint64_t* num_pairs, int threads);
+
 /* The real spherical harmonics (Condon-Shortley phase) used above, degree
  * <= 3, at unit direction d: out[16] in (l, m = -l..l) order. */
 void oracle_sh_basis(const double d[3], double out[16]);

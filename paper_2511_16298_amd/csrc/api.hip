@@ -274,6 +274,10 @@ struct PassChain {
   // pass may drop the culled), and where it stores the count it keeps
   const uint32_t* culled;
   uint32_t* kept;
+  // 32-bit keys: a second value moved with the first (pass p reads psrc[p],
+  // writes pdst[p]), or NULL
+  const uint32_t* const* psrc;
+  uint32_t* const* pdst;
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -302,6 +306,10 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
           a.num_pairs = c.kept;
           a.n_total = c.n_fixed;
         }
+      }
+      if (c.psrc != nullptr) {
+        a.pin = c.psrc[p];
+        a.pout = c.pdst[p];
       }
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       // the last pass ranks only its significant digit bits where a narrower
@@ -464,11 +472,21 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   uint32_t* val = at<uint32_t>(ws, lay.val);
   uint32_t* key_alt = at<uint32_t>(ws, lay.key_alt);
   uint32_t* val_alt = at<uint32_t>(ws, lay.val_alt);
+  // Frames of at most 256 tiles per axis pack a rectangle into 32 bits, which
+  // the depth sort carries beside the indices: expand then reads the
+  // rectangles in sequence instead of gathering a cache line per Gaussian.
+  // The two packed buffers share the 64-bit rectangles' space.
+  bool pack = true;
+  for (uint32_t f = 0; f < lay.n_frames; ++f)
+    pack = pack && io.host_table[f].tiles_x <= 256 && io.host_table[f].tiles_y <= 256;
+  uint32_t* rect32 = pack ? at<uint32_t>(ws, lay.rect) : nullptr;
+  uint32_t* rect32_alt = pack ? rect32 + lay.n : nullptr;
   CountKeysArgs ck{};
   ck.table = table;
   ck.n_frames = lay.n_frames;
   ck.n = lay.n;
   ck.rect = at<uint64_t>(ws, lay.rect);
+  ck.rect32 = rect32;
   ck.key = key;
   ck.val = val;
   ck.tiles_touched = io.tiles_touched;
@@ -489,9 +507,12 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     const uint32_t* vs[4] = {val, val_alt, val, val_alt};
     void* kd[4] = {key_alt, key, key_alt, key};
     uint32_t* vd[4] = {val_alt, val, val_alt, val};
+    const uint32_t* ps[4] = {rect32, rect32_alt, rect32, rect32_alt};
+    uint32_t* pd[4] = {rect32_alt, rect32, rect32_alt, rect32};
     PassChain c{4, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
                 nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d), 0,
-                live ? ck.hist + 3 * 256 + 255 : nullptr, live};  // digit 255 of the top byte: culled only
+                live ? ck.hist + 3 * 256 + 255 : nullptr, live,  // digit 255 of the top byte: culled only
+                pack ? ps : nullptr, pack ? pd : nullptr};
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
 
@@ -511,6 +532,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.key = key;
   e.val = val;
   e.rect = ck.rect;
+  e.rect32 = rect32;  // after four passes the packed rectangles are back in the first buffer
   e.capacity = lay.capacity;
   e.keys = bk[0];
   e.values = bv[0];

@@ -94,8 +94,16 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
     }
     if (cnt != 0 && dbits - 1u >= 0x7F7FFFFFu) bad = true;
     const uint32_t key = cnt != 0 ? dbits : 0xFFFFFFFFu;
-    if (a.rect != nullptr) {  // NULL: counts only (batched sizing)
-      a.rect[g] = rect;
+    if (a.key != nullptr) {  // NULL: counts only (batched sizing)
+      if (a.rect32 != nullptr) {
+        // at most 256 tiles per axis: x0, y0 < 256 and 1 <= w, h <= 256
+        const uint32_t w = static_cast<uint32_t>(rect >> 32) & 0xFFFFu, h = static_cast<uint32_t>(rect >> 48);
+        a.rect32[g] = cnt == 0 ? 0u
+                               : (static_cast<uint32_t>(rect) & 0xFFu) | ((static_cast<uint32_t>(rect >> 16) & 0xFFu) << 8) |
+                                     ((w - 1u) << 16) | ((h - 1u) << 24);
+      } else {
+        a.rect[g] = rect;
+      }
       a.key[g] = key;
       a.val[g] = g;
       // culled keys (0xFFFFFFFF) all hit digit 255: counted per thread and
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
   if (!one_frame)
     for (uint32_t f = tid; f < a.n_frames; f += kCountKeysThreads)
       if (s_fm[f]) atomicAdd(&a.totals[1 + f], s_fm[f]);
-  if (a.rect == nullptr) return;
+  if (a.key == nullptr) return;
   if (tid == 0 && culled != 0)
     for (uint32_t p = 0; p < 4; ++p) s_hist[p * 256 + 255] += culled;
   __syncthreads();
@@ -255,17 +263,29 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     uint32_t cnt = 0;
     const uint32_t g = pos < n_sorted ? a.val[pos] : 0xFFFFFFFFu;
     if (g < a.n) {  // a sorted index is always < n; the test only keeps reads in bounds
-      const uint64_t r = a.rect[g];
       const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
-      const uint32_t w = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
-      const uint32_t h = static_cast<uint32_t>(r >> 48);
-      const uint32_t x0 = static_cast<uint32_t>(r) & 0xFFFFu;
-      const uint32_t y0 = static_cast<uint32_t>(r >> 16) & 0xFFFFu;
+      const uint32_t dep = a.key[pos];
+      uint32_t w, h, x0, y0;
+      if (a.rect32 != nullptr) {
+        // packed, in depth order: read in sequence instead of gathered by index
+        const uint32_t r = a.rect32[pos];
+        const bool live = dep != 0xFFFFFFFFu;
+        x0 = r & 0xFFu;
+        y0 = (r >> 8) & 0xFFu;
+        w = live ? ((r >> 16) & 0xFFu) + 1u : 0u;
+        h = ((r >> 24) & 0xFFu) + 1u;
+      } else {
+        const uint64_t r = a.rect[g];
+        w = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
+        h = static_cast<uint32_t>(r >> 48);
+        x0 = static_cast<uint32_t>(r) & 0xFFFFu;
+        y0 = static_cast<uint32_t>(r >> 16) & 0xFFFFu;
+      }
       const uint32_t tx = s_tab[f].tiles_x;
       cnt = w * h;
       s_org[i] = s_tab[f].tile_base + y0 * tx + x0;
       s_wt[i] = w | (tx << 16);
-      s_dep[i] = a.key[pos];
+      s_dep[i] = dep;
       s_loc[i] = g - s_tab[f].gauss_base;
     }
     s_off[i] = cnt;

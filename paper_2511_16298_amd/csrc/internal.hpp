@@ -64,6 +64,10 @@ struct PassArgs {
   const uint32_t* culled;
   uint32_t* kept;
   uint32_t n_total;
+  // 32-bit keys: an optional second 32-bit value per item (NULL: none), moved
+  // with the first; the depth sort carries the Gaussians' packed rectangles
+  const uint32_t* pin;
+  uint32_t* pout;
 };
 
 struct HistArgs {
@@ -100,6 +104,8 @@ struct CountKeysArgs {
   uint32_t n_frames;
   uint32_t n;               // Gaussians of all frames
   uint64_t* rect;           // out [n]: x0 | y0 << 16 | w << 32 | h << 48 (tiles)
+  uint32_t* rect32;         // or, when every frame has at most 256 tiles per axis (then
+                            // rect is not written): x0 | y0 << 8 | (w - 1) << 16 | (h - 1) << 24
   uint32_t* key;            // out [n]: depth bits, or 0xFFFFFFFF when culled
   uint32_t* val;            // out [n]: global Gaussian index
   uint32_t* tiles_touched;  // optional [n]
@@ -135,6 +141,8 @@ struct ExpandArgs {
   const uint32_t* key;      // sorted depth keys
   const uint32_t* val;      // sorted global indices
   const uint64_t* rect;     // by global index
+  const uint32_t* rect32;   // or packed rectangles in depth order (sorted with the keys; a
+                            // culled Gaussian's is ignored: its key is 0xFFFFFFFF)
   uint32_t capacity;
   uint64_t* keys;           // out pairs: global tile << 32 | depth bits
   uint32_t* values;         // out: frame-local Gaussian index

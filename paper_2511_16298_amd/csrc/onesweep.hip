@@ -171,6 +171,16 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       sm.buf[pos[j]] = k[j];
     }
   }
+  // 32-bit keys: the second value, loaded now (into the registers the keys
+  // leave free) so that its latency hides behind the look-back
+  uint32_t pl[ITEMS];
+  if constexpr (sizeof(K) == 4) {
+    if (a.pin != nullptr) {
+      const uint32_t seg = base + wave * (kWave * ITEMS) + lane_id();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) pl[j] = (FULL || dg[j] < BINS) ? a.pin[seg + j * kWave] : 0u;
+    }
+  }
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
   if (tid < BINS) {
@@ -229,6 +239,21 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t i = j * THREADS + tid;
     if (dst[j] != 0xFFFFFFFFu) a.vout[dst[j]] = s_val[i];
+  }
+  // ---- the second value, the same way ----
+  if constexpr (sizeof(K) == 4) {
+    if (a.pin != nullptr) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (FULL || dg[j] < BINS) s_val[pos[j]] = pl[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = j * THREADS + tid;
+        if (dst[j] != 0xFFFFFFFFu) a.pout[dst[j]] = s_val[i];
+      }
+    }
   }
 }
 

@@ -30,7 +30,9 @@ namespace {
 // consecutive addresses.
 template <typename K, int RB, int ITEMS, int THREADS>
 struct PassSmem {
-  K buf[THREADS * ITEMS];  // keys, then values (as uint32)
+  // keys, then values (as uint32; with 32-bit keys, values and second values
+  // as pairs of uint32)
+  K buf[THREADS * ITEMS * (sizeof(K) == 4 ? 2 : 1)];
   uint32_t wcnt[(THREADS / kWave) << RB];
   uint32_t dstart[1 << RB];
   uint32_t gofs[1 << RB];
@@ -229,7 +231,27 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   }
   __syncthreads();
 
-  // ---- values through the same buffer ----
+  // ---- values through the same buffer (with a second value: both as a
+  // pair, in one round) ----
+  if constexpr (sizeof(K) == 4) {
+    if (a.pin != nullptr) {
+      uint2* s_two = reinterpret_cast<uint2*>(sm.buf);
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (FULL || dg[j] < BINS) s_two[pos[j]] = make_uint2(v[j], pl[j]);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = j * THREADS + tid;
+        if (dst[j] != 0xFFFFFFFFu) {
+          const uint2 vp = s_two[i];
+          a.vout[dst[j]] = vp.x;
+          a.pout[dst[j]] = vp.y;
+        }
+      }
+      return;
+    }
+  }
   uint32_t* s_val = reinterpret_cast<uint32_t*>(sm.buf);
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
@@ -239,21 +261,6 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t i = j * THREADS + tid;
     if (dst[j] != 0xFFFFFFFFu) a.vout[dst[j]] = s_val[i];
-  }
-  // ---- the second value, the same way ----
-  if constexpr (sizeof(K) == 4) {
-    if (a.pin != nullptr) {
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j)
-        if (FULL || dg[j] < BINS) s_val[pos[j]] = pl[j];
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t i = j * THREADS + tid;
-        if (dst[j] != 0xFFFFFFFFu) a.pout[dst[j]] = s_val[i];
-      }
-    }
   }
 }
 
@@ -398,7 +405,7 @@ hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int ite
   SS_PASS_CASE(uint64_t, 6, 16, 512) SS_PASS_CASE(uint64_t, 6, 8, 512)
   SS_PASS_CASE(uint64_t, 5, 16, 512) SS_PASS_CASE(uint64_t, 5, 8, 512)
   SS_PASS_CASE(uint64_t, 4, 16, 512) SS_PASS_CASE(uint64_t, 4, 8, 512)
-  SS_PASS_CASE(uint32_t, 8, 16, 256) SS_PASS_CASE(uint32_t, 8, 12, 256) SS_PASS_CASE(uint32_t, 8, 8, 256)
+  // the Gaussian depth sort's shapes
   SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512)
 #undef SS_PASS_CASE
   return hipErrorInvalidValue;

@@ -806,16 +806,16 @@ def main():
     pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair
     achieved = pass_bytes / (pass_us * 1e-6) / 1e9
     # whole-step algorithmic bytes of the depth-first path that runs.  Frames
-    # of at most 256 tiles per axis (every workload here): count 16N read +
+    # of at most 256 tiles per axis and at most 2^23 Gaussians: count 16N read +
     # 12N write (packed rectangle, depth key, index), four depth passes 24N
     # each (the rectangle rides with the index), expand 12N read + 12M write,
     # Pt tile passes 24M each, ranges 8M + 8T -- 136 N + (20 + 24 Pt) M + 8 T.
-    # Larger frames: 16N count write, 16N per depth pass, expand 8N read + 8N
+    # Otherwise: 16N count write, 16N per depth pass, expand 8N read + 8N
     # rectangle gather -- 112 N + ....  The direct path would move
     # 48 N + (28 + 24 P) M + 8 T.
     N = len(rec)
     tile_passes = -(-(key_bits - 32) // rb)
-    per_gaussian = 136.0 if tx <= 256 and ty <= 256 else 112.0
+    per_gaussian = 136.0 if tx <= 256 and ty <= 256 and N <= (1 << 23) else 112.0
     step_bytes = per_gaussian * N + (20.0 + 24.0 * tile_passes) * M + 8.0 * tx * ty
     direct_bytes = 48.0 * N + (28.0 + 24.0 * passes) * M + 8.0 * tx * ty
 

@@ -475,8 +475,11 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   // Frames of at most 256 tiles per axis pack a rectangle into 32 bits, which
   // the depth sort carries beside the indices: expand then reads the
   // rectangles in sequence instead of gathering a cache line per Gaussian.
-  // The two packed buffers share the 64-bit rectangles' space.
-  bool pack = true;
+  // The two packed buffers share the 64-bit rectangles' space.  Up to 2^23
+  // Gaussians the depth passes absorb the extra 8 B per Gaussian almost for
+  // free (they wait on the look-back more than on memory); beyond that they
+  // are bandwidth-bound and the extra bytes cost what the gather did.
+  bool pack = lay.n <= (1u << 23);
   for (uint32_t f = 0; f < lay.n_frames; ++f)
     pack = pack && io.host_table[f].tiles_x <= 256 && io.host_table[f].tiles_y <= 256;
   uint32_t* rect32 = pack ? at<uint32_t>(ws, lay.rect) : nullptr;

@@ -147,7 +147,7 @@ PassCfg depth_cfg(uint32_t n) {
 }
 
 struct DfLayout {
-  uint32_t n = 0, n_frames = 0, capacity = 0, total_tiles = 0, tile_bits = 0, tpasses = 0, tbins = 256;
+  uint32_t n = 0, n_frames = 0, capacity = 0, total_tiles = 0, tile_bits = 0, tpasses = 0, tbins = 256, trb = 8;
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
@@ -164,7 +164,13 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.total_tiles = static_cast<uint32_t>(total_tiles);
   L.tile_bits = ceil_log2(total_tiles);
   L.tpasses = (L.tile_bits + o.radix_bits - 1) / o.radix_bits;
-  L.tbins = 1u << o.radix_bits;
+  // With 8-bit digits in 512-thread passes, several tile passes split the tile
+  // bits evenly (13 bits: 7 + 6 instead of 8 + 5): the widest pass has fewer
+  // digits, so its runs of one digit, and its writes, are longer.
+  L.trb = o.radix_bits;
+  if (L.tpasses >= 2 && o.radix_bits == 8 && o.threads == 512 && (o.items == 8 || o.items == 16))
+    L.trb = (L.tile_bits + L.tpasses - 1) / L.tpasses;
+  L.tbins = 1u << L.trb;
   L.dcfg = depth_cfg(n);
   L.tcfg = PassCfg{o.items, o.threads};
   L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
@@ -540,7 +546,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.keys = bk[0];
   e.values = bv[0];
   e.npasses = P;
-  e.radix_bits = o.radix_bits;
+  e.radix_bits = lay.trb;
   e.hist = at<uint32_t>(ws, lay.hist_t);
   e.lookback = at<uint64_t>(ws, lay.expand_lb);
   e.status = d_status;
@@ -560,9 +566,9 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       kd[p] = bk[(p + 1) % 2];
       vd[p] = bv[(p + 1) % 2];
     }
-    PassChain c{P, 8, 32, o.radix_bits, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
+    PassChain c{P, 8, 32, lay.trb, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
                 d_status, bases_t, e.hist, P * lay.tbins, at<uint32_t>(ws, lay.lb_t),
-                lay.tile_bits - o.radix_bits * (P - 1)};
+                lay.tile_bits - lay.trb * (P - 1)};
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
   }
   return L.run(SS_KERNEL_RANGES, [&] {

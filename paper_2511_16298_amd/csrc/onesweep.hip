@@ -385,10 +385,10 @@ bool pass_config_supported(int radix_bits, int items, int threads) {
 }
 
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads) {
-  // compiled narrow widths: 64-bit keys, 8-bit passes of 512 threads
-  if (key_bytes != 8 || radix_bits != 8 || threads != 512 || (items != 8 && items != 16)) return 0;
+  // compiled narrow widths: 64-bit keys, 4..7-bit passes of 512 threads
+  if (key_bytes != 8 || radix_bits < 5 || radix_bits > 8 || threads != 512 || (items != 8 && items != 16)) return 0;
   if (bits <= 4) return 4;
-  return bits < 8 ? bits : 0;
+  return bits < radix_bits ? bits : 0;
 }
 
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,

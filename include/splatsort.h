@@ -106,9 +106,11 @@ typedef struct ss_options {
 /* SS_ALGO_DIRECT: duplicate in index order, then ceil((ceil(log2 T) + 32) /
  * radix_bits) passes over all M pairs.  SS_ALGO_DEPTH_FIRST: sort the N
  * Gaussians by depth first (four 8-bit passes over N), duplicate in depth
- * order, then sort the pairs by tile id alone (ceil(log2 T) bits, 8-bit
- * digits); a Gaussian adds at most one pair per tile, so the stable tile
- * sort leaves each tile in (depth, index) order.  radix_bits, items and
+ * order, then sort the pairs by tile id alone (ceil(log2 T) bits in
+ * P = ceil(ceil(log2 T) / radix_bits) passes; with 8-bit digits in
+ * 512-thread passes the bits are split evenly, ceil(ceil(log2 T) / P) per
+ * pass); a Gaussian adds at most one pair per tile, so the stable tile sort
+ * leaves each tile in (depth, index) order.  radix_bits, items and
  * workgroup_size apply to the passes over the pairs.  AUTO = DEPTH_FIRST,
  * except that SS_FLAG_UNSORTED implies DIRECT. */
 #define SS_ALGO_AUTO 0u

@@ -32,6 +32,7 @@ struct Options {
   uint32_t flags = 0;
   uint32_t algorithm = SS_ALGO_AUTO;
   ss_timer* timer = nullptr;
+  bool items_default = true;  // items_per_thread left at 0 (the frame size may choose)
 };
 
 ss_status parse_options(const ss_options* o, Options* out) {
@@ -47,7 +48,10 @@ ss_status parse_options(const ss_options* o, Options* out) {
   out->flags = o->flags;
   out->algorithm = o->algorithm;
   if (o->radix_bits != 0) out->radix_bits = o->radix_bits;
-  if (o->items_per_thread != 0) out->items = o->items_per_thread;
+  if (o->items_per_thread != 0) {
+    out->items = o->items_per_thread;
+    out->items_default = false;
+  }
   // default workgroup: 512 where that configuration exists, else 256
   out->threads = pass_config_supported(static_cast<int>(out->radix_bits), static_cast<int>(out->items), 512)
                      ? 512u : 256u;
@@ -173,6 +177,10 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.tbins = 1u << L.trb;
   L.dcfg = depth_cfg(n);
   L.tcfg = PassCfg{o.items, o.threads};
+  // default shape, fewer than 2^23 pairs: 4,096-pair tiles (twice the
+  // workgroups, so more of them load while others rank; measured faster up
+  // to the full-HD frame, slower from the 27.6M-pair frame on)
+  if (o.items_default && o.threads == 512 && o.items == 16 && capacity < (1u << 23)) L.tcfg.items = 8;
   L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
   L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile();
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals

@@ -37,6 +37,7 @@ import synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
 PASS_SOURCE = os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "onesweep.hip")
+API_SOURCE = os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "api.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 PASS_KERNEL = "k_onesweep"
 
@@ -74,8 +75,17 @@ def parse():
     return p.parse_args()
 
 
-def source_hash(path: str = PASS_SOURCE) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_hash(paths=None) -> str:
+    """sha256[:16] of the sources that decide a profiled kernel: the sort pass
+    kernel together with the host code that picks its launch shapes."""
+    if paths is None:
+        paths = (PASS_SOURCE, API_SOURCE)
+    if isinstance(paths, str):
+        paths = (paths,)
+    h = hashlib.sha256()
+    for path in paths:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def dominant_kernel(workload: str):
@@ -86,7 +96,7 @@ def dominant_kernel(workload: str):
         return "k_preprocess", "", os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "preprocess.hip")
     if workload == "render":
         return "k_render", "", os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "render.hip")
-    return PASS_KERNEL, "unsigned long", PASS_SOURCE
+    return PASS_KERNEL, "unsigned long", (PASS_SOURCE, API_SOURCE)
 
 
 def _rows(pattern: str):
@@ -104,7 +114,7 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     lines = [f"# rocprofv3 kernel statistics, workload {workload}",
              "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
              f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline",
-             f"{dominant_kernel(workload)[0]} source sha256[:16]: {source_hash(dominant_kernel(workload)[2])}", "",
+             f"{dominant_kernel(workload)[0]} sources (kernel, launch shapes) sha256[:16]: {source_hash(dominant_kernel(workload)[2])}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
         name = r["Name"]

@@ -93,7 +93,9 @@ typedef struct ss_timer ss_timer;
 typedef struct ss_options {
   uint32_t struct_size;
   uint32_t radix_bits;     /* 0 = default (8); supported: 4, 6, 8 */
-  uint32_t items_per_thread; /* 0 = default (16); supported: 8, 12, 16 */
+  uint32_t items_per_thread; /* 0 = default (16; 8 for the depth-first tile
+                                passes of a pair capacity below 2^23);
+                                supported: 8, 12, 16 */
   uint32_t flags;          /* SS_FLAG_* (0 = none) */
   ss_timer* timer;         /* optional: record HIP events around every kernel */
   uint32_t workgroup_size; /* sort-pass threads: 0 = default (512 where

@@ -885,6 +885,25 @@ def main():
                                           f"{os.cpu_count()} host CPUs visible)"}
         line["parity_vs_oracle"] = bool(parity)
         if not key32:
+            # the oracle's steps one at a time on one thread (median of three
+            # runs of the frame), and the stage outputs checked against the
+            # whole-frame call
+            st_ms = {"count": [], "scan": [], "duplicate": [], "sort": [], "ranges": []}
+            for _ in range(3):
+                t = time.perf_counter(); cnt, _r = oracle.count(spec.width, spec.height, rec)
+                st_ms["count"].append(time.perf_counter() - t)
+                t = time.perf_counter(); off, tot = oracle.scan(cnt)
+                st_ms["scan"].append(time.perf_counter() - t)
+                t = time.perf_counter(); uk, uv = oracle.duplicate(spec.width, spec.height, rec, off, tot)
+                st_ms["duplicate"].append(time.perf_counter() - t)
+                t = time.perf_counter(); sk, sv = oracle.sort_pairs(uk, uv)
+                st_ms["sort"].append(time.perf_counter() - t)
+                t = time.perf_counter(); rg = oracle.ranges(sk, tx * ty)
+                st_ms["ranges"].append(time.perf_counter() - t)
+            stages_same = (tot == M and np.array_equal(sk, res.keys) and np.array_equal(sv, res.values)
+                           and np.array_equal(rg, res.ranges))
+            line["cpu_baseline_stages_ms"] = {k: round(1e3 * float(np.median(v)), 2) for k, v in st_ms.items()}
+            line["cpu_baseline_stages_ms"]["same_result_as_oracle"] = bool(stages_same)
             # the same oracle steps on all the host threads this job may use
             # (OpenMP count/duplicate, parallel-mode stable sort), checked
             # against the plain oracle's result before it is timed

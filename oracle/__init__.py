@@ -159,6 +159,19 @@ def scan(counts: np.ndarray):
     return off, tot.value
 
 
+def duplicate(width: int, height: int, records: np.ndarray, offsets: np.ndarray, num_pairs: int,
+              tile_px: int = 16):
+    """Step a3 alone: the unsorted (keys, values) from the a2 offsets."""
+    fr, rec = _frame(width, height, records, tile_px)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    k = np.zeros(num_pairs, np.uint64)
+    v = np.zeros(num_pairs, np.uint32)
+    st = lib().oracle_duplicate(ctypes.byref(fr), _ptr(off), num_pairs, _ptr(k), _ptr(v))
+    if st != OK:
+        raise ValueError(f"oracle_duplicate status {st}")
+    return k, v
+
+
 def sort_pairs(keys: np.ndarray, values: np.ndarray):
     """Step a4 alone on copies: stable sort by the 64-bit key."""
     k = np.array(keys, dtype=np.uint64, copy=True)

@@ -2,20 +2,22 @@
 
 One step = the whole hot path (count, scan, duplicate, radix sort, ranges)
 over one synthetic frame whose records are already resident in HBM.  The
-default workload is the full-HD frame (1920x1080, 8,160 tiles, N = 1,000,000
-Gaussians, about 4.8M pairs).  Prints one JSON line.
+default workload is the large heavy-tailed frame (1920x1080, 8,160 tiles,
+N = 6,000,000 Gaussians, about 27.6M pairs); the same run adds the full-HD
+and 256x256 frames (p50/p99 latency) and the 64-frame batch against 64 plain
+launches as extra keys.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-extras]
 
 Profiles (run under rocprofv3, then summarised into profiles/ with
 ``--summarize-profiles DIR``; the exact commands are written into each summary):
 
     rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- \
-        python3 bench.py --steps 20 --warmup 5 --no-cpu-baseline
+        python3 bench.py --workload large-6m --steps 20 --warmup 5 --no-cpu-baseline --no-extras
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- \
-        python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-mib 512
+        python3 bench.py --workload large-6m --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-mib 512
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- \
-        python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-mib 512
+        python3 bench.py --workload large-6m --steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-mib 512
 """
 from __future__ import annotations
 
@@ -36,6 +38,7 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
+DEFAULT_WORKLOAD = "large-6m"
 PASS_SOURCE = os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "onesweep.hip")
 API_SOURCE = os.path.join(ROOT, "paper_2511_16298_amd", "csrc", "api.hip")
 PROFILES = os.path.join(ROOT, "profiles")
@@ -47,12 +50,16 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="fullhd-1m",
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD,
                    choices=sorted(synth.FRAME_WORKLOADS) + sorted(synth.SUPPLEMENTARY_WORKLOADS)
                    + ["batch-64", "serve", "sweep", "render", "preprocess", "shard-large-6m"])
     p.add_argument("--bands", type=int, default=8, help="tile-row bands = GPUs of the sharded frame (shard-*)")
     p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
-    p.add_argument("--serve-rates", default="200,1000,3000", help="requests per second (serve)")
+    p.add_argument("--serve-rates", default="200,1000,3000,6000,12000", help="requests per second (serve)")
+    p.add_argument("--serve-closed-seconds", type=float, default=10.0,
+                   help="closed-loop run per mode (serve; 0: skip)")
+    p.add_argument("--serve-outstanding", type=int, default=48,
+                   help="requests kept in flight by the closed loop (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")
     p.add_argument("--small-arena-gib", type=float, default=0.5,
                    help="second budget, run at the highest rate to force admission stalls (serve; 0: skip)")
@@ -66,6 +73,8 @@ def parse():
                    help="frame sort algorithm (frames, sweep); bitonic-key32 = the paper's normalised "
                         "32-bit float key (lossy within a tile, frames only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default workload only: skip the full-HD and 256x256 frames and the batch comparison")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle baseline (whole frames until exceeded)")
     p.add_argument("--copy-mib", type=int, default=0,
@@ -113,7 +122,7 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
     stats = _rows(os.path.join(d, "stats", "*kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics, workload {workload}",
              "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
-             f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline",
+             f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline --no-extras",
              f"{dominant_kernel(workload)[0]} sources (kernel, launch shapes) sha256[:16]: {source_hash(dominant_kernel(workload)[2])}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -173,15 +182,15 @@ def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
                   "fetch_bytes_per_launch": round(sum(fby[k]) / len(fby[k]) * f_scale * 1024.0),
                   "write_bytes_per_launch": round(sum(wby[k]) / len(wby[k]) * w_scale * 1024.0)}
               for k in sorted(fby) if k in wby and not k.startswith("at::") and "rocclr" not in k}
-    wl = "" if workload == "fullhd-1m" else f"--workload {workload} "
+    wl = f"--workload {workload} "
     rec = {"kernel": " + ".join(tile), "workload": workload, "source_sha256_16": source_hash(ksrc),
            "copy_calibration_mib": copy_mib, "fetch_scale": f_scale, "write_scale": w_scale,
            "dispatches": len(fp), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "traffic_bytes_per_launch": fetch + write, "per_kernel": others, "step_measured": step,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py "
-                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}",
+                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-mib {copy_mib}",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py "
-                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --copy-mib {copy_mib}"]}
+                        f"{wl}--steps 3 --warmup 1 --no-cpu-baseline --no-extras --copy-mib {copy_mib}"]}
     with open(os.path.join(PROFILES, f"{kname}_{workload}_traffic.txt"), "w") as f:
         f.write(f"# HBM traffic of one {kname} launch (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale;\n"
                 "# the scales make a plain copy of copy_calibration_mib MiB read and write exactly that),\n"
@@ -244,84 +253,15 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def bench_batch(args):
-    """64 uneven frames: one segmented sort (eager, and captured in an
-    autotuned graph) against 64 plain per-frame launches, same outputs."""
-    import torch
-    import paper_2511_16298_amd as ss
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    frames = synth.make_batch(64)
-    recs = [ss.records_to_device(r, dev) for (_, _, r) in frames]
-    ms = []
-    for (w, h, _), d in zip(frames, recs):
-        _, _, m, st = ss.count_pairs(d, w, h)
-        assert int(st.item()) == 0
-        ms.append(int(m.item()))
-    total = sum(ms)
-    shapes = [(w, h, len(r)) for (w, h, r) in frames]
-    stream = torch.cuda.current_stream()
-    K, W = args.steps, args.warmup
-    print(f"# batch-64: N={sum(s[2] for s in shapes)}, M={total}", file=sys.stderr, flush=True)
-
-    def timed(fn):
-        for _ in range(W):
-            fn()
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-        ev[0].record(stream)
-        for i in range(K):
-            fn()
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
-        return ev[0].elapsed_time(ev[K]) / K, per
-
-    eager = ss.BatchSorter(shapes, total, device=dev)
-    t_eager, _ = timed(lambda: eager(recs, stream))
-    assert eager.result() == (0, total)
-    gsorter = ss.BatchSorter(shapes, total, device=dev, plan_workspace=True)
-    plan = ss.Plan(gsorter, recs, autotune=True, stream=stream)
-    t_graph, per_graph = timed(lambda: plan.launch(stream))
-    assert gsorter.result() == (0, total)
-    plain = [ss.FrameSorter(w, h, n, m, device=dev) for (w, h, n), m in zip(shapes, ms)]
-
-    def run_plain():
-        for so, d in zip(plain, recs):
-            so(d, stream)
-    t_plain, _ = timed(run_plain)
-    # identical outputs: every frame's plain result equals its batch segment
-    base = gsorter.frame_pair_base.cpu().numpy().astype(np.int64)
-    gk = gsorter.keys.cpu().numpy().view(np.uint64)
-    gv = gsorter.values.cpu().numpy().view(np.uint32)
-    same = True
-    for f, so in enumerate(plain):
-        k = so.out.keys.cpu().numpy().view(np.uint64)[:ms[f]]
-        v = so.out.values.cpu().numpy().view(np.uint32)[:ms[f]]
-        tb = np.uint64(int(gsorter.tile_base[f])) << np.uint64(32)
-        seg = slice(int(base[f]), int(base[f]) + ms[f])
-        same &= bool(np.array_equal(gk[seg] - tb, k) and np.array_equal(gv[seg], v))
-    cfg = plan.config()
-    line = {"metric": "sorted key-value pairs/s, 64-frame segmented batch vs 64 plain launches",
-            "value": total / (t_graph * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
-            "ms_per_step": t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "u64", "data": "synthetic",
-            "config": {"workload": "batch-64: 64 frames, resolution uniform over 640x360/1280x720/1920x1080, "
-                                   "N log-uniform in [5e4, 2e6], seed 1003", "num_pairs": total,
-                       "parallelism": "single GPU"},
-            "batch_graph_pairs_per_s": total / (t_graph * 1e-3),
-            "batch_eager_pairs_per_s": total / (t_eager * 1e-3),
-            "plain_64_launches_pairs_per_s": total / (t_plain * 1e-3),
-            "speedup_vs_plain": t_plain / t_graph,
-            "latency_ms": {"p50": pct(per_graph, 50), "p99": pct(per_graph, 99)},
-            "autotuned": {k: v for k, v in cfg.items()}, "outputs_identical": same}
-    print(json.dumps(line), flush=True)
-
-
 def bench_serve(args):
     """Poisson request streams over a pool of device-resident frames drawn as
-    in the batch workload: continuous batching against one request at a time."""
+    in the batch workload: continuous batching against one request at a time,
+    at offered rates below and above what one request at a time sustains,
+    plus a closed loop that keeps a fixed number of requests outstanding (the
+    most each mode can serve).  A sample of served results is kept and
+    compared, after each run, with the plain single-frame path's output for
+    the same frame."""
+    import collections
     import threading
     import torch
     import paper_2511_16298_amd as ss
@@ -342,6 +282,61 @@ def bench_serve(args):
         pool[i] = (pool[i][0], pool[i][1], None)   # keep the shape only
     rates = [float(x) for x in args.serve_rates.split(",")]
     arena = int(args.arena_gib * (1 << 30))
+    copy_stream = torch.cuda.Stream(device=dev)
+
+    class Sampler:
+        """Keeps device copies of every `every`-th served result (at most
+        `cap`), to be compared with the plain path afterwards."""
+
+        def __init__(self, srv, every=53, cap=16):
+            self.srv, self.every, self.cap, self.kept, self.n = srv, every, cap, [], 0
+
+        def take(self, r, k):
+            self.n += 1
+            if r.status != 0 or self.n % self.every or len(self.kept) >= self.cap:
+                return
+            base = self.srv.arena.data_ptr()
+            m = int(r.num_pairs)
+            w, h, _ = pool[k]
+            tx, ty, _ = ss.geometry(w, h)
+            with torch.cuda.stream(copy_stream):
+                def grab(ptr, nbytes):
+                    off = int(ptr) - base
+                    return self.srv.arena[off:off + nbytes].clone()
+                kk = grab(r.keys, 8 * m).view(torch.int64) - (int(r.tile_base) << 32)
+                vv = grab(r.values, 4 * m).view(torch.int32)
+                rg = grab(r.tile_ranges, 8 * tx * ty).view(torch.int32) - int(r.pair_base)
+            copy_stream.synchronize()
+            self.kept.append((k, kk, vv, rg))
+
+        def verify(self):
+            """(compared, all equal): each kept result against ss_sort_frame."""
+            ok = True
+            for k, kk, vv, rg in self.kept:
+                w, h, _ = pool[k]
+                out = ss.sort_frame(recs[k], w, h)
+                st, m = out.result()
+                ok &= bool(st == 0 and m == kk.numel() and torch.equal(out.keys[:m], kk)
+                           and torch.equal(out.values[:m], vv) and torch.equal(out.tile_ranges.view(-1), rg))
+            n = len(self.kept)
+            self.kept = []
+            return n, bool(ok)
+
+    def summarize(got, span_s, offered_window_s=None):
+        g = np.array([x[:5] for x in got], dtype=np.float64)
+        ok = g[:, 0] == 0
+        lat = (g[:, 4] - g[:, 2]) / 1e3   # ms
+        keep = ok & ((g[:, 2] - g[:, 2].min()) > 1e6)   # skip the first second of arrivals
+        if not keep.any():
+            keep = ok
+        res = {"requests": len(got), "ok": int(ok.sum()), "rejected_budget": int((g[:, 0] == 8).sum()),
+               "pairs": int(g[ok, 1].sum()), "pairs_per_s": float(g[ok, 1].sum() / span_s),
+               "requests_per_s": float(ok.sum() / span_s),
+               "p50_ms": pct(lat[keep], 50), "p99_ms": pct(lat[keep], 99),
+               "mean_round_frames": float(np.mean([x[5] for x in got]))}
+        if offered_window_s:
+            res["offered_pairs_per_s"] = float(g[ok, 1].sum() / offered_window_s)
+        return res
 
     def run_trace(srv, rate):
         seed = synth.SEED_BASE + 4 + int(rate)
@@ -351,6 +346,7 @@ def bench_serve(args):
         lock = threading.Condition()
         got = []
         done_submitting = [False]
+        sampler = Sampler(srv)
 
         def collect():
             i = 0
@@ -360,9 +356,10 @@ def bench_serve(args):
                         lock.wait(0.01)
                     if i >= len(tickets):
                         return
-                    t = tickets[i]
+                    t, k = tickets[i]
                 r = srv.wait(t)
                 got.append((r.status, r.num_pairs, r.submit_us, r.start_us, r.done_us, r.round_frames))
+                sampler.take(r, k)
                 srv.release(t)
                 i += 1
         th = threading.Thread(target=collect)
@@ -375,22 +372,48 @@ def bench_serve(args):
             w, h, _ = pool[int(k)]
             t = srv.submit(recs[int(k)], w, h)
             with lock:
-                tickets.append(t)
+                tickets.append((t, int(k)))
                 lock.notify()
         with lock:
             done_submitting[0] = True
             lock.notify()
         th.join()
         g = np.array([x[:5] for x in got], dtype=np.float64)
-        ok = g[:, 0] == 0
-        lat = (g[:, 4] - g[:, 2]) / 1e3   # ms
-        keep = ok & ((g[:, 2] - g[:, 2].min()) > 1e6)   # skip the first second of arrivals
         span = (g[:, 4].max() - g[:, 2].min()) / 1e6
-        return {"requests": len(got), "ok": int(ok.sum()), "rejected_budget": int((g[:, 0] == 8).sum()),
-                "pairs": int(g[ok, 1].sum()), "pairs_per_s": float(g[ok, 1].sum() / span),
-                "p50_ms": pct(lat[keep], 50), "p99_ms": pct(lat[keep], 99),
-                "mean_round_frames": float(np.mean([x[5] for x in got])),
-                "offered_pairs_per_s": float(g[ok, 1].sum() / args.serve_seconds)}
+        res = summarize(got, span, args.serve_seconds)
+        res["offered_requests_per_s"] = rate
+        res["verified_results"], res["verified_equal_plain"] = sampler.verify()
+        return res
+
+    def run_closed(srv, outstanding, seconds):
+        """Closed loop: `outstanding` requests in flight at all times."""
+        seed = synth.SEED_BASE + 4 + 99
+        picks = synth.uniform_int(synth.stream_key(seed, 7), 1 << 20, len(pool))
+        sampler = Sampler(srv)
+        q = collections.deque()
+        got = []
+        j = 0
+        t_end = time.perf_counter() + seconds
+        for _ in range(outstanding):
+            k = int(picks[j]); j += 1
+            w, h, _ = pool[k]
+            q.append((srv.submit(recs[k], w, h), k))
+        while q:
+            t, k = q.popleft()
+            r = srv.wait(t)
+            got.append((r.status, r.num_pairs, r.submit_us, r.start_us, r.done_us, r.round_frames))
+            sampler.take(r, k)
+            srv.release(t)
+            if time.perf_counter() < t_end:
+                k2 = int(picks[j % len(picks)]); j += 1
+                w, h, _ = pool[k2]
+                q.append((srv.submit(recs[k2], w, h), k2))
+        g = np.array([x[:5] for x in got], dtype=np.float64)
+        span = (g[:, 4].max() - g[:, 2].min()) / 1e6
+        res = summarize(got, span)
+        res["outstanding"] = outstanding
+        res["verified_results"], res["verified_equal_plain"] = sampler.verify()
+        return res
 
     runs = [("batched", 64, 2, arena, rates), ("one_at_a_time", 1, 1, arena, rates)]
     if args.small_arena_gib > 0:
@@ -402,17 +425,30 @@ def bench_serve(args):
             key = f"{mode}@{int(rate)}"
             results[key] = run_trace(srv, rate)
             print(f"# {key}: {results[key]}", file=sys.stderr, flush=True)
+        if args.serve_closed_seconds > 0 and mode != "batched_small_arena":
+            key = f"{mode}@closed"
+            results[key] = run_closed(srv, args.serve_outstanding, args.serve_closed_seconds)
+            print(f"# {key}: {results[key]}", file=sys.stderr, flush=True)
         srv.close()
+        del srv
+        torch.cuda.empty_cache()
+    top = f"batched@{int(rates[-1])}"
     line = {"metric": "served frame-sort requests: pairs/s and p50/p99 request latency",
-            "value": results[f"batched@{int(rates[-1])}"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+            "value": results[top]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
             "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": f"serve: Poisson arrivals {args.serve_rates}/s for {args.serve_seconds:g} s "
                                    f"each, frames drawn from a pool of {len(pool)} device-resident frames of "
                                    f"the batch distribution, HBM budget {args.arena_gib:g} GiB (and "
-                                   f"{args.small_arena_gib:g} GiB at the highest rate)",
+                                   f"{args.small_arena_gib:g} GiB at the highest rate); closed loop with "
+                                   f"{args.serve_outstanding} requests outstanding for "
+                                   f"{args.serve_closed_seconds:g} s",
                        "parallelism": "single GPU"},
             "runs": results}
+    if "batched@closed" in results and "one_at_a_time@closed" in results:
+        line["closed_loop_speedup_pairs_per_s"] = (results["batched@closed"]["pairs_per_s"]
+                                                   / results["one_at_a_time@closed"]["pairs_per_s"])
+    line["all_verified_equal_plain"] = all(r.get("verified_equal_plain", True) for r in results.values())
     print(json.dumps(line), flush=True)
 
 
@@ -727,31 +763,34 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.workload)
-        return
-    if args.workload in ("batch-64", "serve", "sweep", "render", "preprocess", "shard-large-6m"):
-        if args.gpus != 1:
-            print("bench.py measures one GPU only", file=sys.stderr)
-            sys.exit(2)
-        {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
-         "render": bench_render, "preprocess": bench_preprocess, "shard-large-6m": bench_shard}[args.workload](args)
-        return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the sort of one frame runs on one device and "
-              "frames shard across GPUs without communication; run it with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def step_bytes_model(n: int, m: int, tiles_x: int, tiles_y: int, key_bits: int, rb: int = 8) -> tuple:
+    """(depth-first step bytes, direct-path bytes) of one frame.
 
+    Depth-first, frames of at most 256 tiles per axis and at most 2^23
+    Gaussians: count 16N read + 12N write (packed rectangle, depth key,
+    index), four depth passes 24N each (the rectangle rides with the index),
+    expand 12N read + 12M write, Pt tile passes 24M each, ranges 8M + 8T --
+    136 N + (20 + 24 Pt) M + 8 T.  Otherwise: 16N count write, 16N per depth
+    pass, expand 8N read + 8N rectangle gather -- 112 N + ....  The direct
+    path would move 48 N + (28 + 24 P) M + 8 T."""
+    tile_passes = -(-(key_bits - 32) // rb)
+    passes = -(-key_bits // rb)
+    per_gaussian = 136.0 if tiles_x <= 256 and tiles_y <= 256 and n <= (1 << 23) else 112.0
+    step = per_gaussian * n + (20.0 + 24.0 * tile_passes) * m + 8.0 * tiles_x * tiles_y
+    direct = 48.0 * n + (28.0 + 24.0 * passes) * m + 8.0 * tiles_x * tiles_y
+    return step, direct, tile_passes
+
+
+def time_frame(args, workload: str, steps: int, warmup: int, dev, stream, kernel_timer: bool = True):
+    """K whole steps of one frame workload (records resident in HBM): per-step
+    HIP-event times on the launching stream, host wall time, and (optionally)
+    per-kernel durations from a second run with events around each launch."""
     import torch
     import paper_2511_16298_amd as ss
     from paper_2511_16298_amd import _abi
 
-    spec, seed = synth.workload(args.workload)
+    spec, seed = synth.workload(workload)
     rec = synth.make_frame(spec, seed)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     d = ss.records_to_device(rec, dev)
     _, _, m_t, s_t = ss.count_pairs(d, spec.width, spec.height)
     assert int(s_t.item()) == 0
@@ -761,75 +800,181 @@ def main():
     key32 = args.algorithm == "bitonic-key32"
     sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev,
                             workgroup_size=args.wg, algorithm=algo, key32=key32)
-    tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
-    rb = args.radix_bits or 8
-    passes = -(-key_bits // rb)
-    stream = torch.cuda.current_stream()
-    calibration_copy(args, dev, stream)
-
-    print(f"# workload {args.workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
-          f"T={tx * ty}, key bits {key_bits}", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
+    print(f"# workload {workload}: {spec.width}x{spec.height}, N={len(rec)}, M={M}, "
+          f"T={sorter.tiles_x * sorter.tiles_y}, key bits {sorter.key_bits}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
         sorter(d, stream)
     torch.cuda.synchronize()
     st, m_chk = sorter.out.result()
     assert st == 0 and m_chk == M, (st, m_chk)
-
-    # ---- timed region: K whole steps, an event between consecutive steps ----
-    K = args.steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
-    for i in range(K):
+    for i in range(steps):
         sorter(d, stream)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
-    total_ms = ev[0].elapsed_time(ev[K])
-    ms_per_step = total_ms / K
-    print(f"# timed {K} steps: {ms_per_step * 1e3:.1f} us/step (host wall {wall / K * 1e6:.1f} us/step)",
-          file=sys.stderr, flush=True)
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms_per_step = ev[0].elapsed_time(ev[steps]) / steps
+    print(f"# {workload}: timed {steps} steps: {ms_per_step * 1e3:.1f} us/step "
+          f"(host wall {wall / steps * 1e6:.1f} us/step)", file=sys.stderr, flush=True)
+    kern, instr_ms = {}, None
+    if kernel_timer:
+        timer = ss.Timer(max_launches=steps * 16 + 16)
+        torch.cuda.synchronize()
+        evk0, evk1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evk0.record(stream)
+        for i in range(steps):
+            sorter(d, stream, timer=timer)
+        evk1.record(stream)
+        torch.cuda.synchronize()
+        instr_ms = evk0.elapsed_time(evk1) / steps
+        for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count", _abi.SS_KERNEL_COUNT_DUP),
+                           ("digit_bases", _abi.SS_KERNEL_DIGIT_BASES), ("depth_pass", _abi.SS_KERNEL_DEPTH_PASS),
+                           ("expand", _abi.SS_KERNEL_EXPAND), ("sort_pass", _abi.SS_KERNEL_SORT_PASS),
+                           ("ranges", _abi.SS_KERNEL_RANGES)):
+            ms, n = timer.read(kind)
+            if n:
+                kern[name] = {"launches": n, "avg_us": 1e3 * ms / n, "us_per_step": 1e3 * ms / steps}
+        timer.close()
+    return {"spec": spec, "seed": seed, "rec": rec, "d": d, "M": M, "sorter": sorter, "key32": key32,
+            "step_ms": step_ms, "ms_per_step": ms_per_step, "wall_s": wall, "kernels": kern,
+            "instrumented_ms_per_step": instr_ms}
 
-    # ---- per-kernel durations: the same K steps with HIP events around each launch ----
-    timer = ss.Timer(max_launches=K * (passes + 4) + 16)
-    torch.cuda.synchronize()
-    evk0, evk1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    evk0.record(stream)
-    for i in range(K):
-        sorter(d, stream, timer=timer)
-    evk1.record(stream)
-    torch.cuda.synchronize()
-    instr_ms_per_step = evk0.elapsed_time(evk1) / K
-    kern = {}
-    for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count", _abi.SS_KERNEL_COUNT_DUP),
-                       ("digit_bases", _abi.SS_KERNEL_DIGIT_BASES), ("depth_pass", _abi.SS_KERNEL_DEPTH_PASS),
-                       ("expand", _abi.SS_KERNEL_EXPAND), ("sort_pass", _abi.SS_KERNEL_SORT_PASS),
-                       ("ranges", _abi.SS_KERNEL_RANGES)):
-        ms, n = timer.read(kind)
-        if n:
-            kern[name] = {"launches": n, "avg_us": 1e3 * ms / n, "us_per_step": 1e3 * ms / K}
-    timer.close()
+
+def frame_parity(t) -> bool:
+    """The timed frame's GPU output against the oracle, pair for pair."""
+    import oracle
+    spec, rec, M, sorter = t["spec"], t["rec"], t["M"], t["sorter"]
+    res = (oracle.sort_frame_key32(spec.width, spec.height, rec) if t["key32"]
+           else oracle.sort_frame(spec.width, spec.height, rec, stages=False))
+    keys_gpu = sorter.out.keys.cpu().numpy().view(np.uint64)[:M]
+    vals_gpu = sorter.out.values.cpu().numpy().view(np.uint32)[:M]
+    rng_gpu = sorter.out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    return bool(res.num_pairs == M and np.array_equal(res.keys, keys_gpu)
+                and np.array_equal(res.values, vals_gpu) and np.array_equal(res.ranges, rng_gpu))
+
+
+def batch_vs_plain(args, dev, stream, steps: int, warmup: int) -> dict:
+    """The 64-frame batch as one segmented sort (eager, and replayed from an
+    autotuned graph) against the same frames as 64 plain per-frame launches,
+    with every frame's plain output compared to its batch segment."""
+    import torch
+    import paper_2511_16298_amd as ss
+
+    frames = synth.make_batch(64)
+    recs = [ss.records_to_device(r, dev) for (_, _, r) in frames]
+    ms = []
+    for (w, h, _), d in zip(frames, recs):
+        _, _, m, st = ss.count_pairs(d, w, h)
+        assert int(st.item()) == 0
+        ms.append(int(m.item()))
+    total = sum(ms)
+    shapes = [(w, h, len(r)) for (w, h, r) in frames]
+    print(f"# batch-64: N={sum(s[2] for s in shapes)}, M={total}", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for i in range(steps):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        return ev[0].elapsed_time(ev[steps]) / steps, per
+
+    eager = ss.BatchSorter(shapes, total, device=dev)
+    t_eager, _ = timed(lambda: eager(recs, stream))
+    assert eager.result() == (0, total)
+    del eager
+    gsorter = ss.BatchSorter(shapes, total, device=dev, plan_workspace=True)
+    plan = ss.Plan(gsorter, recs, autotune=True, stream=stream)
+    t_graph, per_graph = timed(lambda: plan.launch(stream))
+    assert gsorter.result() == (0, total)
+    plain = [ss.FrameSorter(w, h, n, m, device=dev) for (w, h, n), m in zip(shapes, ms)]
+
+    def run_plain():
+        for so, d in zip(plain, recs):
+            so(d, stream)
+    t_plain, per_plain = timed(run_plain)
+    base = gsorter.frame_pair_base.cpu().numpy().astype(np.int64)
+    gk = gsorter.keys.cpu().numpy().view(np.uint64)
+    gv = gsorter.values.cpu().numpy().view(np.uint32)
+    same = True
+    for f, so in enumerate(plain):
+        k = so.out.keys.cpu().numpy().view(np.uint64)[:ms[f]]
+        v = so.out.values.cpu().numpy().view(np.uint32)[:ms[f]]
+        tb = np.uint64(int(gsorter.tile_base[f])) << np.uint64(32)
+        seg = slice(int(base[f]), int(base[f]) + ms[f])
+        same &= bool(np.array_equal(gk[seg] - tb, k) and np.array_equal(gv[seg], v))
+    cfg = plan.config()
+    plan.close()
+    return {"frames": 64, "num_pairs": total, "num_gaussians": int(sum(s[2] for s in shapes)),
+            "graph_ms": t_graph, "eager_ms": t_eager, "plain_64_launches_ms": t_plain,
+            "batch_graph_pairs_per_s": total / (t_graph * 1e-3),
+            "batch_eager_pairs_per_s": total / (t_eager * 1e-3),
+            "plain_64_launches_pairs_per_s": total / (t_plain * 1e-3),
+            "speedup_vs_plain": t_plain / t_graph,
+            "latency_ms": {"p50": pct(per_graph, 50), "p99": pct(per_graph, 99)},
+            "autotuned": cfg, "outputs_identical": bool(same), "steps": steps}
+
+
+def bench_batch(args):
+    """64 uneven frames: one segmented sort (eager, and captured in an
+    autotuned graph) against 64 plain per-frame launches, same outputs."""
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b = batch_vs_plain(args, dev, torch.cuda.current_stream(), args.steps, args.warmup)
+    line = {"metric": "sorted key-value pairs/s, 64-frame segmented batch vs 64 plain launches",
+            "value": b["batch_graph_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": b["graph_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "batch-64: 64 frames, resolution uniform over 640x360/1280x720/1920x1080, "
+                                   "N log-uniform in [5e4, 2e6], seed 1003", "num_pairs": b["num_pairs"],
+                       "parallelism": "single GPU"}}
+    line.update(b)
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs on a single GPU (the sort of one frame runs "
+              "on one device, and frames or tile-row bands would shard across GPUs without exchanging "
+              "keys); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("batch-64", "serve", "sweep", "render", "preprocess", "shard-large-6m"):
+        {"batch-64": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
+         "render": bench_render, "preprocess": bench_preprocess, "shard-large-6m": bench_shard}[args.workload](args)
+        return
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    calibration_copy(args, dev, stream)
+    t = time_frame(args, args.workload, args.steps, args.warmup, dev, stream)
+    spec, seed, rec, M, sorter = t["spec"], t["seed"], t["rec"], t["M"], t["sorter"]
+    tx, ty, key_bits = sorter.tiles_x, sorter.tiles_y, sorter.key_bits
+    rb = args.radix_bits or 8
+    K, ms_per_step, step_ms, kern = args.steps, t["ms_per_step"], t["step_ms"], t["kernels"]
+    N = len(rec)
     pass_us = kern["sort_pass"]["avg_us"]
     pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair
     achieved = pass_bytes / (pass_us * 1e-6) / 1e9
-    # whole-step algorithmic bytes of the depth-first path that runs.  Frames
-    # of at most 256 tiles per axis and at most 2^23 Gaussians: count 16N read +
-    # 12N write (packed rectangle, depth key, index), four depth passes 24N
-    # each (the rectangle rides with the index), expand 12N read + 12M write,
-    # Pt tile passes 24M each, ranges 8M + 8T -- 136 N + (20 + 24 Pt) M + 8 T.
-    # Otherwise: 16N count write, 16N per depth pass, expand 8N read + 8N
-    # rectangle gather -- 112 N + ....  The direct path would move
-    # 48 N + (28 + 24 P) M + 8 T.
-    N = len(rec)
-    tile_passes = -(-(key_bits - 32) // rb)
-    per_gaussian = 136.0 if tx <= 256 and ty <= 256 and N <= (1 << 23) else 112.0
-    step_bytes = per_gaussian * N + (20.0 + 24.0 * tile_passes) * M + 8.0 * tx * ty
-    direct_bytes = 48.0 * N + (28.0 + 24.0 * passes) * M + 8.0 * tx * ty
-
+    step_bytes, direct_bytes, tile_passes = step_bytes_model(N, M, tx, ty, key_bits, rb)
     pairs_per_s = M / (ms_per_step * 1e-3)
+    p50 = pct(step_ms, 50)
     line = {
         "metric": "sorted key-value pairs/s (HBM-roofline %) + p50/p99 frame-sort latency",
         "value": pairs_per_s,
@@ -846,17 +991,23 @@ def main():
         "config": {"workload": f"{args.workload}: {spec.width}x{spec.height} image, 16x16 tiles "
                                f"({tx}x{ty}={tx * ty}), N={N} projected Gaussians, seed {seed}",
                    "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "path": args.algorithm,
-                   "depth_passes": 4, "tile_passes": tile_passes, "parallelism": "single GPU"},
-        "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99), "max": max(step_ms)},
+                   "depth_passes": kern.get("depth_pass", {}).get("launches", 0) // K,
+                   "tile_passes": tile_passes, "parallelism": "single GPU"},
+        "latency_ms": {"p50": p50, "p99": pct(step_ms, 99), "max": max(step_ms)},
+        # the dominant kernel of the step: the 64-bit-key (tile) sort pass
         "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": profiled_traffic(args.workload),
                      "bytes_per_launch": pass_bytes, "avg_launch_us": pass_us},
-        "step_model": {"path": "depth-first", "bytes": step_bytes, "GB/s": step_bytes / (ms_per_step * 1e-3) / 1e9,
-                       "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                       "direct_path_bytes": direct_bytes},
+        # the whole step: the running path's algorithmic bytes over the p50
+        # step time (HIP events), and the plain method's bytes at that time
+        "step_roofline": {"path": "depth-first", "bytes": step_bytes, "p50_ms": p50,
+                          "GB/s": step_bytes / (p50 * 1e-3) / 1e9,
+                          "frac": step_bytes / (p50 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                          "direct_path_bytes": direct_bytes,
+                          "direct_path_effective_frac": direct_bytes / (p50 * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "kernels": kern,
-        "instrumented_ms_per_step": instr_ms_per_step,
-        "host_wall_us_per_step": wall / K * 1e6,
+        "instrumented_ms_per_step": t["instrumented_ms_per_step"],
+        "host_wall_us_per_step": t["wall_s"] / K * 1e6,
     }
     prof = profiled_record(args.workload)
     if prof and prof.get("step_measured") and args.algorithm == "depth-first" and not args.radix_bits:
@@ -866,42 +1017,39 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        keys_gpu = sorter.out.keys.cpu().numpy().view(np.uint64)[:M]
-        vals_gpu = sorter.out.values.cpu().numpy().view(np.uint32)[:M]
-        rng_gpu = sorter.out.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
-        frames, spent, parity = 0, 0.0, True
+        line["parity_vs_oracle"] = frame_parity(t)
+        key32 = t["key32"]
+        frames, spent = 0, 0.0
         while spent < args.cpu_seconds or frames == 0:
-            t = time.perf_counter()
+            t0 = time.perf_counter()
             res = (oracle.sort_frame_key32(spec.width, spec.height, rec) if key32
                    else oracle.sort_frame(spec.width, spec.height, rec, stages=False))
-            spent += time.perf_counter() - t
+            spent += time.perf_counter() - t0
             frames += 1
-            if frames == 1:
-                parity = (res.num_pairs == M and np.array_equal(res.keys, keys_gpu)
-                          and np.array_equal(res.values, vals_gpu) and np.array_equal(res.ranges, rng_gpu))
         line["cpu_baseline"] = {"value": frames * M / spent, "unit": "pairs/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{frames} whole {args.workload} frames ({spent:.1f} s, "
                                           f"single-threaded oracle on {cpu_model()}, "
                                           f"{os.cpu_count()} host CPUs visible)"}
-        line["parity_vs_oracle"] = bool(parity)
         if not key32:
             # the oracle's steps one at a time on one thread (median of three
             # runs of the frame), and the stage outputs checked against the
             # whole-frame call
             st_ms = {"count": [], "scan": [], "duplicate": [], "sort": [], "ranges": []}
             for _ in range(3):
-                t = time.perf_counter(); cnt, _r = oracle.count(spec.width, spec.height, rec)
-                st_ms["count"].append(time.perf_counter() - t)
-                t = time.perf_counter(); off, tot = oracle.scan(cnt)
-                st_ms["scan"].append(time.perf_counter() - t)
-                t = time.perf_counter(); uk, uv = oracle.duplicate(spec.width, spec.height, rec, off, tot)
-                st_ms["duplicate"].append(time.perf_counter() - t)
-                t = time.perf_counter(); sk, sv = oracle.sort_pairs(uk, uv)
-                st_ms["sort"].append(time.perf_counter() - t)
-                t = time.perf_counter(); rg = oracle.ranges(sk, tx * ty)
-                st_ms["ranges"].append(time.perf_counter() - t)
+                t0 = time.perf_counter(); cnt, _r = oracle.count(spec.width, spec.height, rec)
+                st_ms["count"].append(time.perf_counter() - t0)
+                t0 = time.perf_counter(); off, tot = oracle.scan(cnt)
+                st_ms["scan"].append(time.perf_counter() - t0)
+                t0 = time.perf_counter(); uk, uv = oracle.duplicate(spec.width, spec.height, rec, off, tot)
+                st_ms["duplicate"].append(time.perf_counter() - t0)
+                t0 = time.perf_counter(); sk, sv = oracle.sort_pairs(uk, uv)
+                st_ms["sort"].append(time.perf_counter() - t0)
+                t0 = time.perf_counter(); rg = oracle.ranges(sk, tx * ty)
+                st_ms["ranges"].append(time.perf_counter() - t0)
+                del uk, uv
             stages_same = (tot == M and np.array_equal(sk, res.keys) and np.array_equal(sv, res.values)
                            and np.array_equal(rg, res.ranges))
+            del sk, sv
             line["cpu_baseline_stages_ms"] = {k: round(1e3 * float(np.median(v)), 2) for k, v in st_ms.items()}
             line["cpu_baseline_stages_ms"]["same_result_as_oracle"] = bool(stages_same)
             # the same oracle steps on all the host threads this job may use
@@ -911,22 +1059,49 @@ def main():
             mt = oracle.sort_frame_mt(spec.width, spec.height, rec, threads)
             same = (mt.status == res.status and np.array_equal(mt.keys, res.keys)
                     and np.array_equal(mt.values, res.values) and np.array_equal(mt.ranges, res.ranges))
+            del mt
             mframes, mspent = 0, 0.0
             while mspent < args.cpu_seconds / 4 or mframes < 3:
-                t = time.perf_counter()
+                t0 = time.perf_counter()
                 oracle.sort_frame_mt(spec.width, spec.height, rec, threads)
-                mspent += time.perf_counter() - t
+                mspent += time.perf_counter() - t0
                 mframes += 1
             line["cpu_baseline_parallel"] = {
                 "value": mframes * M / mspent, "unit": "pairs/s", "cores": threads, "kind": "oracle-threaded",
                 "same_result_as_oracle": bool(same),
                 "sample": f"{mframes} whole {args.workload} frames ({mspent:.1f} s, oracle steps with OpenMP "
                           f"count/duplicate and a parallel-mode stable sort on {threads} threads)"}
-        if key32:
+        else:
             # how lossy the normalised key is on this frame: pairs whose position
             # differs from the exact (tile, depth, index) order
             ex = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+            vals_gpu = sorter.out.values.cpu().numpy().view(np.uint32)[:M]
             line["key32_pairs_out_of_exact_order"] = float(np.mean(ex.values != vals_gpu))
+        del res
+    del t
+
+    if args.workload == DEFAULT_WORKLOAD and not args.no_extras and args.algorithm == "depth-first":
+        # the other single-frame workloads (p50/p99 over at least 200 steps),
+        # and the 64-frame batch against 64 plain launches
+        others = {}
+        for wl in ("fullhd-1m", "small-256x256"):
+            steps = max(K, 200)
+            o = time_frame(args, wl, steps, max(args.warmup, 20), dev, stream, kernel_timer=False)
+            sb, _, _ = step_bytes_model(len(o["rec"]), o["M"], o["sorter"].tiles_x, o["sorter"].tiles_y,
+                                        o["sorter"].key_bits)
+            p50o = pct(o["step_ms"], 50)
+            others[wl] = {"num_pairs": o["M"], "num_gaussians": len(o["rec"]), "steps": steps,
+                          "pairs_per_s": o["M"] / (o["ms_per_step"] * 1e-3), "ms_per_step": o["ms_per_step"],
+                          "latency_ms": {"p50": p50o, "p99": pct(o["step_ms"], 99)},
+                          "host_wall_us_per_step": o["wall_s"] / steps * 1e6,
+                          "step_frac_of_peak": sb / (p50o * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                          "parity_vs_oracle": frame_parity(o)}
+            del o
+        line["other_frames"] = others
+        torch.cuda.empty_cache()
+        bsteps = max(3, min(K, 10))
+        line["batch_64"] = batch_vs_plain(args, dev, stream, bsteps, min(args.warmup, 3))
+        torch.cuda.empty_cache()
     print(json.dumps(line), flush=True)
 
 

@@ -9,6 +9,7 @@ values and ranges int32 = uint32 bits).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import dataclasses
 from typing import Optional
@@ -34,6 +35,15 @@ def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
+
+
+def _allocating_on(stream):
+    """Context in which torch allocates for ``stream``: temporaries that the
+    kernels on that stream use are then not handed out again before those
+    kernels have finished, even when ``stream`` is not the current stream."""
+    if stream is None:
+        return contextlib.nullcontext()
+    return _torch().cuda.stream(stream)
 
 
 def records_to_device(records, device="cuda"):
@@ -347,11 +357,12 @@ def count_pairs(records, width: int, height: int, stream=None):
     probe = f
     st, ws = _abi.ss_workspace_bytes(probe, 0, None)
     check(st, "ss_workspace_bytes")
-    work = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
-    tt = torch.empty(n, dtype=torch.int32, device=dev)
-    off = torch.empty(n, dtype=torch.int32, device=dev)
-    m = torch.zeros(1, dtype=torch.int32, device=dev)
-    s = torch.zeros(1, dtype=torch.int32, device=dev)
+    with _allocating_on(stream):
+        work = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+        tt = torch.empty(n, dtype=torch.int32, device=dev)
+        off = torch.empty(n, dtype=torch.int32, device=dev)
+        m = torch.zeros(1, dtype=torch.int32, device=dev)
+        s = torch.zeros(1, dtype=torch.int32, device=dev)
     st = _abi.ss_count_pairs(f, tt.data_ptr(), off.data_ptr(), m.data_ptr(), s.data_ptr(),
                              work.data_ptr(), ws, _stream_handle(stream))
     check(st, "ss_count_pairs")
@@ -385,9 +396,10 @@ def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, it
                         workgroup_size=workgroup_size, algorithm=algorithm)
     st, ws = _abi.ss_sort_pairs_workspace_bytes(n, key_bits, opts)
     check(st, "ss_sort_pairs_workspace_bytes")
-    work = torch.empty(max(ws, 256), dtype=torch.uint8, device=keys.device)
-    ko = torch.empty_like(keys)
-    vo = torch.empty_like(values)
+    with _allocating_on(stream):
+        work = torch.empty(max(ws, 256), dtype=torch.uint8, device=keys.device)
+        ko = torch.empty_like(keys)
+        vo = torch.empty_like(values)
     st = _abi.ss_sort_pairs(keys.data_ptr(), values.data_ptr(), n, key_bits, ko.data_ptr(), vo.data_ptr(),
                             work.data_ptr(), ws, _stream_handle(stream), opts)
     check(st, "ss_sort_pairs")

@@ -38,8 +38,7 @@ ss_options with(const ss_options& base, const Candidate& c) {
   o.radix_bits = c.radix_bits;
   o.items_per_thread = c.items;
   o.workgroup_size = c.threads;
-  o.timer = nullptr;
-  o.flags = 0;
+  o.timer = nullptr;  // the caller's flags stay
   return o;
 }
 
@@ -52,7 +51,10 @@ void destroy(ss_plan* p) {
 }
 
 // Mean milliseconds per launch of one configuration (after one warm-up).
-ss_status time_candidate(ss_plan* p, const ss_options& o, uint32_t repeats, hipStream_t s, double* ms) {
+// The batch's status word is out.status, or else the first word of the
+// workspace (where the depth-first layout keeps it).
+ss_status time_candidate(ss_plan* p, const ss_options& o, uint32_t repeats, hipStream_t s, double* ms,
+                         ss_status* device_status) {
   const uint32_t n = static_cast<uint32_t>(p->frames.size());
   ss_status st = ss_sort_batch(p->frames.data(), n, &p->out, p->workspace, p->workspace_bytes, s, &o);
   if (st != SS_OK) return st;
@@ -73,6 +75,17 @@ ss_status time_candidate(ss_plan* p, const ss_options& o, uint32_t repeats, hipS
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   *ms = static_cast<double>(t) / repeats;
+  // a candidate that stopped early on a device error (look-back timeout,
+  // capacity, bad input) would time as the fastest: read its status word
+  if (st == SS_OK) {
+    uint32_t dev_status = SS_ERR_HIP;
+    const uint32_t* word = p->out.status ? p->out.status : static_cast<const uint32_t*>(p->workspace);
+    if (hipMemcpyAsync(&dev_status, word, sizeof(dev_status), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = SS_ERR_HIP;
+    else
+      *device_status = static_cast<ss_status>(dev_status);
+  }
   return st;
 }
 
@@ -127,8 +140,15 @@ ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream)
           b > desc->workspace_bytes)
         continue;
       double ms = 0.0;
-      st = time_candidate(p, o, repeats, s, &ms);
+      ss_status dev = SS_OK;
+      st = time_candidate(p, o, repeats, s, &ms, &dev);
       if (st != SS_OK) break;
+      if (dev != SS_OK) {
+        // a device error is the data's (capacity, bad depth) or a timeout: the
+        // candidate is not chosen; its time is reported as negative
+        p->candidate_ms.push_back(-1.0);
+        continue;
+      }
       p->candidate_ms.push_back(ms);
       if (ms < best) {
         best = ms;

@@ -92,32 +92,43 @@ def test_batch_capacity_error():
     assert st == ss._abi.SS_ERR_CAPACITY and m == total
 
 
-def test_full_64_frame_batch_sampled():
-    """The 64-frame batch at full size: three frames checked pair for pair
-    against the oracle, every frame checked by invariants."""
-    frames = synth.make_batch(64)
-    b, st, m = run_batch(frames)
-    assert st == 0
+def test_full_64_frame_batch_every_frame(batch64):
+    """The 64-frame batch at full size (38.8M Gaussians, 182.9M pairs: the
+    unpacked-rectangle path, since it holds more than 2^23 Gaussians): every
+    frame's segment, frame-local ranges, pair count and first pair compared
+    pair for pair with the oracle's result for that frame alone."""
+    frames, refs = batch64
+    ms = [int(r.num_pairs) for r in refs]
+    b, st, m = run_batch(frames, capacity=sum(ms))
+    assert st == 0 and m == sum(ms)
     keys, vals = u64(b.keys)[:m], u32(b.values)[:m]
     rng = u32(b.tile_ranges).reshape(-1, 2)
     base, cnt = u32(b.frame_pair_base).astype(np.int64), u32(b.frame_pairs).astype(np.int64)
-    assert base[0] == 0 and np.array_equal(base[1:], (base + cnt)[:-1]) and base[-1] + cnt[-1] == m
-    assert np.all(keys[1:] >= keys[:-1])
-    assert rng[0, 0] == 0 and rng[-1, 1] == m and np.array_equal(rng[1:, 0], rng[:-1, 1])
-    sizes = [len(r) for (_, _, r) in frames]
-    for f in np.argsort(sizes)[:3]:
-        w, h, rec = frames[f]
-        ref = oracle.sort_frame(w, h, rec, stages=False)
+    assert np.array_equal(cnt, np.array(ms, np.int64))
+    assert np.array_equal(base, np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64))
+    tile_base = 0
+    for f, ref in enumerate(refs):
+        assert int(b.tile_base[f]) == tile_base, f
         seg = slice(int(base[f]), int(base[f] + cnt[f]))
-        assert cnt[f] == ref.num_pairs
-        tb = np.uint64(int(b.tile_base[f])) << np.uint64(32)
-        assert np.array_equal(keys[seg] - tb, ref.keys)
-        assert np.array_equal(vals[seg], ref.values)
-    for f, (w, h, rec) in enumerate(frames):
-        seg = slice(int(base[f]), int(base[f] + cnt[f]))
-        v = vals[seg]
-        cnt_g, _ = oracle.count(w, h, rec)
-        assert np.array_equal(np.bincount(v, minlength=len(rec))[:len(rec)], cnt_g)
+        tb = np.uint64(tile_base) << np.uint64(32)
+        assert np.array_equal(keys[seg] - tb, ref.keys), f
+        assert np.array_equal(vals[seg], ref.values), f
+        t = ref.num_tiles
+        assert np.array_equal(rng[tile_base:tile_base + t] - np.uint32(base[f]), ref.ranges), f
+        tile_base += t
+    assert tile_base == rng.shape[0]
+
+
+def test_batch_with_unpacked_rectangles():
+    """Frames wider or taller than 256 tiles: the depth sort carries no packed
+    rectangles and expand gathers the 64-bit rectangles by index."""
+    frames = [(4200, 200, synth.make_frame(synth.FrameSpec(4200, 200, 20_000), 41)),
+              (640, 360, synth.make_frame(synth.FrameSpec(640, 360, 12_000), 42)),
+              (300, 4500, synth.make_frame(synth.FrameSpec(300, 4500, 9_000), 43))]
+    for rb in (8, 6):
+        b, st, m = run_batch(frames, radix_bits=rb)
+        assert st == 0
+        check_against_oracle(frames, b, m)
 
 
 def test_plan_graph_replays_match_eager():

@@ -47,6 +47,38 @@ def test_results_in_the_mix_equal_alone():
     srv.close()
 
 
+def test_batch_sized_requests_in_the_mix_equal_alone(batch64):
+    """Requests drawn from the batch distribution at full size (50k-2M
+    Gaussians per frame, the served workload's frames), several rounds in
+    flight on two streams with up to 16 frames per round: every result equals
+    the oracle's result for that frame alone, pair for pair."""
+    frames, refs = batch64
+    sizes = np.array([len(r) for (_, _, r) in frames])
+    big = [int(i) for i in np.argsort(sizes)[::-1][:3]]      # the three largest frames (>= 1M Gaussians)
+    assert sizes[big].min() >= 1_000_000
+    rs = np.random.default_rng(11)
+    order = big + [int(i) for i in rs.integers(0, len(frames), 33)] + big
+    dev = {i: ss.records_to_device(frames[i][2]) for i in set(order)}
+    srv = ss.Server(24 << 30, max_batch_frames=16, n_streams=2)
+    tickets = [(srv.submit(dev[i], frames[i][0], frames[i][1]), i) for i in order]
+    mixed = 0
+    for t, i in tickets:
+        r = srv.wait(t)
+        assert r.status == 0, _abi.status_string(r.status)
+        ref = refs[i]
+        assert r.num_pairs == ref.num_pairs, i
+        k, v, rg = srv.result_arrays(r, ref.num_tiles)
+        assert np.array_equal(k, ref.keys), i
+        assert np.array_equal(v, ref.values), i
+        assert np.array_equal(rg, ref.ranges), i
+        mixed += r.round_frames > 1
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == len(order) and st["pending"] == 0 and st["arena_used"] == 0
+    assert mixed > 0, "no request was batched with another"
+    srv.close()
+
+
 def test_budget_rejects_what_can_never_fit_and_waits_otherwise():
     big = synth.make_frame(synth.scaled(synth.FULL_HD, 200_000), 3)
     small = frames_pool(6, 502, n_range=(2_000, 4_000))

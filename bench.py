@@ -763,22 +763,40 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def packed_pairs(n: int, max_frame_n: int, tile_bits: int, tile_passes: int) -> bool:
+    """Whether the default tile passes carry each pair as one 64-bit item:
+    tile, a depth field of at least 27 bits and the frame-local index fit,
+    and so does the depth-order position that replaces the depth field when
+    the depths span too many binades (the library's rule, default shapes)."""
+    idx_bits = (max_frame_n - 1).bit_length() if max_frame_n > 1 else 0
+    field = 64 - tile_bits - idx_bits
+    pos_bits = (n - 1).bit_length() if n > 1 else 0
+    return tile_passes >= 1 and tile_bits <= 32 and idx_bits < 32 and field >= 27 and pos_bits <= field
+
+
 def step_bytes_model(n: int, m: int, tiles_x: int, tiles_y: int, key_bits: int, rb: int = 8) -> tuple:
-    """(depth-first step bytes, direct-path bytes) of one frame.
+    """(depth-first step bytes, direct-path bytes, tile passes, packed) of one frame.
 
     Depth-first, frames of at most 256 tiles per axis and at most 2^23
     Gaussians: count 16N read + 12N write (packed rectangle, depth key,
     index), four depth passes 24N each (the rectangle rides with the index),
-    expand 12N read + 12M write, Pt tile passes 24M each, ranges 8M + 8T --
-    136 N + (20 + 24 Pt) M + 8 T.  Otherwise: 16N count write, 16N per depth
-    pass, expand 8N read + 8N rectangle gather -- 112 N + ....  The direct
-    path would move 48 N + (28 + 24 P) M + 8 T."""
-    tile_passes = -(-(key_bits - 32) // rb)
+    expand 12N read.  Then, with packed 64-bit pairs: expand writes 8M, the
+    Pt - 1 first tile passes 16M each, the last one reads 8M and writes the
+    12-byte pairs and the ranges (8T) -- 136 N + (12 + 16 Pt) M + 8 T;
+    otherwise expand writes 12M, each tile pass moves 24M and the ranges
+    kernel reads 8M and writes 8T -- 136 N + (20 + 24 Pt) M + 8 T.  Larger
+    frames: 16N count write, 16N per depth pass, expand 8N read + 8N
+    rectangle gather -- 112 N + ....  The direct path would move
+    48 N + (28 + 24 P) M + 8 T."""
+    tile_bits = key_bits - 32
+    tile_passes = -(-tile_bits // rb)
     passes = -(-key_bits // rb)
     per_gaussian = 136.0 if tiles_x <= 256 and tiles_y <= 256 and n <= (1 << 23) else 112.0
-    step = per_gaussian * n + (20.0 + 24.0 * tile_passes) * m + 8.0 * tiles_x * tiles_y
+    packed = packed_pairs(n, n, tile_bits, tile_passes)
+    per_pair = (12.0 + 16.0 * tile_passes) if packed else (20.0 + 24.0 * tile_passes)
+    step = per_gaussian * n + per_pair * m + 8.0 * tiles_x * tiles_y
     direct = 48.0 * n + (28.0 + 24.0 * passes) * m + 8.0 * tiles_x * tiles_y
-    return step, direct, tile_passes
+    return step, direct, tile_passes, packed
 
 
 def time_frame(args, workload: str, steps: int, warmup: int, dev, stream, kernel_timer: bool = True):
@@ -972,7 +990,15 @@ def main():
     pass_us = kern["sort_pass"]["avg_us"]
     pass_bytes = 24.0 * M                       # read + write of (u64 key, u32 value) per pair
     achieved = pass_bytes / (pass_us * 1e-6) / 1e9
-    step_bytes, direct_bytes, tile_passes = step_bytes_model(N, M, tx, ty, key_bits, rb)
+    step_bytes, direct_bytes, tile_passes, packed = step_bytes_model(N, M, tx, ty, key_bits, rb)
+    if (packed and args.algorithm == "depth-first" and args.radix_bits in (0, 8) and args.items in (0, 8, 16)
+            and args.wg in (0, 512)):
+        # packed pairs: the first Pt - 1 passes move 8-byte items (16 B per
+        # pair), the last reads 8 and writes 12; per launch on average
+        pass_bytes = (16.0 * (tile_passes - 1) + 20.0) / tile_passes * M
+        achieved = pass_bytes / (pass_us * 1e-6) / 1e9
+    else:
+        packed = False
     pairs_per_s = M / (ms_per_step * 1e-3)
     p50 = pct(step_ms, 50)
     line = {
@@ -992,7 +1018,7 @@ def main():
                                f"({tx}x{ty}={tx * ty}), N={N} projected Gaussians, seed {seed}",
                    "num_pairs": M, "key_bits": key_bits, "radix_bits": rb, "path": args.algorithm,
                    "depth_passes": kern.get("depth_pass", {}).get("launches", 0) // K,
-                   "tile_passes": tile_passes, "parallelism": "single GPU"},
+                   "tile_passes": tile_passes, "packed_pairs": packed, "parallelism": "single GPU"},
         "latency_ms": {"p50": p50, "p99": pct(step_ms, 99), "max": max(step_ms)},
         # the dominant kernel of the step: the 64-bit-key (tile) sort pass
         "roofline": {"bound": "hbm", "kernel": "sort_pass", "achieved": achieved, "peak": PEAK_HBM_GBS,
@@ -1087,8 +1113,8 @@ def main():
         for wl in ("fullhd-1m", "small-256x256"):
             steps = max(K, 200)
             o = time_frame(args, wl, steps, max(args.warmup, 20), dev, stream, kernel_timer=False)
-            sb, _, _ = step_bytes_model(len(o["rec"]), o["M"], o["sorter"].tiles_x, o["sorter"].tiles_y,
-                                        o["sorter"].key_bits)
+            sb, _, _, _ = step_bytes_model(len(o["rec"]), o["M"], o["sorter"].tiles_x, o["sorter"].tiles_y,
+                                           o["sorter"].key_bits)
             p50o = pct(o["step_ms"], 50)
             others[wl] = {"num_pairs": o["M"], "num_gaussians": len(o["rec"]), "steps": steps,
                           "pairs_per_s": o["M"] / (o["ms_per_step"] * 1e-3), "ms_per_step": o["ms_per_step"],

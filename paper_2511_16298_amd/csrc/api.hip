@@ -16,6 +16,8 @@ constexpr uint32_t kDefaultRadix = 8;
 constexpr uint32_t kDefaultItems = 16;
 constexpr uint32_t kDefaultThreads = 512;
 constexpr size_t kAlign = 256;
+// tile passes: at most ceil(32 / 4)
+constexpr uint32_t kMaxTilePasses = 8;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
@@ -152,6 +154,10 @@ PassCfg depth_cfg(uint32_t n) {
 
 struct DfLayout {
   uint32_t n = 0, n_frames = 0, capacity = 0, total_tiles = 0, tile_bits = 0, tpasses = 0, tbins = 256, trb = 8;
+  // packed pairs through the tile passes (PackedPairs): tile << (64 - tile
+  // bits) | depth field << idx_bits | index
+  bool packed = false;
+  uint32_t idx_bits = 0;
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
@@ -160,7 +166,22 @@ struct DfLayout {
          key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, total = 0;
 };
 
-DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64_t total_tiles, const Options& o) {
+// Pairs travel through the tile passes as one 64-bit item when the tile id,
+// the largest frame-local index and a depth field fit: the depth field needs
+// 27 bits for depths spanning up to 16 binades (23 mantissa bits plus the
+// exponent above the smallest one), and at least the bits of a position in
+// depth order (the fallback when the depths span more).
+bool use_packed(uint32_t tile_bits, uint32_t tpasses, uint32_t idx_bits, uint32_t n, const PassCfg& tcfg,
+                uint32_t trb) {
+  if (tpasses == 0 || tile_bits > 32) return false;
+  if (!packed_pass_supported(static_cast<int>(trb), static_cast<int>(tcfg.items), static_cast<int>(tcfg.threads)))
+    return false;
+  const uint32_t depth_field = 64 - tile_bits - idx_bits;
+  return idx_bits < 32 && depth_field >= 27 && ceil_log2(n) <= depth_field;
+}
+
+DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64_t total_tiles, const Options& o,
+                        uint32_t max_frame_n) {
   DfLayout L;
   L.n = n;
   L.n_frames = n_frames;
@@ -183,10 +204,13 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   if (o.items_default && o.threads == 512 && o.items == 16 && capacity < (1u << 23)) L.tcfg.items = 8;
   L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
   L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile();
+  L.idx_bits = ceil_log2(max_frame_n);
+  L.packed = use_packed(L.tile_bits, L.tpasses, L.idx_bits, n, L.tcfg, L.trb);
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
   L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
   size_t off = 0;
-  L.scalars = off;   off = align_up(off + 8 * sizeof(uint32_t));  // status, M, offsets' M and status, live
+  L.scalars = off;   off = align_up(off + 8 * sizeof(uint32_t));  // status, M, offsets' M and status, live,
+                                                                     // depth top byte max / min
   L.bad = off;       off = align_up(off + sizeof(uint32_t));
   L.totals = off;    off = align_up(off + (1 + static_cast<size_t>(n_frames)) * sizeof(uint64_t));
   L.ck_blocks = (n + kCountKeysTile - 1) / kCountKeysTile;
@@ -197,7 +221,9 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.hist_d = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * 4 * 256 * sizeof(uint32_t));
   L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * L.tpasses * L.tbins * sizeof(uint32_t));
   L.lb_d = off;      off = align_up(off + static_cast<size_t>(4) * L.dblocks * 256 * sizeof(uint32_t));
-  L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses) * L.tblocks * L.tbins * sizeof(uint32_t));
+  // packed: the last tile pass's look-back words are 64-bit (one more slice)
+  L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses + (L.packed ? 1 : 0)) * L.tblocks * L.tbins *
+                                            sizeof(uint32_t));
   L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
   L.clear_end = off;
   L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
@@ -292,6 +318,16 @@ struct PassChain {
   // writes pdst[p]), or NULL
   const uint32_t* const* psrc;
   uint32_t* const* pdst;
+  // packed pairs (64-bit items): NULL for key + value passes.  The last pass
+  // unpacks into kdst/vdst and writes the tile ranges, with 64-bit look-back
+  // words at lookback64.
+  const PackedPairs* packed;
+  uint32_t* ranges;
+  uint64_t* lookback64;
+  // the depth sort: its first pass stores the top-byte range of the depth
+  // keys with pairs (for packed pairs) at depth_top_out, from hist_top
+  uint32_t* depth_top_out;
+  const uint32_t* hist_top;
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -325,6 +361,20 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
         a.pin = c.psrc[p];
         a.pout = c.pdst[p];
       }
+      if (p == 0 && c.depth_top_out != nullptr) {
+        a.depth_top_out = c.depth_top_out;
+        a.hist_top = c.hist_top;
+      }
+      int mode = kPassKV;
+      if (c.packed != nullptr) {
+        a.packed = *c.packed;
+        mode = p + 1 == c.npasses ? kPassUnpack : kPassItems;
+        if (mode == kPassUnpack) {
+          a.ranges = c.ranges;
+          a.low_bits = a.shift - c.packed->tile_shift;
+          a.lookback64 = c.lookback64;
+        }
+      }
       a.lookback = c.lookback + static_cast<size_t>(p) * c.nblocks * bins;
       // the last pass ranks only its significant digit bits where a narrower
       // pass exists (its digits above them are empty; the histogram, base and
@@ -337,7 +387,7 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
         if (narrow != 0) rb = narrow;
       }
       if (launch_pass(a, static_cast<int>(c.key_bytes), rb, static_cast<int>(c.cfg.items),
-                      static_cast<int>(c.cfg.threads), c.nblocks, s) != hipSuccess)
+                      static_cast<int>(c.cfg.threads), c.nblocks, s, mode) != hipSuccess)
         return SS_ERR_HIP;
     }
     return SS_OK;
@@ -530,6 +580,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
                 nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d), 0,
                 live ? ck.hist + 3 * 256 + 255 : nullptr, live,  // digit 255 of the top byte: culled only
                 pack ? ps : nullptr, pack ? pd : nullptr};
+    if (lay.packed) {
+      c.depth_top_out = scal + 5;
+      c.hist_top = ck.hist + 3 * 256;
+    }
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
 
@@ -541,6 +595,19 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   bv[P % 2] = io.values;
   bk[(P + 1) % 2] = at<uint64_t>(ws, lay.alt_keys);
   bv[(P + 1) % 2] = at<uint32_t>(ws, lay.alt_vals);
+  // Packed pairs: items ping-pong between the workspace and the output key
+  // array, so that the last pass reads the workspace and unpacks into the
+  // output: pass p reads the workspace when P - 1 - p is even.
+  PackedPairs pk{};
+  uint64_t* items_in[kMaxTilePasses + 1];
+  if (lay.packed) {
+    pk.tile_shift = 64 - lay.tile_bits;
+    pk.idx_bits = lay.idx_bits;
+    pk.depth_top = scal + 5;
+    pk.depth_sorted = key;
+    for (uint32_t p = 0; p < P; ++p) items_in[p] = (P - 1 - p) % 2 == 0 ? at<uint64_t>(ws, lay.alt_keys) : io.keys;
+    bk[0] = items_in[0];
+  }
   ExpandArgs e{};
   e.table = table;
   e.n_frames = lay.n_frames;
@@ -559,6 +626,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.lookback = at<uint64_t>(ws, lay.expand_lb);
   e.status = d_status;
   e.nblocks = lay.eblocks;
+  e.packed = lay.packed;
+  e.pk = pk;
   e.totals = PairTotalsArgs{ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, lay.n_frames,
                             lay.capacity, d_num_pairs, d_status, io.frame_pairs, io.frame_pair_base};
   SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
@@ -573,11 +642,38 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       vs[p] = bv[p % 2];
       kd[p] = bk[(p + 1) % 2];
       vd[p] = bv[(p + 1) % 2];
+      if (lay.packed) {
+        ks[p] = items_in[p];
+        vs[p] = nullptr;
+        kd[p] = p + 1 < P ? static_cast<void*>(items_in[p + 1]) : static_cast<void*>(io.keys);
+        vd[p] = p + 1 < P ? nullptr : io.values;
+      }
     }
-    PassChain c{P, 8, 32, lay.trb, lay.tcfg, lay.tblocks, ks.data(), vs.data(), kd.data(), vd.data(), d_num_pairs, 0,
-                d_status, bases_t, e.hist, P * lay.tbins, at<uint32_t>(ws, lay.lb_t),
+    uint32_t* lb_t = at<uint32_t>(ws, lay.lb_t);
+    PassChain c{P, 8, lay.packed ? pk.tile_shift : 32u, lay.trb, lay.tcfg, lay.tblocks, ks.data(), vs.data(),
+                kd.data(), vd.data(), d_num_pairs, 0, d_status, bases_t, e.hist, P * lay.tbins, lb_t,
                 lay.tile_bits - lay.trb * (P - 1)};
+    if (lay.packed) {
+      c.packed = &pk;
+      c.ranges = io.ranges;
+      // after the 32-bit words of passes 0 .. P-2 (a multiple of 64 bytes)
+      c.lookback64 = reinterpret_cast<uint64_t*>(lb_t + static_cast<size_t>(P - 1) * lay.tblocks * lay.tbins);
+    }
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
+    if (lay.packed) {
+      // the digits of the last pass: those of its (possibly narrower)
+      // instantiation, whose bases are all published (when it is also the
+      // first pass, it publishes only those)
+      uint32_t last_rb = lay.trb;
+      const uint32_t last_bits = lay.tile_bits - lay.trb * (P - 1);
+      const int narrow = narrow_pass_bits(static_cast<int>(last_bits), 8, static_cast<int>(lay.trb),
+                                          static_cast<int>(lay.tcfg.items), static_cast<int>(lay.tcfg.threads));
+      if (last_bits < lay.trb && narrow != 0) last_rb = static_cast<uint32_t>(narrow);
+      return L.run(SS_KERNEL_RANGES, [&] {
+        return launch_ranges_fix(io.keys, d_num_pairs, d_status, bases_t + static_cast<size_t>(P - 1) * lay.tbins,
+                                 1u << last_rb, lay.total_tiles, io.ranges, s);
+      });
+    }
   }
   return L.run(SS_KERNEL_RANGES, [&] {
     return launch_ranges(io.keys, d_num_pairs, d_status, lay.capacity, lay.total_tiles, io.ranges, s);
@@ -604,6 +700,7 @@ FrameInfo frame_info(const ss_frame* f, const Geometry& g, uint32_t gauss_base, 
 struct BatchShape {
   std::vector<FrameInfo> table;
   uint64_t n = 0, tiles = 0;
+  uint32_t max_n = 0;   // Gaussians of the largest frame
 };
 
 ss_status batch_shape(const ss_frame* frames, uint32_t n_frames, BatchShape* b) {
@@ -617,6 +714,7 @@ ss_status batch_shape(const ss_frame* frames, uint32_t n_frames, BatchShape* b) 
     b->table[f] = frame_info(&frames[f], g, static_cast<uint32_t>(b->n), static_cast<uint32_t>(b->tiles));
     b->n += frames[f].num_gaussians;
     b->tiles += g.num_tiles;
+    if (frames[f].num_gaussians > b->max_n) b->max_n = frames[f].num_gaussians;
     if (b->n > 0x7FFFFFFFull || b->tiles > 0xFFFFFFFFull) return SS_ERR_INVALID_ARGUMENT;
   }
   return SS_OK;
@@ -735,7 +833,8 @@ ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity, cons
   SS_TRY(parse_options(options, &o));
   if (pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
   const size_t sort = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
-                                    : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o).total;
+                                    : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o,
+                                                     frame->num_gaussians).total;
   // ss_count_pairs runs in any workspace sized here (its own layout can be
   // the larger one, e.g. for N = 0)
   const size_t count = make_layout(frame->num_gaussians, 0, g.key_bits, Options{}).total;
@@ -791,7 +890,7 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   Launcher L(s, o.timer);
   if (use_direct(o)) return run_direct(L, frame, g, out, o, workspace, s);
   const FrameInfo fi = frame_info(frame, g, 0, 0);
-  const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o);
+  const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o, frame->num_gaussians);
   DfIO io{&fi, frame, out->keys, out->values, out->tile_ranges, out->tiles_touched, out->offsets,
           out->num_pairs, out->status, nullptr, nullptr};
   return run_depth_first(L, lay, o, io, workspace, s);
@@ -805,7 +904,7 @@ ss_status ss_batch_workspace_bytes(const ss_frame* frames, uint32_t n_frames, ui
   Options o;
   SS_TRY(parse_options(options, &o));
   if (use_direct(o)) return SS_ERR_UNSUPPORTED;
-  *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o).total;
+  *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o, b.max_n).total;
   return SS_OK;
 }
 
@@ -822,7 +921,7 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
   if (cap > 0 && (out->keys == nullptr || out->values == nullptr)) return SS_ERR_INVALID_ARGUMENT;
   if (!aligned(out->keys, 8) || !aligned(out->values, 4) || !aligned(out->tile_ranges, 4))
     return SS_ERR_INVALID_ARGUMENT;
-  const DfLayout lay = make_df_layout(static_cast<uint32_t>(b.n), n_frames, cap, b.tiles, o);
+  const DfLayout lay = make_df_layout(static_cast<uint32_t>(b.n), n_frames, cap, b.tiles, o, b.max_n);
   if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total) return SS_ERR_WORKSPACE;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);

@@ -148,4 +148,63 @@ __device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_
   return true;
 }
 
+// The look-back above with 64-bit words that also carry a maximum: bits 0-29
+// the count, bits 30-61 a value combined by max (0 = none), bits 62-63 the
+// state.  Returns the exclusive count and maximum, and publishes this
+// workgroup's inclusive word (own count and maximum `own_max`).
+constexpr uint64_t kLbAggW = 1ull << 62;
+constexpr uint64_t kLbIncW = 2ull << 62;
+constexpr uint64_t kLbCountW = (1ull << 30) - 1;
+constexpr uint64_t kLbMaxW = (1ull << 32) - 1;
+
+__device__ __forceinline__ uint64_t lb_word(uint64_t state, uint32_t count, uint32_t mx) {
+  return state | (static_cast<uint64_t>(mx) << 30) | count;
+}
+
+__device__ __forceinline__ bool lookback_digit_max(uint64_t* lb, uint32_t t, uint32_t stride, uint32_t d,
+                                                   uint32_t own, uint32_t own_max, uint32_t* status,
+                                                   uint32_t& excl, uint32_t& excl_max) {
+  excl = 0;
+  excl_max = 0;
+  if (t == 0) return true;
+  int32_t kb = static_cast<int32_t>(t) - 1;
+  uint32_t spins = 0;
+  while (true) {
+    uint64_t w[kLookbackWindow];
+#pragma unroll
+    for (int j = 0; j < kLookbackWindow; ++j)
+      w[j] = kb - j >= 0 ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbIncW;
+    uint32_t add = 0, mx = 0;
+    int32_t used = 0;
+    bool inc = false, stall = false;
+#pragma unroll
+    for (int j = 0; j < kLookbackWindow; ++j) {
+      if (inc || stall) continue;
+      if ((w[j] >> 62) == 0) {
+        stall = true;
+      } else {
+        add += static_cast<uint32_t>(w[j] & kLbCountW);
+        const uint32_t m = static_cast<uint32_t>((w[j] >> 30) & kLbMaxW);
+        mx = m > mx ? m : mx;
+        ++used;
+        inc = (w[j] >> 62) == 2;
+      }
+    }
+    excl += add;
+    excl_max = mx > excl_max ? mx : excl_max;
+    if (inc) break;
+    kb -= used;
+    if (stall) {
+      if (++spins > kSpinLimit) {
+        if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  st_agent(&lb[static_cast<size_t>(t) * stride + d],
+           lb_word(kLbIncW, excl + own, own_max > excl_max ? own_max : excl_max));
+  return true;
+}
+
 }  // namespace ss

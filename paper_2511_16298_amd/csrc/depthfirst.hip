@@ -254,6 +254,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   const uint32_t ticket = blockIdx.x;   // look-back order (see common.hpp)
   const uint32_t base = ticket * kExpandTile;
   const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;  // Gaussians the depth sort kept
+  uint32_t ebase = 0;
+  const bool trimmed = a.packed && packed_depth_trimmed(a.pk.depth_top[0], a.pk.depth_top[1], a.pk, &ebase);
 
   // ---- Gaussians of this workgroup: striped loads, per-Gaussian info ----
 #pragma unroll
@@ -285,7 +287,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       cnt = w * h;
       s_org[i] = s_tab[f].tile_base + y0 * tx + x0;
       s_wt[i] = w | (tx << 16);
-      s_dep[i] = dep;
+      // packed items carry the depth field: trimmed depth bits, or the
+      // position in depth order (the unpacking pass looks the bits up)
+      s_dep[i] = !a.packed ? dep : trimmed ? dep - ebase : pos;
       s_loc[i] = g - s_tab[f].gauss_base;
     }
     s_off[i] = cnt;
@@ -411,8 +415,13 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         const uint32_t dy = kk / w;
         const uint32_t dx = kk - dy * w;
         const uint32_t tile = s_org[i] + dy * (wt >> 16) + dx;
-        keys[q] = (static_cast<uint64_t>(tile) << 32) | s_dep[i];
-        vals[q] = s_loc[i];
+        if (a.packed) {
+          keys[q] = (static_cast<uint64_t>(tile) << a.pk.tile_shift) |
+                    (static_cast<uint64_t>(s_dep[i]) << a.pk.idx_bits) | s_loc[i];
+        } else {
+          keys[q] = (static_cast<uint64_t>(tile) << 32) | s_dep[i];
+          vals[q] = s_loc[i];
+        }
         for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&s_hist[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
       }
     }

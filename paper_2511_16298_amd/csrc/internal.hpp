@@ -31,6 +31,29 @@ struct CountDupArgs {
   uint32_t nblocks;
 };
 
+// A (tile, depth, index) pair held in one 64-bit item: tile << tile_shift |
+// depth field << idx_bits | frame-local index.  The depth field is the depth
+// bits minus (b_min << 24), b_min the smallest top byte of a depth that has
+// pairs, when every such depth then fits (trimmed); otherwise it is the
+// Gaussian's position in depth order, and the unpacking pass reads the depth
+// bits there (depth_sorted).  Both sides decide the same way from the two
+// words the depth sort's first pass stores from its top-byte histogram:
+// depth_top[0] = largest, depth_top[1] = smallest top byte of such a depth.
+struct PackedPairs {
+  uint32_t tile_shift;          // 64 - tile bits
+  uint32_t idx_bits;            // index field width
+  const uint32_t* depth_top;    // [2]
+  const uint32_t* depth_sorted; // raw depth bits in depth order (the fallback's lookup)
+};
+
+__device__ __forceinline__ bool packed_depth_trimmed(uint32_t top_max, uint32_t top_min, const PackedPairs& p,
+                                                     uint32_t* ebase) {
+  *ebase = top_min << 24;
+  const uint32_t dbits = p.tile_shift - p.idx_bits;
+  const uint64_t span = top_max >= top_min ? static_cast<uint64_t>(top_max - top_min + 1) : 1ull;
+  return dbits >= 32 || (span << 24) <= (1ull << dbits);
+}
+
 struct PassArgs {
   const void* kin;            // uint64_t or uint32_t keys
   const uint32_t* vin;
@@ -68,6 +91,23 @@ struct PassArgs {
   // with the first; the depth sort carries the Gaussians' packed rectangles
   const uint32_t* pin;
   uint32_t* pout;
+  // The depth sort's first pass: when not NULL, its workgroup 0 stores here,
+  // after its tile, the largest and smallest top byte among the depth keys
+  // of Gaussians with pairs (from hist_top, copy c at + c * hist_stride, of
+  // the keys' top byte; bin 255 holds the culled ones).
+  uint32_t* depth_top_out;
+  const uint32_t* hist_top;
+  // Packed pairs (64-bit items without values, see PackedPairs): the layout
+  // and, for the pass that unpacks them, where the depth bits come from.
+  PackedPairs packed;
+  // Tile ranges written by the last tile pass (NULL: not this pass).  Its
+  // look-back words are 64-bit (lookback64, zeroed [nblocks][bins]): count,
+  // and 1 + the largest tile part below this pass's digit among the counted
+  // pairs, so that the first pair of a digit run knows its predecessor's
+  // tile; each digit's first pair overall is left to k_ranges_fix.
+  uint32_t* ranges;
+  uint32_t low_bits;          // tile bits below this pass's digit
+  uint64_t* lookback64;
 };
 
 struct HistArgs {
@@ -144,8 +184,10 @@ struct ExpandArgs {
   const uint32_t* rect32;   // or packed rectangles in depth order (sorted with the keys; a
                             // culled Gaussian's is ignored: its key is 0xFFFFFFFF)
   uint32_t capacity;
-  uint64_t* keys;           // out pairs: global tile << 32 | depth bits
-  uint32_t* values;         // out: frame-local Gaussian index
+  uint64_t* keys;           // out pairs: global tile << 32 | depth bits (or packed items)
+  uint32_t* values;         // out: frame-local Gaussian index (unused when packed)
+  bool packed;              // write packed 64-bit items (layout `pk`) instead
+  PackedPairs pk;
   uint32_t npasses;         // tile-digit passes that follow
   uint32_t radix_bits;      // their digit width (<= 8)
   uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits]
@@ -171,8 +213,19 @@ hipError_t launch_ranges(const uint64_t* keys, const uint32_t* num_pairs, const 
                          uint32_t capacity, uint32_t num_tiles, uint32_t* ranges, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_hist(const HistArgs& a, int radix_bits, hipStream_t s);
+// mode: kPassKV (key + value), kPassItems (packed items in and out),
+// kPassUnpack (packed items in; keys + values out, tile ranges when
+// a.ranges != NULL).
+constexpr int kPassKV = 0, kPassItems = 1, kPassUnpack = 2;
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
-                       hipStream_t s);
+                       hipStream_t s, int mode = kPassKV);
+// Whether a packed pass of this shape is compiled.
+bool packed_pass_supported(int radix_bits, int items, int threads);
+// After a last pass with fused ranges: each digit's first pair (its
+// predecessor is in another digit run) and the tail past the last pair.
+hipError_t launch_ranges_fix(const uint64_t* keys, const uint32_t* num_pairs, const uint32_t* status,
+                             const uint32_t* bases, uint32_t bins, uint32_t num_tiles, uint32_t* ranges,
+                             hipStream_t s);
 // The compiled digit width (>= bits) that a pass of this shape can use when
 // its digit has only `bits` significant bits, or 0 (use radix_bits).
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads);

@@ -6,6 +6,13 @@
 // workgroup needs only the counts of its digits in earlier workgroups, which
 // it gets by a decoupled look-back, and then scatters its tile straight to the
 // output.  One read and one write of every pair per pass.
+//
+// Three forms of the item: a key with a 32-bit value (kPassKV, both key
+// widths); a packed 64-bit pair alone (kPassItems: tile, depth field and
+// index in one word, see PackedPairs); and the last pass over packed pairs
+// (kPassUnpack), which writes the pairs back as 64-bit keys (tile << 32 |
+// depth bits) and 32-bit indices and, while it writes them, the tile ranges:
+// a pair whose tile differs from its predecessor's starts a range.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -28,7 +35,7 @@ namespace {
 // keep LDS small (160 KB per CU holds four 256 x 16 tiles of 64-bit keys, or
 // two 512 x 16 ones) -- and written out so that runs of one digit land on
 // consecutive addresses.
-template <typename K, int RB, int ITEMS, int THREADS>
+template <typename K, int RB, int ITEMS, int THREADS, int MODE>
 struct PassSmem {
   // keys, then values (as uint32; with 32-bit keys, values and second values
   // as pairs of uint32)
@@ -36,6 +43,9 @@ struct PassSmem {
   uint32_t wcnt[(THREADS / kWave) << RB];
   uint32_t dstart[1 << RB];
   uint32_t gofs[1 << RB];
+  // kPassUnpack: per digit, 1 + the largest tile part below the digit among
+  // the pairs of earlier workgroups (0: none)
+  uint32_t lbx[MODE == kPassUnpack ? (1 << RB) : 1];
   unsigned long long tmp[THREADS / kWave];
   uint32_t timeout;
   uint32_t drop;     // 32-bit keys: this pass drops culled Gaussians
@@ -45,10 +55,10 @@ struct PassSmem {
 // every one of the TILE slots holds a pair (all tiles but the last, unless
 // items are dropped), so no per-item bounds tests are needed.  `dropped`
 // (32-bit keys): culled items an earlier pass dropped, all of digit 255.
-template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
-__device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t base,
-                                          uint32_t n, uint32_t dropped, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
-                                          uint32_t (&dg)[ITEMS]) {
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
+__device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm,
+                                          uint32_t base, uint32_t n, uint32_t dropped, K (&k)[ITEMS],
+                                          uint32_t (&v)[ITEMS], uint32_t (&dg)[ITEMS]) {
   constexpr int BINS = 1 << RB;
   constexpr uint32_t DMASK = BINS - 1;
   const int tid = threadIdx.x;
@@ -77,7 +87,7 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
     const uint32_t idx = seg + j * kWave + lane;
     if (FULL || idx < n) {
       k[j] = kin[idx];
-      v[j] = a.vin[idx];
+      v[j] = MODE == kPassKV ? a.vin[idx] : 0u;
       dg[j] = static_cast<uint32_t>(k[j] >> a.shift) & DMASK;
     } else {
       k[j] = 0;
@@ -87,8 +97,20 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
   }
 }
 
-template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
-__device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
+// kPassUnpack: the pair at output position o is the first of its tile when
+// its predecessor's tile tp is smaller; then o starts tile t, ends tp, and
+// every tile between them is empty at o.
+__device__ __forceinline__ void range_boundary(uint32_t* __restrict__ ranges, int64_t tp, uint32_t t, uint32_t o) {
+  if (tp >= 0) ranges[2 * tp + 1] = o;
+  for (int64_t e = tp + 1; e < static_cast<int64_t>(t); ++e) {
+    ranges[2 * e] = o;
+    ranges[2 * e + 1] = o;
+  }
+  ranges[2 * static_cast<size_t>(t)] = o;
+}
+
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
+__device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm, uint32_t t,
                                           uint32_t base, uint32_t n, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
                                           uint32_t (&dg)[ITEMS]) {
   constexpr int WAVES = THREADS / kWave;
@@ -97,6 +119,13 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   constexpr int TILE = THREADS * ITEMS;
   const int tid = threadIdx.x;
   const uint32_t wave = tid / kWave;
+  // kPassUnpack: the depth field's form, read now (uniform scalar loads) and
+  // used only when writing
+  uint32_t top_max = 0, top_min = 0;
+  if constexpr (MODE == kPassUnpack) {
+    top_max = a.packed.depth_top[0];
+    top_min = a.packed.depth_top[1];
+  }
 
   // ---- stable rank inside the wave ----
   // peers = lanes whose digit equals this lane's: for every digit bit b,
@@ -143,7 +172,9 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       sm.wcnt[w * BINS + tid] = bcnt;
       bcnt += c;
     }
-    st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
+    // kPassUnpack publishes after the permute, with its largest tile part
+    if (MODE != kPassUnpack)
+      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
   }
   uint32_t gbase, lexcl;
   uint32_t tile_pairs = 0;  // 32-bit keys: valid items of the tile (some may be dropped)
@@ -183,6 +214,19 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       for (int j = 0; j < ITEMS; ++j) pl[j] = (FULL || dg[j] < BINS) ? a.pin[seg + j * kWave] : 0u;
     }
   }
+  // kPassUnpack: the digit's largest tile part in this workgroup is that of
+  // its last slot (the input is in order of the lower tile bits)
+  uint32_t own_max = 0;
+  if constexpr (MODE == kPassUnpack) {
+    __syncthreads();
+    if (tid < BINS && bcnt != 0) {
+      const uint32_t lowmask = a.low_bits >= 32 ? ~0u : (1u << a.low_bits) - 1u;
+      own_max = 1u + (static_cast<uint32_t>(sm.buf[lexcl + bcnt - 1] >> a.packed.tile_shift) & lowmask);
+    }
+    if (tid < BINS)
+      st_agent(&a.lookback64[static_cast<size_t>(t) * BINS + tid],
+               lb_word(t == 0 ? kLbIncW : kLbAggW, bcnt, own_max));
+  }
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
   if (tid < BINS) {
@@ -202,7 +246,13 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       gbase = w & ~kBasePublished;
     }
     uint32_t excl = 0;
-    if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl)) sm.timeout = 1;
+    if constexpr (MODE == kPassUnpack) {
+      uint32_t excl_max = 0;
+      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max)) sm.timeout = 1;
+      sm.lbx[tid] = excl != 0 ? excl_max : 0u;
+    } else {
+      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl)) sm.timeout = 1;
+    }
     sm.gofs[tid] = gbase + excl - lexcl;
   }
   __syncthreads();
@@ -215,6 +265,45 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   const uint32_t valid_n = FULL ? TILE
                            : sizeof(K) == 4 ? tile_pairs
                                             : ((n - base) < static_cast<uint32_t>(TILE) ? (n - base) : TILE);
+  if constexpr (MODE == kPassUnpack) {
+    // packed pair -> (tile << 32 | depth bits, index); tile ranges on the way
+    const uint32_t S = a.packed.tile_shift, ib = a.packed.idx_bits;
+    uint32_t ebase;
+    const bool trimmed = packed_depth_trimmed(top_max, top_min, a.packed, &ebase);
+    const uint64_t pmask = (1ull << S) - 1;
+    const uint32_t imask = ib >= 32 ? ~0u : (1u << ib) - 1u;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t i = j * THREADS + tid;
+      if (FULL || i < valid_n) {
+        const uint64_t item = sm.buf[i];
+        const uint32_t d = static_cast<uint32_t>(item >> a.shift) & DMASK;
+        const uint32_t o = sm.gofs[d] + i;
+        if (o < n) {
+          const uint32_t tile = static_cast<uint32_t>(item >> S);
+          const uint64_t payload = item & pmask;
+          const uint32_t hi = static_cast<uint32_t>(payload >> ib);
+          const uint32_t dbits = trimmed ? hi + ebase : a.packed.depth_sorted[hi];
+          kout[o] = (static_cast<uint64_t>(tile) << 32) | dbits;
+          a.vout[o] = static_cast<uint32_t>(payload) & imask;
+          // predecessor: the slot before, inside this digit's run; else the
+          // last pair of the digit in earlier workgroups; else (the digit's
+          // first pair overall) left to k_ranges_fix
+          int64_t tp = -1;
+          bool known = true;
+          if (i > sm.dstart[d]) {
+            tp = static_cast<int64_t>(sm.buf[i - 1] >> S);
+          } else {
+            const uint32_t lx = sm.lbx[d];
+            known = lx != 0;
+            tp = (static_cast<int64_t>(d) << a.low_bits) | static_cast<int64_t>(lx - 1u);
+          }
+          if (known && tp != static_cast<int64_t>(tile)) range_boundary(a.ranges, tp, tile, o);
+        }
+      }
+    }
+    return;
+  }
   uint32_t dst[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -229,6 +318,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       }
     }
   }
+  if constexpr (MODE == kPassItems) return;
   __syncthreads();
 
   // ---- values through the same buffer (with a second value: both as a
@@ -264,14 +354,14 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   }
 }
 
-template <typename K, int RB, int ITEMS, int THREADS, bool FULL>
-__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS>& sm, uint32_t t,
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm, uint32_t t,
                                           uint32_t base, uint32_t n, uint32_t dropped) {
   K k[ITEMS];
   uint32_t v[ITEMS];
   uint32_t dg[ITEMS];
-  pass_load<K, RB, ITEMS, THREADS, FULL>(a, sm, base, n, dropped, k, v, dg);
-  pass_rest<K, RB, ITEMS, THREADS, FULL>(a, sm, t, base, n, k, v, dg);
+  pass_load<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, base, n, dropped, k, v, dg);
+  pass_rest<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, t, base, n, k, v, dg);
 }
 
 // The extra workgroup of a chain's first 64-bit pass: digit bases of
@@ -294,13 +384,51 @@ __device__ __forceinline__ void publish_bases(const PassArgs& a, uint32_t* s_tmp
   }
 }
 
+// The depth sort's first pass, workgroup 0, after its tile: the largest and
+// smallest top byte of the depth keys of Gaussians with pairs (positive
+// depths have a top byte below 128; culled keys sit in bin 255).
+template <int THREADS>
+__device__ __forceinline__ void store_depth_top(const PassArgs& a, uint32_t* s2) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s2[0] = 0;
+    s2[1] = 0xFF;
+  }
+  __syncthreads();
+  if (threadIdx.x < 128) {
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kHistCopies; ++k) c += a.hist_top[static_cast<size_t>(k) * a.hist_stride + threadIdx.x];
+    if (c != 0) {
+      atomicMax(&s2[0], static_cast<uint32_t>(threadIdx.x));
+      atomicMin(&s2[1], static_cast<uint32_t>(threadIdx.x));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.depth_top_out[0] = s2[0];
+    a.depth_top_out[1] = s2[1] <= s2[0] ? s2[1] : 0u;
+  }
+}
+
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
+__device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm);
+
 // DROP (32-bit keys, the depth sort's first pass): may drop the culled
 // Gaussians (the decision is known only after the loads).
-template <typename K, int RB, int ITEMS, int THREADS, bool DROP>
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
 __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
-  constexpr int TILE = THREADS * ITEMS;
-  __shared__ PassSmem<K, RB, ITEMS, THREADS> sm;
+  __shared__ PassSmem<K, RB, ITEMS, THREADS, MODE> sm;
   if (a.status && *a.status != SS_OK) return;
+  onesweep_body<K, RB, ITEMS, THREADS, MODE, DROP>(a, sm);
+  if constexpr (sizeof(K) == 4) {
+    if (a.depth_top_out != nullptr && blockIdx.x == 0) store_depth_top<THREADS>(a, sm.dstart);
+  }
+}
+
+template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
+__device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm) {
+  constexpr int TILE = THREADS * ITEMS;
   const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
   const int tid = threadIdx.x;
   if (tid == 0) sm.timeout = 0;
@@ -324,16 +452,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   if constexpr (!DROP) {
     const uint32_t dropped = sizeof(K) == 4 && a.n_total != 0 ? a.n_total - n : 0u;
     if (n - base >= static_cast<uint32_t>(TILE))
-      pass_tile<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n, dropped);
+      pass_tile<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, dropped);
     else
-      pass_tile<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n, dropped);
+      pass_tile<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, dropped);
   } else {
     // the loads go out before the drop decision (one thread's reads of the
     // culled count), which only marks the culled as not pairs
     K k[ITEMS];
     uint32_t v[ITEMS];
     uint32_t dg[ITEMS];
-    pass_load<K, RB, ITEMS, THREADS, false>(a, sm, base, n, 0u, k, v, dg);
+    pass_load<K, RB, ITEMS, THREADS, MODE, false>(a, sm, base, n, 0u, k, v, dg);
     if (tid == 0) {
       // drop when the culled are more than n / 16 (the same decision in
       // every workgroup)
@@ -354,25 +482,54 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
     // the second variant fits the registers (up to 12 items per thread)
     if constexpr (ITEMS <= 12) {
       if (n - base >= static_cast<uint32_t>(TILE) && !sm.drop) {
-        pass_rest<K, RB, ITEMS, THREADS, true>(a, sm, t, base, n, k, v, dg);
+        pass_rest<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, k, v, dg);
         return;
       }
     }
-    pass_rest<K, RB, ITEMS, THREADS, false>(a, sm, t, base, n, k, v, dg);
+    pass_rest<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, k, v, dg);
   }
 }
 
-template <typename K, int RB, int ITEMS, int THREADS>
+template <typename K, int RB, int ITEMS, int THREADS, int MODE>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
   const uint32_t grid = nblocks + (sizeof(K) == 8 && a.publish_passes != 0 ? 1u : 0u);
   if constexpr (sizeof(K) == 4) {
     if (a.culled != nullptr) {
-      hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, true>), dim3(grid), dim3(THREADS), 0, s, a);
+      hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, MODE, true>), dim3(grid), dim3(THREADS), 0, s, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, false>), dim3(grid), dim3(THREADS), 0, s, a);
+  hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, MODE, false>), dim3(grid), dim3(THREADS), 0, s, a);
   return hipGetLastError();
+}
+
+// One workgroup: the boundary at each digit's first pair (its predecessor
+// lies in the previous non-empty digit's run) and the tiles after the last
+// pair; with no pairs every range is [0, 0).  `bins`: the digits of the last
+// pass's instantiation (every one of their bases is published).
+__global__ __launch_bounds__(256) void k_ranges_fix(const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ num_pairs,
+                                                    const uint32_t* __restrict__ status,
+                                                    const uint32_t* __restrict__ bases, uint32_t bins,
+                                                    uint32_t num_tiles, uint32_t* __restrict__ ranges) {
+  if (status && *status != SS_OK) return;
+  const uint32_t m = *num_pairs;
+  for (uint32_t d = threadIdx.x; d < bins; d += blockDim.x) {
+    const uint32_t o = bases[d] & ~kBasePublished;
+    const uint32_t next = d + 1 < bins ? bases[d + 1] & ~kBasePublished : m;
+    if (next > o && o < m) {
+      const int64_t tp = o == 0 ? -1 : static_cast<int64_t>(keys[o - 1] >> 32);
+      const uint32_t tile = static_cast<uint32_t>(keys[o] >> 32);
+      if (tp != static_cast<int64_t>(tile)) range_boundary(ranges, tp, tile, o);
+    }
+  }
+  // after the last pair (tile tl): tl ends at m, later tiles are [m, m)
+  const int64_t tl = m == 0 ? -1 : static_cast<int64_t>(keys[m - 1] >> 32);
+  if (threadIdx.x == 0 && tl >= 0) ranges[2 * tl + 1] = m;
+  for (int64_t e = tl + 1 + threadIdx.x; e < static_cast<int64_t>(num_tiles); e += blockDim.x) {
+    ranges[2 * e] = m;
+    ranges[2 * e + 1] = m;
+  }
 }
 
 }  // namespace
@@ -380,8 +537,12 @@ hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
 bool pass_config_supported(int radix_bits, int items, int threads) {
   const bool rb_ok = radix_bits == 4 || radix_bits == 6 || radix_bits == 8;
   const bool it_ok = items == 8 || items == 12 || items == 16;
-  const bool th_ok = threads == 256 || (threads == 512 && radix_bits == 8 && (items == 8 || items == 16));
+  const bool th_ok = threads == 256 || (threads == 512 && (items == 8 || items == 16));
   return rb_ok && it_ok && th_ok;
+}
+
+bool packed_pass_supported(int radix_bits, int items, int threads) {
+  return threads == 512 && (items == 8 || items == 16) && radix_bits >= 4 && radix_bits <= 8;
 }
 
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads) {
@@ -392,11 +553,11 @@ int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int thr
 }
 
 hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int items, int threads, uint32_t nblocks,
-                       hipStream_t s) {
+                       hipStream_t s, int mode) {
   if (nblocks == 0) return hipSuccess;
-#define SS_PASS_CASE(K, RB, IT, TH)                                                        \
-  if (key_bytes == sizeof(K) && radix_bits == RB && items == IT && threads == TH) \
-    return pass_launch<K, RB, IT, TH>(a, nblocks, s);
+#define SS_PASS_CASE(K, RB, IT, TH)                                                                        \
+  if (mode == kPassKV && key_bytes == sizeof(K) && radix_bits == RB && items == IT && threads == TH) \
+    return pass_launch<K, RB, IT, TH, kPassKV>(a, nblocks, s);
   SS_PASS_CASE(uint64_t, 8, 16, 256) SS_PASS_CASE(uint64_t, 8, 12, 256) SS_PASS_CASE(uint64_t, 8, 8, 256)
   SS_PASS_CASE(uint64_t, 6, 16, 256) SS_PASS_CASE(uint64_t, 6, 12, 256) SS_PASS_CASE(uint64_t, 6, 8, 256)
   SS_PASS_CASE(uint64_t, 4, 16, 256) SS_PASS_CASE(uint64_t, 4, 12, 256) SS_PASS_CASE(uint64_t, 4, 8, 256)
@@ -408,7 +569,25 @@ hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int ite
   // the Gaussian depth sort's shapes
   SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512)
 #undef SS_PASS_CASE
+  // packed pairs: 512-thread shapes, 4..8-bit digits
+#define SS_PACKED_CASE(RB, IT)                                                      \
+  if (key_bytes == 8 && radix_bits == RB && items == IT && threads == 512) {        \
+    if (mode == kPassItems) return pass_launch<uint64_t, RB, IT, 512, kPassItems>(a, nblocks, s);   \
+    if (mode == kPassUnpack) return pass_launch<uint64_t, RB, IT, 512, kPassUnpack>(a, nblocks, s); \
+  }
+  SS_PACKED_CASE(8, 16) SS_PACKED_CASE(8, 8) SS_PACKED_CASE(7, 16) SS_PACKED_CASE(7, 8)
+  SS_PACKED_CASE(6, 16) SS_PACKED_CASE(6, 8) SS_PACKED_CASE(5, 16) SS_PACKED_CASE(5, 8)
+  SS_PACKED_CASE(4, 16) SS_PACKED_CASE(4, 8)
+#undef SS_PACKED_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_ranges_fix(const uint64_t* keys, const uint32_t* num_pairs, const uint32_t* status,
+                             const uint32_t* bases, uint32_t bins, uint32_t num_tiles, uint32_t* ranges,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_ranges_fix, dim3(1), dim3(256), 0, s, keys, num_pairs, status, bases, bins, num_tiles,
+                     ranges);
+  return hipGetLastError();
 }
 
 }  // namespace ss

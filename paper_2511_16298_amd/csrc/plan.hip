@@ -29,7 +29,8 @@ struct Candidate {
 
 // Every pass configuration compiled into the library.
 const Candidate kCandidates[] = {
-    {8, 16, 512}, {8, 8, 512}, {8, 16, 256}, {8, 12, 256}, {8, 8, 256}, {6, 16, 256}, {4, 16, 256},
+    {8, 16, 512}, {8, 8, 512}, {6, 16, 512}, {6, 8, 512}, {4, 16, 512}, {8, 16, 256}, {8, 12, 256},
+    {8, 8, 256},  {6, 16, 256}, {4, 16, 256},
 };
 
 ss_options with(const ss_options& base, const Candidate& c) {

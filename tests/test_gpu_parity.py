@@ -340,3 +340,41 @@ def test_culled_gaussians_with_and_without_dropping(culled_fraction, n):
         assert np.array_equal(u64(s.out.keys)[:m], o.keys), drop
         assert np.array_equal(u32(s.out.values)[:m], o.values), drop
         assert np.array_equal(u32(s.out.tile_ranges).reshape(-1, 2), o.ranges), drop
+
+
+def depth_field_mode(tile_bits, n, depths):
+    """Which depth field the packed 64-bit pairs carry for a single frame:
+    'trimmed' (depth bits minus the smallest top byte << 24, when every
+    depth that has pairs then fits the field), 'position' (the depth-order
+    position, when they do not), or None (pairs not packed)."""
+    idx_bits = int(np.ceil(np.log2(max(n, 1)))) if n > 1 else 0
+    field = 64 - tile_bits - idx_bits
+    if tile_bits == 0 or field < 27 or int(np.ceil(np.log2(max(n, 1)))) > field:
+        return None
+    top = np.asarray(depths, np.float32).view(np.uint32) >> 24
+    span = int(top.max()) - int(top.min()) + 1
+    return "trimmed" if field >= 32 or (span << 24) <= (1 << field) else "position"
+
+
+# frames whose pairs travel packed, with depth ranges on both sides of the
+# trimmed field's width: (tiles_x, tiles_y, N, depth_lo, depth_hi, expected field)
+PACKED_CASES = [(256, 256, 1 << 21, 1.0, 100.0, "trimmed"),
+                (256, 256, 1 << 21, 1e-3, 1e3, "position"),
+                (120, 68, 5_000_000, 1e-4, 1e4, "trimmed"),
+                (120, 68, 5_000_000, 1e-6, 1e6, "position")]
+
+
+@pytest.mark.parametrize("case", PACKED_CASES, ids=lambda c: f"{c[0]}x{c[1]}-n{c[2]}-{c[5]}")
+def test_packed_pairs_both_depth_fields(case):
+    """Pairs carried through the tile passes as one 64-bit item: with the
+    trimmed depth field, and with the depth-order position when the depths
+    span more binades than the field holds (the last pass then reads each
+    depth back); bit-exact against the oracle either way."""
+    tx, ty, n, lo, hi, mode = case
+    W, H = 16 * tx, 16 * ty
+    rec = synth.make_frame(synth.FrameSpec(W, H, n, depth_lo=lo, depth_hi=hi), 7100 + tx)
+    cnt, _ = oracle.count(W, H, rec)
+    tile_bits = int(np.ceil(np.log2(tx * ty)))
+    assert depth_field_mode(tile_bits, n, rec["depth"][cnt > 0]) == mode
+    print(f"packed case {tx}x{ty} N={n} depth [{lo}, {hi}] -> {mode}", flush=True)
+    assert_same(W, H, rec, gpu_frame(W, H, rec, stages=False), stages=False)

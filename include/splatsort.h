@@ -185,6 +185,22 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out,
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
 
+/* ss_sort_frame without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a library-owned array
+ * of SS_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, held until the
+ * process ends; the call allocates nothing (device or host).  Frames whose
+ * ss_workspace_bytes exceeds it return SS_ERR_WORKSPACE before anything is
+ * enqueued (the full-HD frame of 10^6 Gaussians fits).  Depth-first path
+ * only: other algorithms, SS_FLAG_UNSORTED and SS_FLAG_KEY32_LOSSY are
+ * SS_ERR_UNSUPPORTED.  The array serves the GPU that `stream` belongs to;
+ * every call on that GPU shares it, so calls that overlap on one GPU race
+ * (order them on one stream).  Outputs, errors and results are those of
+ * ss_sort_frame. */
+#define SS_NOALLOC_SCRATCH_BYTES (128u << 20)
+ss_status ss_sort_frame_noalloc(const ss_frame* frame, const ss_frame_out* out, void* stream,
+                                const ss_options* options);
+
 /* Many frames in one segmented sort (up to SS_MAX_BATCH_FRAMES).  Frame f's
  * tiles are renumbered tile_base[f] + t, tile_base the exclusive prefix sum
  * of the frames' tile counts; keys hold global tile ids, values frame-local

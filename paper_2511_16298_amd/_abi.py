@@ -48,6 +48,7 @@ SS_FLAG_DROP_CULLED = 4
 
 SS_MAX_IMAGE_PX = 1048560
 SS_MAX_PAIR_CAPACITY = (1 << 30) - 1
+SS_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class ss_frame(ctypes.Structure):
@@ -157,6 +158,8 @@ _SIGNATURES = {
     "ss_count_pairs": ([ctypes.POINTER(ss_frame), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "ss_sort_frame": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_frame_out), _P, _SZ, _P,
                        ctypes.POINTER(ss_options)], ctypes.c_int),
+    "ss_sort_frame_noalloc": ([ctypes.POINTER(ss_frame), ctypes.POINTER(ss_frame_out), _P,
+                               ctypes.POINTER(ss_options)], ctypes.c_int),
     "ss_batch_workspace_bytes": ([ctypes.POINTER(ss_frame), _U32, _U32, ctypes.POINTER(ss_options),
                                   ctypes.POINTER(_SZ)], ctypes.c_int),
     "ss_sort_batch": ([ctypes.POINTER(ss_frame), _U32, ctypes.POINTER(ss_batch_out), _P, _SZ, _P,
@@ -252,6 +255,11 @@ def ss_count_pairs(frame: ss_frame, d_tiles_touched, d_offsets, d_num_pairs, d_s
 def ss_sort_frame(frame: ss_frame, out: ss_frame_out, workspace, workspace_bytes, stream, options=None):
     return lib().ss_sort_frame(ctypes.byref(frame), ctypes.byref(out), workspace, workspace_bytes, stream,
                                ctypes.byref(options) if options is not None else None)
+
+
+def ss_sort_frame_noalloc(frame: ss_frame, out: ss_frame_out, stream, options=None):
+    return lib().ss_sort_frame_noalloc(ctypes.byref(frame), ctypes.byref(out), stream,
+                                       ctypes.byref(options) if options is not None else None)
 
 
 def _frames_array(frames):

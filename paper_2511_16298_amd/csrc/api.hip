@@ -633,10 +633,11 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
   if (P > 0) {
     uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
-    std::vector<const void*> ks(P);
-    std::vector<const uint32_t*> vs(P);
-    std::vector<void*> kd(P);
-    std::vector<uint32_t*> vd(P);
+    // fixed arrays: the frame path allocates nothing on the host either
+    const void* ks[kMaxTilePasses];
+    const uint32_t* vs[kMaxTilePasses];
+    void* kd[kMaxTilePasses];
+    uint32_t* vd[kMaxTilePasses];
     for (uint32_t p = 0; p < P; ++p) {
       ks[p] = bk[p % 2];
       vs[p] = bv[p % 2];
@@ -650,8 +651,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       }
     }
     uint32_t* lb_t = at<uint32_t>(ws, lay.lb_t);
-    PassChain c{P, 8, lay.packed ? pk.tile_shift : 32u, lay.trb, lay.tcfg, lay.tblocks, ks.data(), vs.data(),
-                kd.data(), vd.data(), d_num_pairs, 0, d_status, bases_t, e.hist, P * lay.tbins, lb_t,
+    PassChain c{P, 8, lay.packed ? pk.tile_shift : 32u, lay.trb, lay.tcfg, lay.tblocks, ks, vs,
+                kd, vd, d_num_pairs, 0, d_status, bases_t, e.hist, P * lay.tbins, lb_t,
                 lay.tile_bits - lay.trb * (P - 1)};
     if (lay.packed) {
       c.packed = &pk;

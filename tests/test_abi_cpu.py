@@ -101,7 +101,7 @@ def test_sort_frame_argument_errors_are_synchronous():
     assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
     # options
     for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 8, 0), (0, 0, 0, 128),
-                           (6, 0, 0, 512), (0, 12, 0, 512)]:
+                           (6, 12, 0, 512), (0, 12, 0, 512), (0, 0, 0, 1024)]:
         opt = _abi.make_options(rb, it, flags=fl, workgroup_size=wg)
         assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, opt) == _abi.SS_ERR_UNSUPPORTED
     bad = _abi.make_options()
@@ -290,3 +290,21 @@ def test_key32_option_rules():
     a, b, c, d = 1 << 20, 2 << 20, 3 << 20, 4 << 20
     assert _abi.ss_sort_pairs(a, b, 1000, 45, c, d, 8 << 20, need_p, None, opt) == _abi.SS_ERR_UNSUPPORTED
 
+
+
+def test_noalloc_rejects_before_enqueueing():
+    """The no-allocation entry point returns its argument errors before any
+    GPU work: a workspace beyond its fixed array, an unsupported algorithm,
+    missing outputs."""
+    o = fake_out(cap=_abi.SS_MAX_PAIR_CAPACITY)
+    big = frame(1920, 1080, 50_000_000, ptr=256)
+    st, need = _abi.ss_workspace_bytes(big, o.pair_capacity, None)
+    assert st == 0 and need > _abi.SS_NOALLOC_SCRATCH_BYTES
+    assert _abi.ss_sort_frame_noalloc(big, o, None) == _abi.SS_ERR_WORKSPACE
+    small = frame(256, 256, 1000, ptr=256)
+    o2 = fake_out(cap=10_000)
+    for algo in (_abi.SS_ALGO_DIRECT, _abi.SS_ALGO_BITONIC):
+        assert _abi.ss_sort_frame_noalloc(small, o2, None, _abi.make_options(algorithm=algo)) == \
+            _abi.SS_ERR_UNSUPPORTED
+    assert _abi.ss_sort_frame_noalloc(small, o2, None, _abi.make_options(flags=_abi.SS_FLAG_UNSORTED)) == \
+        _abi.SS_ERR_UNSUPPORTED

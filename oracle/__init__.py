@@ -21,7 +21,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# SS_ORACLE_LIB selects another build of the same source (the sanitizer
+# run of the pins builds one with -fsanitize=address,undefined)
+LIB_PATH = os.environ.get("SS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.cpp")
 
 OK, ERR_INVALID_ARGUMENT, ERR_CAPACITY, ERR_OVERFLOW, ERR_INVALID_INPUT = 0, 1, 3, 4, 5

@@ -19,65 +19,19 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "splatsort.h"
 
 namespace {
 
-constexpr size_t kArenaAlign = 256;
-size_t round_up(size_t x) { return (x + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+using ss::Arena;
+using ss::kArenaAlign;
+size_t round_up(size_t x) { return ss::arena_round_up(x); }
 
 double now_us() {
   using namespace std::chrono;
   return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator over [0, size) with coalescing of freed neighbours.
-class Arena {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-    size_ = size;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = round_up(bytes ? bytes : kArenaAlign);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t at = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        used_ += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = round_up(bytes ? bytes : kArenaAlign);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
-    }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t size() const { return size_; }
-  size_t used() const { return used_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t size_ = 0, used_ = 0;
-};
 
 struct Round;
 
@@ -298,38 +252,36 @@ void worker_loop(ss_server* s) {
       std::vector<Request*> take;
       size_t ws_b = 0, out_b = 0, ws_off = 0, out_off = 0;
       uint32_t cap = 0, tiles = 0;
-      bool got = false;
       for (Request* r : s->pending) {
         if (take.size() >= s->desc.max_batch_frames || r->pairs < 0) break;
         take.push_back(r);
       }
-      while (!take.empty()) {
-        ss_status bst;
-        round_bytes(take, s->desc, &ws_b, &out_b, &cap, &tiles, &bst);
-        if (bst == SS_OK && s->arena.alloc(ws_b, &ws_off)) {
-          if (s->arena.alloc(out_b, &out_off)) {
-            got = true;
-            break;
-          }
-          s->arena.release(ws_off, ws_b);
-        }
-        if (take.size() == 1) {
+      bool never_fits = false;
+      const uint32_t k = ss::admit_prefix(
+          s->arena, static_cast<uint32_t>(take.size()),
+          [&](uint32_t n, size_t* ws, size_t* out) {
+            std::vector<Request*> prefix(take.begin(), take.begin() + n);
+            ss_status bst;
+            round_bytes(prefix, s->desc, ws, out, &cap, &tiles, &bst);
+            return bst == SS_OK;
+          },
+          &ws_off, &ws_b, &out_off, &out_b, &never_fits);
+      const bool got = k > 0;
+      if (got) {
+        take.resize(k);  // cap and tiles are those of this prefix (the last one sized)
+      } else {
+        if (!take.empty() && never_fits) {
           // alone in an empty arena it could never fit: reject
-          size_t need = round_up(ws_b) + round_up(out_b);
-          if (bst != SS_OK || need > s->arena.size()) {
-            Request* r = take[0];
-            r->status = SS_ERR_BUDGET;
-            r->done = true;
-            r->done_us = now_us();
-            ++s->rejected;
-            ++s->completed;
-            s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
-            s->cv_done.notify_all();
-          }
-          take.clear();
-          break;
+          Request* r = take[0];
+          r->status = SS_ERR_BUDGET;
+          r->done = true;
+          r->done_us = now_us();
+          ++s->rejected;
+          ++s->completed;
+          s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+          s->cv_done.notify_all();
         }
-        take.pop_back();
+        take.clear();
       }
       if (got) {
         auto rd = std::make_shared<Round>();

@@ -225,21 +225,27 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_
 // written in rounds of 4096: an owner map marks, for every Gaussian starting
 // inside the round, its first slot; a max-scan spreads the owners over the
 // round; thread t writes slots t, t + 512, ... (coalesced).
+// LDS: about 51 KB of fixed arrays (three workgroups per CU), plus the frame
+// table and the tile-digit histograms sized by the launch (expand_dyn_lds).
+// Workgroup 0 finishes the pair totals in the owner map's space, before its
+// first expansion round.
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
-  __shared__ FrameInfo s_tab[kMaxFrames];
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  FrameInfo* s_tab = reinterpret_cast<FrameInfo*>(s_dyn);                            // [n_frames]
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_dyn + a.n_frames * sizeof(FrameInfo));  // [npasses << radix_bits]
   __shared__ uint32_t s_off[kExpandTile];
   __shared__ uint32_t s_org[kExpandTile];   // global tile of (x0, y0)
   __shared__ uint32_t s_wt[kExpandTile];    // w | tiles_x << 16
   __shared__ uint32_t s_dep[kExpandTile];
   __shared__ uint32_t s_loc[kExpandTile];
-  __shared__ uint16_t s_map[kChunk];
+  __shared__ __align__(16) uint16_t s_map[kChunk];
   __shared__ uint32_t s_incl[kExpandThreads];
-  __shared__ uint32_t s_hist[8 * 256];   // tile digits: up to 32 bits at 4 bits per pass
   __shared__ unsigned long long s_tmp64[kExpandThreads / kWave];
   __shared__ uint32_t s_tmp[kExpandThreads / kWave];
   __shared__ uint32_t s_first, s_retry, s_timeout;
   __shared__ unsigned long long s_prefix;
-  __shared__ unsigned long long s_fm[kMaxFrames];
+  static_assert(kChunk * sizeof(uint16_t) >= kMaxFrames * sizeof(unsigned long long), "totals in the map");
+  unsigned long long* s_fm = reinterpret_cast<unsigned long long*>(s_map);
 
   // No status test on entry: workgroup 0 sets the status from the totals
   // while the others run, and every workgroup must publish its look-back
@@ -455,7 +461,8 @@ hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s) {
 
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
   if (a.nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3(a.nblocks), dim3(kExpandThreads), 0, s, a);
+  const size_t dyn = a.n_frames * sizeof(FrameInfo) + (static_cast<size_t>(a.npasses) << a.radix_bits) * 4;
+  hipLaunchKernelGGL(k_expand, dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
   return hipGetLastError();
 }
 

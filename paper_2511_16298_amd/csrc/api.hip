@@ -681,6 +681,55 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   });
 }
 
+// ----------------------------- small frames --------------------------------
+// At most 256 tiles and 16,384 Gaussians, one frame, without the optional
+// per-Gaussian outputs: two kernels (tiny.hip).  Workspace: per-tile count
+// rows of the bucketing workgroups, then their pair regions.
+struct TinyLayout {
+  uint32_t nblocks = 0, region_cap = 0;
+  size_t rows = 0, region = 0, total = 0;
+};
+
+bool tiny_shape(uint32_t n, uint32_t num_tiles, const Options& o) {
+  return (o.algorithm == SS_ALGO_AUTO || o.algorithm == SS_ALGO_DEPTH_FIRST) &&
+         (o.flags & (SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY)) == 0 && num_tiles <= kTinyMaxTiles &&
+         n <= kTinyMaxGaussians;
+}
+
+TinyLayout make_tiny_layout(uint32_t n, uint32_t num_tiles, uint32_t capacity) {
+  TinyLayout L;
+  L.nblocks = (n + kTinyGaussians - 1) / kTinyGaussians;
+  const uint64_t most = static_cast<uint64_t>(kTinyGaussians) * num_tiles;
+  L.region_cap = static_cast<uint32_t>(most < capacity ? most : capacity);
+  size_t off = 0;
+  L.rows = off;    off = align_up(off + static_cast<size_t>(L.nblocks) * (2 * num_tiles + 1) * sizeof(uint32_t));
+  L.region = off;  off = align_up(off + static_cast<size_t>(L.nblocks) * L.region_cap * sizeof(uint64_t));
+  L.total = off;
+  return L;
+}
+
+ss_status run_tiny(Launcher& L, const ss_frame* frame, const Geometry& g, const ss_frame_out* out, void* ws,
+                   hipStream_t s) {
+  const TinyLayout lay = make_tiny_layout(frame->num_gaussians, g.num_tiles, out->pair_capacity);
+  TinyArgs a{};
+  a.gaussians = frame->gaussians;
+  a.n = frame->num_gaussians;
+  a.tiles_x = g.tiles_x;
+  a.tiles_y = g.tiles_y;
+  a.nblocks = lay.nblocks;
+  a.region = at<uint64_t>(ws, lay.region);
+  a.region_cap = lay.region_cap;
+  a.rows = at<uint32_t>(ws, lay.rows);
+  a.capacity = out->pair_capacity;
+  a.keys = out->keys;
+  a.values = out->values;
+  a.ranges = out->tile_ranges;
+  a.num_pairs = out->num_pairs;  // both set by the caller
+  a.status = out->status;
+  SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_tiny(a, s, true); }));
+  return L.run(SS_KERNEL_SORT_PASS, [&] { return launch_tiny(a, s, false); });
+}
+
 // Duplication in index order: the direct radix path, the bitonic network and
 // the unsorted stage.
 bool use_direct(const Options& o) {
@@ -833,9 +882,16 @@ ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity, cons
   Options o;
   SS_TRY(parse_options(options, &o));
   if (pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
-  const size_t sort = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
-                                    : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o,
-                                                     frame->num_gaussians).total;
+  size_t sort = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
+                              : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o,
+                                               frame->num_gaussians).total;
+  // small frames take the two-kernel path unless per-Gaussian outputs are
+  // asked for, so both layouts must fit (the extra 8 words hold the status
+  // when the caller gives none)
+  if (tiny_shape(frame->num_gaussians, g.num_tiles, o)) {
+    const size_t tiny = make_tiny_layout(frame->num_gaussians, g.num_tiles, pair_capacity).total + 256;
+    sort = sort > tiny ? sort : tiny;
+  }
   // ss_count_pairs runs in any workspace sized here (its own layout can be
   // the larger one, e.g. for N = 0)
   const size_t count = make_layout(frame->num_gaussians, 0, g.key_bits, Options{}).total;
@@ -890,6 +946,13 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);
   if (use_direct(o)) return run_direct(L, frame, g, out, o, workspace, s);
+  if (tiny_shape(frame->num_gaussians, g.num_tiles, o) && out->tiles_touched == nullptr && out->offsets == nullptr) {
+    // status and pair count: the caller's words, else the workspace's last 256 bytes
+    ss_frame_out o2 = *out;
+    if (o2.status == nullptr) o2.status = at<uint32_t>(workspace, need - 256);
+    if (o2.num_pairs == nullptr) o2.num_pairs = at<uint32_t>(workspace, need - 256) + 1;
+    return run_tiny(L, frame, g, &o2, workspace, s);
+  }
   const FrameInfo fi = frame_info(frame, g, 0, 0);
   const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o, frame->num_gaussians);
   DfIO io{&fi, frame, out->keys, out->values, out->tile_ranges, out->tiles_touched, out->offsets,

@@ -230,6 +230,31 @@ hipError_t launch_ranges_fix(const uint64_t* keys, const uint32_t* num_pairs, co
 // its digit has only `bits` significant bits, or 0 (use radix_bits).
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads);
 
+// Small frames in two kernels (see tiny.hip): at most kTinyMaxTiles tiles
+// and kTinyMaxGaussians Gaussians, one frame.
+constexpr uint32_t kTinyGaussians = 512;       // Gaussians per bucketing workgroup
+constexpr uint32_t kTinyMaxGaussians = 16384;
+constexpr uint32_t kTinyMaxBlocks = kTinyMaxGaussians / kTinyGaussians;
+constexpr uint32_t kTinyMaxTiles = 256;
+struct TinyArgs {
+  const ss_gaussian2d* gaussians;
+  uint32_t n;
+  uint32_t tiles_x, tiles_y;
+  uint32_t nblocks;         // ceil(n / kTinyGaussians)
+  uint64_t* region;         // [nblocks][region_cap] pairs grouped by tile per workgroup
+  uint32_t region_cap;      // min(kTinyGaussians * tiles, capacity): a workgroup's most pairs
+  uint32_t* rows;           // [nblocks][2 tiles + 1]: per-tile counts, their exclusive
+                            // prefix, a bad-depth flag
+  uint32_t capacity;
+  uint64_t* keys;
+  uint32_t* values;
+  uint32_t* ranges;
+  uint32_t* num_pairs;
+  uint32_t* status;
+};
+// bucket = true: kernel 1 (skipped for no Gaussians); false: kernel 2.
+hipError_t launch_tiny(const TinyArgs& a, hipStream_t s, bool bucket);
+
 // Render (see render.hip).
 struct RenderArgs {
   const ss_gaussian2d* gaussians;

@@ -378,3 +378,70 @@ def test_packed_pairs_both_depth_fields(case):
     assert depth_field_mode(tile_bits, n, rec["depth"][cnt > 0]) == mode
     print(f"packed case {tx}x{ty} N={n} depth [{lo}, {hi}] -> {mode}", flush=True)
     assert_same(W, H, rec, gpu_frame(W, H, rec, stages=False), stages=False)
+
+
+def tiny_path_frames():
+    """Frames the two-kernel small-frame path takes (at most 256 tiles and
+    16,384 Gaussians, no per-Gaussian outputs asked for), with its edges."""
+    rs = np.random.default_rng(77)
+    cases = []
+    for i in range(80):
+        W, H, rec = pins.random_tiny_frame(rs)
+        cases.append((f"tiny{i}", W, H, rec))
+    spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
+    cases.append(("small-256x256", spec.width, spec.height, synth.make_frame(spec, seed)))
+    cases.append(("max-n", 256, 256, synth.make_frame(synth.scaled(synth.SMALL, 16_384), 11)))
+    cases.append(("one-over-max-n", 256, 256, synth.make_frame(synth.scaled(synth.SMALL, 16_385), 12)))
+    cases.append(("row", 4096, 16, synth.make_frame(synth.FrameSpec(4096, 16, 5000), 13)))
+    cases.append(("column", 16, 4096, synth.make_frame(synth.FrameSpec(16, 4096, 5000), 14)))
+    cases.append(("one-tile", 16, 9, synth.make_frame(synth.FrameSpec(16, 9, 16_384), 15)))
+    cover = synth.make_frame(synth.FrameSpec(250, 250, 3000), 16)   # 3000 pairs in every tile
+    cover["radius"] = 5000
+    cases.append(("cover", 250, 250, cover))
+    ties = cover.copy()
+    ties["depth"] = np.float32(1.5)
+    cases.append(("cover-ties", 250, 250, ties))
+    one = blank(16_384)                                            # 16,384 pairs in one tile
+    one["mean_x"], one["mean_y"], one["radius"] = 16 * 40 + 8, 16 * 100 + 8, 1
+    one["depth"] = np.random.default_rng(3).choice(np.float32([1.0, 2.0, 3.0]), 16_384)
+    cases.append(("one-tile-full", 256, 256, one))
+    culled = synth.make_frame(synth.scaled(synth.SMALL, 4000), 17)
+    culled["radius"] = 0
+    cases.append(("all-culled", 256, 256, culled))
+    cases.append(("empty", 100, 70, blank(0)))
+    return cases
+
+
+def test_small_frame_path():
+    for name, W, H, rec in tiny_path_frames():
+        print(f"small-frame path: {name} {W}x{H} N={len(rec)}", flush=True)
+        cap = None if len(rec) else 0
+        assert_same(W, H, rec, gpu_frame(W, H, rec, capacity=cap, stages=False), stages=False)
+
+
+def test_small_frame_path_errors_and_reuse():
+    spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
+    rec = synth.make_frame(spec, seed)
+    o = oracle.sort_frame(spec.width, spec.height, rec, stages=False)
+    g = gpu_frame(256, 256, rec, capacity=o.num_pairs - 1, stages=False)
+    assert g["status"] == _abi.SS_ERR_CAPACITY and g["M"] == o.num_pairs
+    g = gpu_frame(256, 256, rec, capacity=100, stages=False)
+    assert g["status"] == _abi.SS_ERR_CAPACITY and g["M"] == o.num_pairs
+    for bad in (np.nan, -1.0, np.inf, 0.0):
+        r2 = rec.copy()
+        r2["depth"][4321] = bad
+        assert gpu_frame(256, 256, r2, capacity=o.num_pairs, stages=False)["status"] == _abi.SS_ERR_INVALID_INPUT
+    r2 = rec.copy()
+    r2["depth"][4321], r2["radius"][4321] = np.nan, 0
+    assert_same(256, 256, r2, gpu_frame(256, 256, r2, capacity=o.num_pairs, stages=False), stages=False)
+    # the same buffers: an error, then a good frame
+    d = ss.records_to_device(rec)
+    sorter = ss.FrameSorter(256, 256, len(rec), o.num_pairs)
+    bad = rec.copy()
+    bad["depth"][9] = np.nan
+    assert sorter(ss.records_to_device(bad)).result()[0] == _abi.SS_ERR_INVALID_INPUT
+    out = sorter(d)
+    assert out.result() == (0, o.num_pairs)
+    assert np.array_equal(u64(out.keys)[:o.num_pairs], o.keys)
+    assert np.array_equal(u32(out.values)[:o.num_pairs], o.values)
+    assert np.array_equal(u32(out.tile_ranges).reshape(-1, 2), o.ranges)

@@ -158,12 +158,17 @@ struct DfLayout {
   // bits) | depth field << idx_bits | index
   bool packed = false;
   uint32_t idx_bits = 0;
+  // Segmented batch (several frames): after the depth sort a stable pass by
+  // frame makes the Gaussians frame-major, so each frame's pairs come out
+  // contiguous and the tile passes sort every frame on its own, on
+  // frame-local tile ids (tile_bits then counts the largest frame's tiles).
+  bool seg = false;
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
   size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
          lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
-         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, total = 0;
+         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, total = 0;
 };
 
 // Pairs travel through the tile passes as one 64-bit item when the tile id,
@@ -180,22 +185,27 @@ bool use_packed(uint32_t tile_bits, uint32_t tpasses, uint32_t idx_bits, uint32_
   return idx_bits < 32 && depth_field >= 27 && ceil_log2(n) <= depth_field;
 }
 
+// Tile passes for `bits` tile bits.  With 8-bit digits in 512-thread passes,
+// several passes split the bits evenly (13 bits: 7 + 6 instead of 8 + 5): the
+// widest pass has fewer digits, so its runs of one digit, and its writes, are
+// longer.
+void plan_tile_passes(DfLayout& L, uint32_t bits, const Options& o) {
+  L.tile_bits = bits;
+  L.tpasses = (bits + o.radix_bits - 1) / o.radix_bits;
+  L.trb = o.radix_bits;
+  if (L.tpasses >= 2 && o.radix_bits == 8 && o.threads == 512 && (o.items == 8 || o.items == 16))
+    L.trb = (bits + L.tpasses - 1) / L.tpasses;
+  L.tbins = 1u << L.trb;
+}
+
 DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64_t total_tiles, const Options& o,
-                        uint32_t max_frame_n) {
+                        uint32_t max_frame_n, uint64_t max_frame_tiles) {
   DfLayout L;
   L.n = n;
   L.n_frames = n_frames;
   L.capacity = capacity;
   L.total_tiles = static_cast<uint32_t>(total_tiles);
-  L.tile_bits = ceil_log2(total_tiles);
-  L.tpasses = (L.tile_bits + o.radix_bits - 1) / o.radix_bits;
-  // With 8-bit digits in 512-thread passes, several tile passes split the tile
-  // bits evenly (13 bits: 7 + 6 instead of 8 + 5): the widest pass has fewer
-  // digits, so its runs of one digit, and its writes, are longer.
-  L.trb = o.radix_bits;
-  if (L.tpasses >= 2 && o.radix_bits == 8 && o.threads == 512 && (o.items == 8 || o.items == 16))
-    L.trb = (L.tile_bits + L.tpasses - 1) / L.tpasses;
-  L.tbins = 1u << L.trb;
+  plan_tile_passes(L, ceil_log2(total_tiles), o);
   L.dcfg = depth_cfg(n);
   L.tcfg = PassCfg{o.items, o.threads};
   // default shape, fewer than 2^23 pairs: 4,096-pair tiles (twice the
@@ -203,9 +213,27 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   // to the full-HD frame, slower from the 27.6M-pair frame on)
   if (o.items_default && o.threads == 512 && o.items == 16 && capacity < (1u << 23)) L.tcfg.items = 8;
   L.dblocks = (n + L.dcfg.tile() - 1) / L.dcfg.tile();
-  L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile();
   L.idx_bits = ceil_log2(max_frame_n);
   L.packed = use_packed(L.tile_bits, L.tpasses, L.idx_bits, n, L.tcfg, L.trb);
+  // Segmented batch: frame-local tiles (at most 2^16 per frame, as the
+  // expansion's 16-bit tile field holds) in packed pairs, without dropping
+  // culled Gaussians (the frame pass places frame f at its first Gaussian)
+  if (n_frames > 1 && (o.flags & SS_FLAG_DROP_CULLED) == 0) {
+    const uint32_t lbits = ceil_log2(max_frame_tiles);
+    if (lbits >= 1 && lbits <= 16) {
+      const DfLayout whole = L;
+      plan_tile_passes(L, lbits, o);
+      if (use_packed(L.tile_bits, L.tpasses, L.idx_bits, n, L.tcfg, L.trb)) {
+        L.seg = true;
+        L.packed = true;
+      } else {
+        L = whole;
+      }
+    }
+  }
+  // a segmented pass has up to one partial workgroup per frame
+  L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile() + (L.seg ? n_frames : 0u);
+  const uint32_t hframes = L.seg ? n_frames : 1u;  // tile histograms and bases per frame
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
   L.count_blocks = n == 0 ? 1u : (n + kCountTile - 1) / kCountTile;
   size_t off = 0;
@@ -219,13 +247,18 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.scan_lb = off;   off = align_up(off + static_cast<size_t>(L.count_blocks) * sizeof(uint64_t));
   L.expand_lb = off; off = align_up(off + static_cast<size_t>(L.eblocks) * sizeof(uint64_t));
   L.hist_d = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * 4 * 256 * sizeof(uint32_t));
-  L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * L.tpasses * L.tbins * sizeof(uint32_t));
-  L.lb_d = off;      off = align_up(off + static_cast<size_t>(4) * L.dblocks * 256 * sizeof(uint32_t));
+  L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * hframes * L.tpasses * L.tbins *
+                                            sizeof(uint32_t));
+  // four depth passes, and the frame pass when segmented
+  L.lb_d = off;      off = align_up(off + static_cast<size_t>(L.seg ? 5 : 4) * L.dblocks * 256 * sizeof(uint32_t));
   // packed: the last tile pass's look-back words are 64-bit (one more slice)
   L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses + (L.packed ? 1 : 0)) * L.tblocks * L.tbins *
                                             sizeof(uint32_t));
-  L.bases_t = off;   off = align_up(off + static_cast<size_t>(L.tpasses) * L.tbins * sizeof(uint32_t));
+  L.bases_t = off;   off = align_up(off + static_cast<size_t>(hframes) * L.tpasses * L.tbins * sizeof(uint32_t));
   L.clear_end = off;
+  // written whole by the expansion's totals
+  L.seg_base = off;  off = align_up(off + (L.seg ? n_frames + 1u : 0u) * sizeof(uint32_t));
+  L.seg_wgs = off;   off = align_up(off + (L.seg ? n_frames + 1u : 0u) * sizeof(uint32_t));
   L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
   L.rect = off;      off = align_up(off + static_cast<size_t>(n) * sizeof(uint64_t));
   L.key = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
@@ -328,6 +361,15 @@ struct PassChain {
   // keys with pairs (for packed pairs) at depth_top_out, from hist_top
   uint32_t* depth_top_out;
   const uint32_t* hist_top;
+  // the depth sort's frame pass (32-bit keys): digit = frame of the value
+  bool frame_digit;
+  const FrameInfo* table;     // frame pass, and the segmented unpacking pass
+  uint32_t n_frames;
+  // segmented 64-bit passes (PassArgs): per-frame workgroups, pairs, and
+  // histograms and bases frame_stride apart
+  const uint32_t* seg_wgs;
+  const uint32_t* seg_base;
+  uint32_t frame_stride;
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -364,6 +406,15 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       if (p == 0 && c.depth_top_out != nullptr) {
         a.depth_top_out = c.depth_top_out;
         a.hist_top = c.hist_top;
+      }
+      a.frame_digit = c.frame_digit;
+      a.table = c.table;
+      a.n_frames = c.n_frames;
+      if (c.seg_wgs != nullptr) {
+        a.seg_wgs = c.seg_wgs;
+        a.seg_base = c.seg_base;
+        a.seg_frames = c.n_frames;
+        a.bases_frame_stride = c.frame_stride;
       }
       int mode = kPassKV;
       if (c.packed != nullptr) {
@@ -586,6 +637,27 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     }
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
+  // segmented: a stable pass by frame, key -> alt (each frame's Gaussians
+  // stay in depth order, culled last, at the frame's first Gaussian)
+  if (lay.seg) {
+    const void* ks[1] = {key};
+    const uint32_t* vs[1] = {val};
+    void* kd[1] = {key_alt};
+    uint32_t* vd[1] = {val_alt};
+    const uint32_t* ps[1] = {rect32};
+    uint32_t* pd[1] = {rect32_alt};
+    PassChain c{1, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
+                nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d) + static_cast<size_t>(4) * lay.dblocks * 256,
+                0, nullptr, nullptr, pack ? ps : nullptr, pack ? pd : nullptr};
+    c.frame_digit = true;
+    c.table = table;
+    c.n_frames = lay.n_frames;
+    SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
+  }
+  // the Gaussians in (frame-major when segmented) depth order
+  const uint32_t* skey = lay.seg ? key_alt : key;
+  const uint32_t* sval = lay.seg ? val_alt : val;
+  const uint32_t* srect32 = lay.seg ? rect32_alt : rect32;
 
   // expand into pairs, then sort them by tile id alone
   const uint32_t P = lay.tpasses;
@@ -604,7 +676,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     pk.tile_shift = 64 - lay.tile_bits;
     pk.idx_bits = lay.idx_bits;
     pk.depth_top = scal + 5;
-    pk.depth_sorted = key;
+    pk.depth_sorted = skey;
     for (uint32_t p = 0; p < P; ++p) items_in[p] = (P - 1 - p) % 2 == 0 ? at<uint64_t>(ws, lay.alt_keys) : io.keys;
     bk[0] = items_in[0];
   }
@@ -613,10 +685,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.n_frames = lay.n_frames;
   e.n = lay.n;
   e.n_sorted = live;
-  e.key = key;
-  e.val = val;
+  e.key = skey;
+  e.val = sval;
   e.rect = ck.rect;
-  e.rect32 = rect32;  // after four passes the packed rectangles are back in the first buffer
+  e.rect32 = srect32;
   e.capacity = lay.capacity;
   e.keys = bk[0];
   e.values = bv[0];
@@ -628,8 +700,14 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.nblocks = lay.eblocks;
   e.packed = lay.packed;
   e.pk = pk;
+  e.seg = lay.seg;
   e.totals = PairTotalsArgs{ck.totals, ck.block_total, ck.block_frame, lay.ck_blocks, ck.bad, lay.n_frames,
                             lay.capacity, d_num_pairs, d_status, io.frame_pairs, io.frame_pair_base};
+  uint32_t* seg_base = lay.seg ? at<uint32_t>(ws, lay.seg_base) : nullptr;
+  uint32_t* seg_wgs = lay.seg ? at<uint32_t>(ws, lay.seg_wgs) : nullptr;
+  e.totals.seg_base = seg_base;
+  e.totals.seg_wgs = seg_wgs;
+  e.totals.seg_tile = lay.tcfg.tile();
   SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
   if (P > 0) {
     uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
@@ -652,13 +730,20 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     }
     uint32_t* lb_t = at<uint32_t>(ws, lay.lb_t);
     PassChain c{P, 8, lay.packed ? pk.tile_shift : 32u, lay.trb, lay.tcfg, lay.tblocks, ks, vs,
-                kd, vd, d_num_pairs, 0, d_status, bases_t, e.hist, P * lay.tbins, lb_t,
-                lay.tile_bits - lay.trb * (P - 1)};
+                kd, vd, d_num_pairs, 0, d_status, bases_t, e.hist,
+                (lay.seg ? lay.n_frames : 1u) * P * lay.tbins, lb_t, lay.tile_bits - lay.trb * (P - 1)};
     if (lay.packed) {
       c.packed = &pk;
       c.ranges = io.ranges;
       // after the 32-bit words of passes 0 .. P-2 (a multiple of 64 bytes)
       c.lookback64 = reinterpret_cast<uint64_t*>(lb_t + static_cast<size_t>(P - 1) * lay.tblocks * lay.tbins);
+    }
+    if (lay.seg) {
+      c.table = table;
+      c.n_frames = lay.n_frames;
+      c.seg_wgs = seg_wgs;
+      c.seg_base = seg_base;
+      c.frame_stride = P * lay.tbins;
     }
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
     if (lay.packed) {
@@ -670,6 +755,11 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       const int narrow = narrow_pass_bits(static_cast<int>(last_bits), 8, static_cast<int>(lay.trb),
                                           static_cast<int>(lay.tcfg.items), static_cast<int>(lay.tcfg.threads));
       if (last_bits < lay.trb && narrow != 0) last_rb = static_cast<uint32_t>(narrow);
+      if (lay.seg)
+        return L.run(SS_KERNEL_RANGES, [&] {
+          return launch_ranges_fix_seg(io.keys, d_status, bases_t + static_cast<size_t>(P - 1) * lay.tbins,
+                                       1u << last_rb, P * lay.tbins, seg_base, table, lay.n_frames, io.ranges, s);
+        });
       return L.run(SS_KERNEL_RANGES, [&] {
         return launch_ranges_fix(io.keys, d_num_pairs, d_status, bases_t + static_cast<size_t>(P - 1) * lay.tbins,
                                  1u << last_rb, lay.total_tiles, io.ranges, s);
@@ -751,6 +841,7 @@ struct BatchShape {
   std::vector<FrameInfo> table;
   uint64_t n = 0, tiles = 0;
   uint32_t max_n = 0;   // Gaussians of the largest frame
+  uint64_t max_tiles = 0;  // tiles of the frame with the most
 };
 
 ss_status batch_shape(const ss_frame* frames, uint32_t n_frames, BatchShape* b) {
@@ -765,6 +856,7 @@ ss_status batch_shape(const ss_frame* frames, uint32_t n_frames, BatchShape* b) 
     b->n += frames[f].num_gaussians;
     b->tiles += g.num_tiles;
     if (frames[f].num_gaussians > b->max_n) b->max_n = frames[f].num_gaussians;
+    if (g.num_tiles > b->max_tiles) b->max_tiles = g.num_tiles;
     if (b->n > 0x7FFFFFFFull || b->tiles > 0xFFFFFFFFull) return SS_ERR_INVALID_ARGUMENT;
   }
   return SS_OK;
@@ -884,7 +976,7 @@ ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity, cons
   if (pair_capacity > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;
   size_t sort = use_direct(o) ? make_layout(frame->num_gaussians, pair_capacity, g.key_bits, o).total
                               : make_df_layout(frame->num_gaussians, 1, pair_capacity, g.num_tiles, o,
-                                               frame->num_gaussians).total;
+                                               frame->num_gaussians, g.num_tiles).total;
   // small frames take the two-kernel path unless per-Gaussian outputs are
   // asked for, so both layouts must fit (the extra 8 words hold the status
   // when the caller gives none)
@@ -954,7 +1046,7 @@ ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out, void* wo
     return run_tiny(L, frame, g, &o2, workspace, s);
   }
   const FrameInfo fi = frame_info(frame, g, 0, 0);
-  const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o, frame->num_gaussians);
+  const DfLayout lay = make_df_layout(frame->num_gaussians, 1, cap, g.num_tiles, o, frame->num_gaussians, g.num_tiles);
   DfIO io{&fi, frame, out->keys, out->values, out->tile_ranges, out->tiles_touched, out->offsets,
           out->num_pairs, out->status, nullptr, nullptr};
   return run_depth_first(L, lay, o, io, workspace, s);
@@ -968,7 +1060,7 @@ ss_status ss_batch_workspace_bytes(const ss_frame* frames, uint32_t n_frames, ui
   Options o;
   SS_TRY(parse_options(options, &o));
   if (use_direct(o)) return SS_ERR_UNSUPPORTED;
-  *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o, b.max_n).total;
+  *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o, b.max_n, b.max_tiles).total;
   return SS_OK;
 }
 
@@ -985,7 +1077,7 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
   if (cap > 0 && (out->keys == nullptr || out->values == nullptr)) return SS_ERR_INVALID_ARGUMENT;
   if (!aligned(out->keys, 8) || !aligned(out->values, 4) || !aligned(out->tile_ranges, 4))
     return SS_ERR_INVALID_ARGUMENT;
-  const DfLayout lay = make_df_layout(static_cast<uint32_t>(b.n), n_frames, cap, b.tiles, o, b.max_n);
+  const DfLayout lay = make_df_layout(static_cast<uint32_t>(b.n), n_frames, cap, b.tiles, o, b.max_n, b.max_tiles);
   if (workspace == nullptr || !aligned(workspace, kAlign) || workspace_bytes < lay.total) return SS_ERR_WORKSPACE;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   Launcher L(s, o.timer);

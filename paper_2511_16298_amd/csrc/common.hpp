@@ -108,17 +108,20 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* s_tmp, T& total) {
 // *status (when not NULL).
 constexpr int kLookbackWindow = 8;
 
+// `first`: the chain's first workgroup (0, or a segment's first), which
+// publishes its count as inclusive at once.
 __device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_t stride, uint32_t d, uint32_t own,
-                                               uint32_t* status, uint32_t& excl) {
+                                               uint32_t* status, uint32_t& excl, uint32_t first = 0) {
   excl = 0;
-  if (t == 0) return true;
+  if (t == first) return true;
   int32_t kb = static_cast<int32_t>(t) - 1;  // nearest predecessor not yet consumed
+  const int32_t lo = static_cast<int32_t>(first);
   uint32_t spins = 0;
   while (true) {
     uint32_t w[kLookbackWindow];
 #pragma unroll
     for (int j = 0; j < kLookbackWindow; ++j)
-      w[j] = kb - j >= 0 ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbInc32;
+      w[j] = kb - j >= lo ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbInc32;
     uint32_t add = 0;
     int32_t used = 0;
     bool inc = false, stall = false;
@@ -163,17 +166,18 @@ __device__ __forceinline__ uint64_t lb_word(uint64_t state, uint32_t count, uint
 
 __device__ __forceinline__ bool lookback_digit_max(uint64_t* lb, uint32_t t, uint32_t stride, uint32_t d,
                                                    uint32_t own, uint32_t own_max, uint32_t* status,
-                                                   uint32_t& excl, uint32_t& excl_max) {
+                                                   uint32_t& excl, uint32_t& excl_max, uint32_t first = 0) {
   excl = 0;
   excl_max = 0;
-  if (t == 0) return true;
+  if (t == first) return true;
   int32_t kb = static_cast<int32_t>(t) - 1;
+  const int32_t lo = static_cast<int32_t>(first);
   uint32_t spins = 0;
   while (true) {
     uint64_t w[kLookbackWindow];
 #pragma unroll
     for (int j = 0; j < kLookbackWindow; ++j)
-      w[j] = kb - j >= 0 ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbIncW;
+      w[j] = kb - j >= lo ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbIncW;
     uint32_t add = 0, mx = 0;
     int32_t used = 0;
     bool inc = false, stall = false;

@@ -172,13 +172,28 @@ __device__ __forceinline__ void finish_totals(const PairTotalsArgs& a, unsigned 
     *a.num_pairs = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(m);
     if (*a.status == SS_OK) *a.status = st;
   }
-  if (a.frame_pairs == nullptr) return;
+  if (a.frame_pairs == nullptr && a.seg_base == nullptr) return;
   const uint32_t f32 = fm > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fm);
   uint32_t all;
   const uint32_t ex = block_exclusive_scan<uint32_t, THREADS>(f32, s_tmp, all);
   if (d < a.n_frames) {
-    a.frame_pairs[d] = f32;
+    if (a.frame_pairs) a.frame_pairs[d] = f32;
     if (a.frame_pair_base) a.frame_pair_base[d] = ex;
+  }
+  if (a.seg_base == nullptr) return;
+  // segmented tile passes (meaningful only while the status stays SS_OK,
+  // i.e. all pairs fit in 32 bits): each frame's first pair and first
+  // workgroup
+  const uint32_t wgs = static_cast<uint32_t>((static_cast<uint64_t>(f32) + a.seg_tile - 1) / a.seg_tile);
+  uint32_t wall;
+  const uint32_t wex = block_exclusive_scan<uint32_t, THREADS>(wgs, s_tmp, wall);
+  if (d < a.n_frames) {
+    a.seg_base[d] = ex;
+    a.seg_wgs[d] = wex;
+  }
+  if (d == 0) {
+    a.seg_base[a.n_frames] = all;
+    a.seg_wgs[a.n_frames] = wall;
   }
 }
 
@@ -226,15 +241,22 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_
 // inside the round, its first slot; a max-scan spreads the owners over the
 // round; thread t writes slots t, t + 512, ... (coalesced).
 // LDS: about 51 KB of fixed arrays (three workgroups per CU), plus the frame
-// table and the tile-digit histograms sized by the launch (expand_dyn_lds).
+// table and the tile-digit histograms sized by the launch (launch_expand).
 // Workgroup 0 finishes the pair totals in the owner map's space, before its
 // first expansion round.
+//
+// Segmented (a.seg: the Gaussians are frame-major, so frame f holds
+// positions [gauss_base[f], gauss_base[f] + n_f)): pairs carry frame-local
+// tiles and the histograms are per frame.  LDS holds those of the frames of
+// the workgroup's first and last Gaussian; pairs of a frame between them
+// (frames smaller than a workgroup) count straight into global memory.
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  FrameInfo* s_tab = reinterpret_cast<FrameInfo*>(s_dyn);                            // [n_frames]
-  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_dyn + a.n_frames * sizeof(FrameInfo));  // [npasses << radix_bits]
+  FrameInfo* s_tab = reinterpret_cast<FrameInfo*>(s_dyn);  // [n_frames]
+  // [1 or 2 frames][npasses << radix_bits]
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_dyn + a.n_frames * sizeof(FrameInfo));
   __shared__ uint32_t s_off[kExpandTile];
-  __shared__ uint32_t s_org[kExpandTile];   // global tile of (x0, y0)
+  __shared__ uint32_t s_org[kExpandTile];   // global tile of (x0, y0); segmented: frame-local | frame << 16
   __shared__ uint32_t s_wt[kExpandTile];    // w | tiles_x << 16
   __shared__ uint32_t s_dep[kExpandTile];
   __shared__ uint32_t s_loc[kExpandTile];
@@ -255,10 +277,18 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   for (uint32_t i = tid; i < a.n_frames; i += kExpandThreads) s_tab[i] = a.table[i];
   const uint32_t rb = a.radix_bits;
   const uint32_t bins = 1u << rb;
-  for (uint32_t i = tid; i < a.npasses * bins; i += kExpandThreads) s_hist[i] = 0;
+  const uint32_t hframe = a.npasses * bins;  // one frame's histograms
+  const uint32_t hwords = a.seg ? 2 * hframe : hframe;
+  for (uint32_t i = tid; i < hwords; i += kExpandThreads) s_hist[i] = 0;
   __syncthreads();
   const uint32_t ticket = blockIdx.x;   // look-back order (see common.hpp)
   const uint32_t base = ticket * kExpandTile;
+  // segmented: the frames whose histograms live in LDS
+  uint32_t f_lo = 0, f_hi = 0;
+  if (a.seg && a.n != 0) {
+    f_lo = frame_of(s_tab, a.n_frames, min(base, a.n - 1));
+    f_hi = frame_of(s_tab, a.n_frames, min(base + kExpandTile, a.n) - 1);
+  }
   const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;  // Gaussians the depth sort kept
   uint32_t ebase = 0;
   const bool trimmed = a.packed && packed_depth_trimmed(a.pk.depth_top[0], a.pk.depth_top[1], a.pk, &ebase);
@@ -291,7 +321,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       }
       const uint32_t tx = s_tab[f].tiles_x;
       cnt = w * h;
-      s_org[i] = s_tab[f].tile_base + y0 * tx + x0;
+      s_org[i] = a.seg ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0;
       s_wt[i] = w | (tx << 16);
       // packed items carry the depth field: trimmed depth bits, or the
       // position in depth order (the unpacking pass looks the bits up)
@@ -420,7 +450,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         const uint32_t w = wt & 0xFFFFu;
         const uint32_t dy = kk / w;
         const uint32_t dx = kk - dy * w;
-        const uint32_t tile = s_org[i] + dy * (wt >> 16) + dx;
+        const uint32_t org = s_org[i];
+        const uint32_t tile = (a.seg ? org & 0xFFFFu : org) + dy * (wt >> 16) + dx;
         if (a.packed) {
           keys[q] = (static_cast<uint64_t>(tile) << a.pk.tile_shift) |
                     (static_cast<uint64_t>(s_dep[i]) << a.pk.idx_bits) | s_loc[i];
@@ -428,15 +459,25 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
           keys[q] = (static_cast<uint64_t>(tile) << 32) | s_dep[i];
           vals[q] = s_loc[i];
         }
-        for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&s_hist[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+        uint32_t* h = s_hist;
+        if (a.seg) {
+          const uint32_t f = org >> 16;
+          h = f == f_lo ? s_hist
+              : f == f_hi ? s_hist + hframe
+                          : a.hist + (static_cast<size_t>(ticket % kHistCopies) * a.n_frames + f) * hframe;
+        }
+        for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&h[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
       }
     }
     __syncthreads();
   }
-  uint32_t* gh = a.hist + static_cast<size_t>(ticket % kHistCopies) * a.npasses * bins;
-  for (uint32_t i = tid; i < a.npasses * bins; i += kExpandThreads) {
+  // histogram copy ticket % kHistCopies: [npasses][bins], or, segmented,
+  // [frame][npasses][bins]
+  const size_t copy = static_cast<size_t>(ticket % kHistCopies) * (a.seg ? a.n_frames : 1u) * hframe;
+  for (uint32_t i = tid; i < hwords; i += kExpandThreads) {
     const uint32_t v = s_hist[i];
-    if (v) atomicAdd(&gh[i], v);
+    const uint32_t f = i < hframe ? f_lo : f_hi;
+    if (v) atomicAdd(&a.hist[copy + (a.seg ? static_cast<size_t>(f) * hframe : 0u) + i % hframe], v);
   }
 }
 
@@ -461,7 +502,8 @@ hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s) {
 
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
   if (a.nblocks == 0) return hipSuccess;
-  const size_t dyn = a.n_frames * sizeof(FrameInfo) + (static_cast<size_t>(a.npasses) << a.radix_bits) * 4;
+  const size_t dyn = a.n_frames * sizeof(FrameInfo) + (static_cast<size_t>(a.npasses) << a.radix_bits) * 4 *
+                                                         (a.seg ? 2u : 1u);
   hipLaunchKernelGGL(k_expand, dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
   return hipGetLastError();
 }

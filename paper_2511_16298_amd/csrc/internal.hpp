@@ -31,6 +31,17 @@ struct CountDupArgs {
   uint32_t nblocks;
 };
 
+// One frame of a (possibly one-frame) batch, as the depth-first kernels see it.
+struct FrameInfo {
+  uint32_t gauss_base;   // first global Gaussian index of the frame
+  uint32_t n;            // Gaussians of the frame
+  uint32_t tiles_x, tiles_y;
+  uint32_t tile_base;    // first global tile id of the frame
+  uint32_t pad;
+  const ss_gaussian2d* gaussians;
+};
+static_assert(sizeof(FrameInfo) == 32, "frame table entry");
+
 // A (tile, depth, index) pair held in one 64-bit item: tile << tile_shift |
 // depth field << idx_bits | frame-local index.  The depth field is the depth
 // bits minus (b_min << 24), b_min the smallest top byte of a depth that has
@@ -108,6 +119,21 @@ struct PassArgs {
   uint32_t* ranges;
   uint32_t low_bits;          // tile bits below this pass's digit
   uint64_t* lookback64;
+  // Segmented 64-bit passes (a batch whose pairs are frame-major, after the
+  // depth sort's frame pass): no workgroup's tile straddles two frames, a frame's
+  // workgroups look back only among themselves, digit bases are per frame.
+  // The chain's first pass starts with seg_frames publishing workgroups, one
+  // per frame.  hist: [copy][frame][pass][bins] (hist_stride between copies),
+  // bases: [frame][pass][bins] (bases_frame_stride between frames).
+  const uint32_t* seg_wgs;    // [frames + 1] first tile workgroup of each frame; NULL: not segmented
+  const uint32_t* seg_base;   // [frames + 1] first pair of each frame (the last: all pairs)
+  uint32_t seg_frames;
+  uint32_t bases_frame_stride;
+  const FrameInfo* table;     // kPassUnpack, segmented: tile_base of each frame
+  // The depth sort's frame pass (32-bit keys): an item's digit is its frame,
+  // from its value (the Gaussian's global index) and the frames' gauss_base.
+  bool frame_digit;
+  uint32_t n_frames;
 };
 
 struct HistArgs {
@@ -117,16 +143,6 @@ struct HistArgs {
   uint32_t* hist;             // zeroed [kHistCopies][npasses][bins]
 };
 
-// One frame of a (possibly one-frame) batch, as the depth-first kernels see it.
-struct FrameInfo {
-  uint32_t gauss_base;   // first global Gaussian index of the frame
-  uint32_t n;            // Gaussians of the frame
-  uint32_t tiles_x, tiles_y;
-  uint32_t tile_base;    // first global tile id of the frame
-  uint32_t pad;
-  const ss_gaussian2d* gaussians;
-};
-static_assert(sizeof(FrameInfo) == 32, "frame table entry");
 
 // Frames carried by value in one launch's arguments.
 constexpr uint32_t kArgFrames = 32;
@@ -171,6 +187,11 @@ struct PairTotalsArgs {
   uint32_t* status;            // set only while it still reads SS_OK
   uint32_t* frame_pairs;       // optional
   uint32_t* frame_pair_base;   // optional
+  // segmented tile passes: [n_frames + 1] first pair and first tile
+  // workgroup of each frame (workgroups of seg_tile pairs), or NULL
+  uint32_t* seg_base;
+  uint32_t* seg_wgs;
+  uint32_t seg_tile;
 };
 
 struct ExpandArgs {
@@ -188,9 +209,13 @@ struct ExpandArgs {
   uint32_t* values;         // out: frame-local Gaussian index (unused when packed)
   bool packed;              // write packed 64-bit items (layout `pk`) instead
   PackedPairs pk;
+  // segmented (frame-major Gaussians): items carry frame-local tiles and the
+  // tile-digit histograms are per frame ([copy][frame][npasses][bins])
+  bool seg;
   uint32_t npasses;         // tile-digit passes that follow
   uint32_t radix_bits;      // their digit width (<= 8)
-  uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits]
+  uint32_t* hist;           // zeroed [kHistCopies][npasses][1 << radix_bits] (segmented:
+                            // [kHistCopies][n_frames][npasses][1 << radix_bits])
   uint64_t* lookback;       // zeroed [nblocks]
   uint32_t* status;
   uint32_t nblocks;
@@ -226,6 +251,11 @@ bool packed_pass_supported(int radix_bits, int items, int threads);
 hipError_t launch_ranges_fix(const uint64_t* keys, const uint32_t* num_pairs, const uint32_t* status,
                              const uint32_t* bases, uint32_t bins, uint32_t num_tiles, uint32_t* ranges,
                              hipStream_t s);
+// The same per frame of a segmented batch (one workgroup per frame):
+// bases [frame][...] frame_stride apart, seg_base [frames + 1].
+hipError_t launch_ranges_fix_seg(const uint64_t* keys, const uint32_t* status, const uint32_t* bases, uint32_t bins,
+                                 uint32_t frame_stride, const uint32_t* seg_base, const FrameInfo* table,
+                                 uint32_t n_frames, uint32_t* ranges, hipStream_t s);
 // The compiled digit width (>= bits) that a pass of this shape can use when
 // its digit has only `bits` significant bits, or 0 (use radix_bits).
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads);

@@ -46,10 +46,33 @@ struct PassSmem {
   // kPassUnpack: per digit, 1 + the largest tile part below the digit among
   // the pairs of earlier workgroups (0: none)
   uint32_t lbx[MODE == kPassUnpack ? (1 << RB) : 1];
+  // segmented 64-bit passes: each frame's first tile workgroup; the depth
+  // sort's frame pass: each frame's first Gaussian
+  uint32_t aux[kMaxFrames + 1];
   unsigned long long tmp[THREADS / kWave];
   uint32_t timeout;
   uint32_t drop;     // 32-bit keys: this pass drops culled Gaussians
 };
+
+// Where a workgroup's tile sits in a segmented pass (a frame's first tile
+// workgroup, the frame's digit bases, its first global tile); the whole
+// sort is one segment otherwise.
+struct SegCtx {
+  uint32_t first;
+  const uint32_t* bases;
+  uint32_t tile_base;
+};
+
+// Largest f < n_frames with first[f] <= x (first[] non-decreasing).
+__device__ __forceinline__ uint32_t segment_of(const uint32_t* first, uint32_t n_frames, uint32_t x) {
+  uint32_t lo = 0, hi = n_frames;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // The tile body, in two parts: the loads, then ranking and scatter.  FULL:
 // every one of the TILE slots holds a pair (all tiles but the last, unless
@@ -69,10 +92,15 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
   if constexpr (sizeof(K) == 4) {
     if (tid < BINS) {
       uint32_t gtot = 0;
+      if (a.frame_digit) {
+        // the frame pass: digit f holds the frame's Gaussians (none dropped)
+        gtot = static_cast<uint32_t>(tid) < a.n_frames ? sm.aux[tid + 1] - sm.aux[tid] : 0u;
+      } else {
 #pragma unroll
-      for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + tid];
-      // culled Gaussians dropped by an earlier pass (all of digit 255)
-      if (tid == BINS - 1) gtot -= dropped;
+        for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + tid];
+        // culled Gaussians dropped by an earlier pass (all of digit 255)
+        if (tid == BINS - 1) gtot -= dropped;
+      }
       sm.gofs[tid] = gtot;
     }
   }
@@ -88,7 +116,8 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
     if (FULL || idx < n) {
       k[j] = kin[idx];
       v[j] = MODE == kPassKV ? a.vin[idx] : 0u;
-      dg[j] = static_cast<uint32_t>(k[j] >> a.shift) & DMASK;
+      dg[j] = sizeof(K) == 4 && a.frame_digit ? segment_of(sm.aux, a.n_frames, v[j])
+                                              : static_cast<uint32_t>(k[j] >> a.shift) & DMASK;
     } else {
       k[j] = 0;
       v[j] = 0;
@@ -112,7 +141,7 @@ __device__ __forceinline__ void range_boundary(uint32_t* __restrict__ ranges, in
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
 __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm, uint32_t t,
                                           uint32_t base, uint32_t n, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
-                                          uint32_t (&dg)[ITEMS]) {
+                                          uint32_t (&dg)[ITEMS], const SegCtx& sc) {
   constexpr int WAVES = THREADS / kWave;
   constexpr int BINS = 1 << RB;
   constexpr uint32_t DMASK = BINS - 1;
@@ -174,7 +203,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     }
     // kPassUnpack publishes after the permute, with its largest tile part
     if (MODE != kPassUnpack)
-      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == 0 ? kLbInc32 : kLbAgg32) | bcnt);
+      st_agent(&a.lookback[static_cast<size_t>(t) * BINS + tid], (t == sc.first ? kLbInc32 : kLbAgg32) | bcnt);
   }
   uint32_t gbase, lexcl;
   uint32_t tile_pairs = 0;  // 32-bit keys: valid items of the tile (some may be dropped)
@@ -197,11 +226,17 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   __syncthreads();
 
   // ---- permute the keys into digit order in LDS ----
+  // (the frame pass's digit is not in the key: it parks each slot's digit
+  // in the buffer's second half, free until the values go through it)
+  const bool frame_digit = sizeof(K) == 4 && a.frame_digit;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (FULL || dg[j] < BINS) {
       pos[j] += sm.dstart[dg[j]] + wc[dg[j]];
       sm.buf[pos[j]] = k[j];
+      if constexpr (sizeof(K) == 4) {
+        if (frame_digit) sm.buf[TILE + pos[j]] = static_cast<K>(dg[j]);
+      }
     }
   }
   // 32-bit keys: the second value, loaded now (into the registers the keys
@@ -225,7 +260,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     }
     if (tid < BINS)
       st_agent(&a.lookback64[static_cast<size_t>(t) * BINS + tid],
-               lb_word(t == 0 ? kLbIncW : kLbAggW, bcnt, own_max));
+               lb_word(t == sc.first ? kLbIncW : kLbAggW, bcnt, own_max));
   }
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
@@ -233,7 +268,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     if constexpr (sizeof(K) == 8) {
       // published by workgroup 0 of the chain's first pass, long before any
       // workgroup gets here
-      uint32_t w = ld_agent(&a.bases[tid]), spins = 0;
+      uint32_t w = ld_agent(&sc.bases[tid]), spins = 0;
       while ((w & kBasePublished) == 0) {
         if (++spins > kSpinLimit) {
           sm.timeout = 1;
@@ -241,17 +276,18 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        w = ld_agent(&a.bases[tid]);
+        w = ld_agent(&sc.bases[tid]);
       }
       gbase = w & ~kBasePublished;
     }
     uint32_t excl = 0;
     if constexpr (MODE == kPassUnpack) {
       uint32_t excl_max = 0;
-      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max)) sm.timeout = 1;
+      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max, sc.first))
+        sm.timeout = 1;
       sm.lbx[tid] = excl != 0 ? excl_max : 0u;
     } else {
-      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl)) sm.timeout = 1;
+      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl, sc.first)) sm.timeout = 1;
     }
     sm.gofs[tid] = gbase + excl - lexcl;
   }
@@ -280,7 +316,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
         const uint32_t d = static_cast<uint32_t>(item >> a.shift) & DMASK;
         const uint32_t o = sm.gofs[d] + i;
         if (o < n) {
-          const uint32_t tile = static_cast<uint32_t>(item >> S);
+          const uint32_t tile = sc.tile_base + static_cast<uint32_t>(item >> S);
           const uint64_t payload = item & pmask;
           const uint32_t hi = static_cast<uint32_t>(payload >> ib);
           const uint32_t dbits = trimmed ? hi + ebase : a.packed.depth_sorted[hi];
@@ -292,11 +328,11 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
           int64_t tp = -1;
           bool known = true;
           if (i > sm.dstart[d]) {
-            tp = static_cast<int64_t>(sm.buf[i - 1] >> S);
+            tp = static_cast<int64_t>(sc.tile_base + static_cast<uint32_t>(sm.buf[i - 1] >> S));
           } else {
             const uint32_t lx = sm.lbx[d];
             known = lx != 0;
-            tp = (static_cast<int64_t>(d) << a.low_bits) | static_cast<int64_t>(lx - 1u);
+            tp = sc.tile_base + ((static_cast<int64_t>(d) << a.low_bits) | static_cast<int64_t>(lx - 1u));
           }
           if (known && tp != static_cast<int64_t>(tile)) range_boundary(a.ranges, tp, tile, o);
         }
@@ -311,7 +347,11 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     dst[j] = 0xFFFFFFFFu;
     if (FULL || i < valid_n) {
       const K key = sm.buf[i];
-      const uint32_t o = sm.gofs[static_cast<uint32_t>(key >> a.shift) & DMASK] + i;
+      uint32_t d = static_cast<uint32_t>(key >> (frame_digit ? 0u : a.shift)) & DMASK;
+      if constexpr (sizeof(K) == 4) {
+        if (frame_digit) d = static_cast<uint32_t>(sm.buf[TILE + i]);
+      }
+      const uint32_t o = sm.gofs[d] + i;
       if (o < n) {
         kout[o] = key;
         dst[j] = o;
@@ -356,12 +396,12 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
 
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm, uint32_t t,
-                                          uint32_t base, uint32_t n, uint32_t dropped) {
+                                          uint32_t base, uint32_t n, uint32_t dropped, const SegCtx& sc) {
   K k[ITEMS];
   uint32_t v[ITEMS];
   uint32_t dg[ITEMS];
   pass_load<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, base, n, dropped, k, v, dg);
-  pass_rest<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, t, base, n, k, v, dg);
+  pass_rest<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, t, base, n, k, v, dg, sc);
 }
 
 // The extra workgroup of a chain's first 64-bit pass: digit bases of
@@ -414,6 +454,28 @@ __device__ __forceinline__ void store_depth_top(const PassArgs& a, uint32_t* s2)
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
 __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm);
 
+// Segmented: publishing workgroup f computes frame f's digit bases for
+// publish_passes passes (from the frame's histograms) and offsets them by the
+// frame's first pair.
+template <int RB, int THREADS>
+__device__ __forceinline__ void publish_bases_seg(const PassArgs& a, uint32_t f, uint32_t* s_tmp) {
+  constexpr int BINS = 1 << RB;
+  const int tid = threadIdx.x;
+  const uint32_t first = a.seg_base[f];
+  const size_t fo = static_cast<size_t>(f) * a.bases_frame_stride;
+  for (uint32_t q = 0; q < a.publish_passes; ++q) {
+    uint32_t tot = 0;
+    if (tid < BINS) {
+#pragma unroll
+      for (uint32_t c = 0; c < kHistCopies; ++c)
+        tot += a.hist[static_cast<size_t>(c) * a.hist_stride + fo + q * BINS + tid];
+    }
+    uint32_t all;
+    const uint32_t ex = block_exclusive_scan<uint32_t, THREADS>(tot, s_tmp, all);
+    if (tid < BINS) st_agent(&a.bases[fo + q * BINS + tid], (first + ex) | kBasePublished);
+  }
+}
+
 // DROP (32-bit keys, the depth sort's first pass): may drop the culled
 // Gaussians (the decision is known only after the loads).
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
@@ -436,25 +498,50 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
   __syncthreads();
   // In a chain's first 64-bit pass workgroup 0 only publishes the digit
   // bases (dispatched first, it has them out before any tile needs them, and
-  // no tile's look-back waits on it); tile b is then workgroup b + 1.
+  // no tile's look-back waits on it); tile b is then workgroup b + 1.  A
+  // segmented chain has one publishing workgroup per frame.
   uint32_t t = blockIdx.x;
+  SegCtx sc{0u, a.bases, 0u};
+  uint32_t base = 0, end = n;
   if constexpr (sizeof(K) == 8) {
-    if (a.publish_passes != 0) {
-      if (t == 0) {
+    const uint32_t publishers = a.publish_passes == 0 ? 0u : a.seg_wgs != nullptr ? a.seg_frames : 1u;
+    if (t < publishers) {
+      if (a.seg_wgs != nullptr)
+        publish_bases_seg<RB, THREADS>(a, t, reinterpret_cast<uint32_t*>(sm.tmp));
+      else
         publish_bases<RB, THREADS>(a, reinterpret_cast<uint32_t*>(sm.tmp));
-        return;
-      }
-      --t;
+      return;
+    }
+    t -= publishers;
+    if (a.seg_wgs != nullptr) {
+      // this workgroup's frame, and its tile inside the frame's pairs
+      for (uint32_t i = tid; i <= a.seg_frames; i += THREADS) sm.aux[i] = a.seg_wgs[i];
+      __syncthreads();
+      if (t >= sm.aux[a.seg_frames]) return;   // more workgroups than the frames' tiles
+      const uint32_t f = segment_of(sm.aux, a.seg_frames, t);
+      sc.first = sm.aux[f];
+      sc.bases = a.bases + static_cast<size_t>(f) * a.bases_frame_stride;
+      if (MODE == kPassUnpack) sc.tile_base = a.table[f].tile_base;
+      base = a.seg_base[f] + (t - sc.first) * TILE;
+      end = a.seg_base[f + 1];
+    } else {
+      base = t * TILE;
+    }
+  } else {
+    base = t * TILE;
+    if (a.frame_digit) {
+      // frames' first Gaussians, then all of them
+      for (uint32_t i = tid; i <= a.n_frames; i += THREADS) sm.aux[i] = i < a.n_frames ? a.table[i].gauss_base : n;
+      __syncthreads();
     }
   }
-  const uint32_t base = t * TILE;
-  if (base >= n) return;  // uniform over the workgroup
+  if (base >= end) return;  // uniform over the workgroup
   if constexpr (!DROP) {
     const uint32_t dropped = sizeof(K) == 4 && a.n_total != 0 ? a.n_total - n : 0u;
-    if (n - base >= static_cast<uint32_t>(TILE))
-      pass_tile<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, dropped);
+    if (end - base >= static_cast<uint32_t>(TILE))
+      pass_tile<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, end, dropped, sc);
     else
-      pass_tile<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, dropped);
+      pass_tile<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, end, dropped, sc);
   } else {
     // the loads go out before the drop decision (one thread's reads of the
     // culled count), which only marks the culled as not pairs
@@ -482,17 +569,18 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
     // the second variant fits the registers (up to 12 items per thread)
     if constexpr (ITEMS <= 12) {
       if (n - base >= static_cast<uint32_t>(TILE) && !sm.drop) {
-        pass_rest<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, k, v, dg);
+        pass_rest<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, k, v, dg, sc);
         return;
       }
     }
-    pass_rest<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, k, v, dg);
+    pass_rest<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, k, v, dg, sc);
   }
 }
 
 template <typename K, int RB, int ITEMS, int THREADS, int MODE>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
-  const uint32_t grid = nblocks + (sizeof(K) == 8 && a.publish_passes != 0 ? 1u : 0u);
+  const uint32_t publishers = a.publish_passes == 0 ? 0u : a.seg_wgs != nullptr ? a.seg_frames : 1u;
+  const uint32_t grid = nblocks + (sizeof(K) == 8 ? publishers : 0u);
   if constexpr (sizeof(K) == 4) {
     if (a.culled != nullptr) {
       hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, MODE, true>), dim3(grid), dim3(THREADS), 0, s, a);
@@ -529,6 +617,49 @@ __global__ __launch_bounds__(256) void k_ranges_fix(const uint64_t* __restrict__
   for (int64_t e = tl + 1 + threadIdx.x; e < static_cast<int64_t>(num_tiles); e += blockDim.x) {
     ranges[2 * e] = m;
     ranges[2 * e + 1] = m;
+  }
+}
+
+// One workgroup per frame of a segmented batch: the frame's tiles before its
+// first pair start (and end) at its first pair, each digit's first pair
+// starts a range, and the tiles after its last pair are empty at its end.
+__global__ __launch_bounds__(256) void k_ranges_fix_seg(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ status,
+                                                        const uint32_t* __restrict__ bases, uint32_t bins,
+                                                        uint32_t frame_stride, const uint32_t* __restrict__ seg_base,
+                                                        const FrameInfo* __restrict__ table,
+                                                        uint32_t* __restrict__ ranges) {
+  if (status && *status != SS_OK) return;
+  const uint32_t f = blockIdx.x;
+  const uint32_t lo = seg_base[f], hi = seg_base[f + 1];
+  const uint32_t t0 = table[f].tile_base, t1 = t0 + table[f].tiles_x * table[f].tiles_y;
+  const uint32_t* b = bases + static_cast<size_t>(f) * frame_stride;
+  for (uint32_t d = threadIdx.x; d < bins; d += blockDim.x) {
+    const uint32_t o = b[d] & ~kBasePublished;
+    const uint32_t next = d + 1 < bins ? b[d + 1] & ~kBasePublished : hi;
+    if (next > o && o < hi) {
+      const uint32_t tile = static_cast<uint32_t>(keys[o] >> 32);
+      if (tile < t0 || tile >= t1) continue;  // not this frame's: never so for a sorted frame
+      if (o == lo) {
+        // the frame's first pair: its lower tiles are empty at lo
+        for (uint32_t e = t0; e < tile; ++e) {
+          ranges[2 * e] = lo;
+          ranges[2 * e + 1] = lo;
+        }
+        ranges[2 * tile] = lo;
+      } else {
+        const int64_t tp = static_cast<int64_t>(keys[o - 1] >> 32);
+        if (tp >= t0 && tp < tile) range_boundary(ranges, tp, tile, o);
+      }
+    }
+  }
+  // after the frame's last pair (tile tl): tl ends at hi, later tiles are [hi, hi)
+  int64_t tl = hi == lo ? static_cast<int64_t>(t0) - 1 : static_cast<int64_t>(keys[hi - 1] >> 32);
+  if (tl >= static_cast<int64_t>(t1)) tl = static_cast<int64_t>(t1) - 1;  // (as above)
+  if (threadIdx.x == 0 && tl >= static_cast<int64_t>(t0)) ranges[2 * tl + 1] = hi;
+  for (int64_t e = tl + 1 + threadIdx.x; e < static_cast<int64_t>(t1); e += blockDim.x) {
+    ranges[2 * e] = hi;
+    ranges[2 * e + 1] = hi;
   }
 }
 
@@ -580,6 +711,15 @@ hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int ite
   SS_PACKED_CASE(4, 16) SS_PACKED_CASE(4, 8)
 #undef SS_PACKED_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_ranges_fix_seg(const uint64_t* keys, const uint32_t* status, const uint32_t* bases, uint32_t bins,
+                                 uint32_t frame_stride, const uint32_t* seg_base, const FrameInfo* table,
+                                 uint32_t n_frames, uint32_t* ranges, hipStream_t s) {
+  if (n_frames == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ranges_fix_seg, dim3(n_frames), dim3(256), 0, s, keys, status, bases, bins, frame_stride,
+                     seg_base, table, ranges);
+  return hipGetLastError();
 }
 
 hipError_t launch_ranges_fix(const uint64_t* keys, const uint32_t* num_pairs, const uint32_t* status,

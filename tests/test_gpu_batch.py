@@ -85,6 +85,52 @@ def test_batch_with_degenerate_frames():
     check_against_oracle(frames, b, m)
 
 
+def test_segmented_batch_frames_smaller_than_a_workgroup():
+    """Many frames below 2,048 Gaussians between larger ones: one expansion
+    workgroup spans several frames (the frames between its first and last
+    count their tile digits straight into global memory); empty and
+    one-Gaussian frames in the run."""
+    rs = np.random.default_rng(11)
+    frames = []
+    for f in range(40):
+        n = [0, 1, 7, 300, 900, 1500, 2047, 2049][f % 8] if f % 5 else int(rs.integers(3000, 12000))
+        w, h = [(320, 180), (64, 48), (640, 360), (16, 16)][f % 4]
+        frames.append((w, h, synth.make_frame(synth.FrameSpec(w, h, n), 500 + f)))
+    for kw in ({}, {"radix_bits": 4}, {"items_per_thread": 8}):
+        b, st, m = run_batch(frames, **kw)
+        assert st == 0, kw
+        check_against_oracle(frames, b, m)
+
+
+def test_segmented_and_whole_batch_agree():
+    """The same frames through the segmented tile passes (default) and the
+    whole-batch ones (dropping culled Gaussians keeps the batch whole, as do
+    256-thread passes): identical outputs, equal to the oracle's."""
+    frames = synth.make_batch(7, seed=123, n_range=(4_000, 40_000))
+    outs = []
+    for kw in ({}, {"drop_culled": True}, {"workgroup_size": 256}):
+        b, st, m = run_batch(frames, **kw)
+        assert st == 0, kw
+        check_against_oracle(frames, b, m)
+        outs.append((u64(b.keys)[:m].copy(), u32(b.values)[:m].copy(), u32(b.tile_ranges).copy()))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
+
+
+def test_batch_frame_tile_limits():
+    """A frame of exactly 2^16 tiles (4096 x 4096: the widest frame-local
+    tile field of the segmented passes) and, in another batch, one of more
+    (4200 x 4200, 69,169 tiles: the whole-batch passes)."""
+    for big in (4096, 4200):
+        frames = [(big, big, synth.make_frame(synth.FrameSpec(big, big, 30_000), 61)),
+                  (640, 360, synth.make_frame(synth.FrameSpec(640, 360, 10_000), 62)),
+                  (1280, 720, synth.make_frame(synth.FrameSpec(1280, 720, 5_000), 63))]
+        b, st, m = run_batch(frames)
+        assert st == 0, big
+        check_against_oracle(frames, b, m)
+
+
 def test_batch_capacity_error():
     frames = synth.make_batch(3, n_range=(5_000, 9_000))
     total = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)

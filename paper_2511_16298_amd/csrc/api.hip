@@ -594,9 +594,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   // Gaussians the depth passes absorb the extra 8 B per Gaussian almost for
   // free (they wait on the look-back more than on memory); beyond that they
   // are bandwidth-bound and the extra bytes cost what the gather did.
-  bool pack = lay.n <= (1u << 23);
+  bool small_rects = true;
   for (uint32_t f = 0; f < lay.n_frames; ++f)
-    pack = pack && io.host_table[f].tiles_x <= 256 && io.host_table[f].tiles_y <= 256;
+    small_rects = small_rects && io.host_table[f].tiles_x <= 256 && io.host_table[f].tiles_y <= 256;
+  const bool pack = lay.n <= (1u << 23) && small_rects;
   uint32_t* rect32 = pack ? at<uint32_t>(ws, lay.rect) : nullptr;
   uint32_t* rect32_alt = pack ? rect32 + lay.n : nullptr;
   CountKeysArgs ck{};
@@ -689,6 +690,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.val = sval;
   e.rect = ck.rect;
   e.rect32 = srect32;
+  e.small_rects = small_rects;
   e.capacity = lay.capacity;
   e.keys = bk[0];
   e.values = bv[0];

@@ -256,10 +256,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   // [1 or 2 frames][npasses << radix_bits]
   uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_dyn + a.n_frames * sizeof(FrameInfo));
   __shared__ uint32_t s_off[kExpandTile];
-  __shared__ uint32_t s_org[kExpandTile];   // global tile of (x0, y0); segmented: frame-local | frame << 16
-  __shared__ uint32_t s_wt[kExpandTile];    // w | tiles_x << 16
-  __shared__ uint32_t s_dep[kExpandTile];
-  __shared__ uint32_t s_loc[kExpandTile];
+  // per Gaussian, read as one 16-byte word per pair: x = global tile of
+  // (x0, y0) (segmented: frame-local | frame << 16), y = w | tiles_x << 16,
+  // z = depth field, w = frame-local index
+  __shared__ uint4 s_info[kExpandTile];
   __shared__ __align__(16) uint16_t s_map[kChunk];
   __shared__ uint32_t s_incl[kExpandThreads];
   __shared__ unsigned long long s_tmp64[kExpandThreads / kWave];
@@ -321,12 +321,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       }
       const uint32_t tx = s_tab[f].tiles_x;
       cnt = w * h;
-      s_org[i] = a.seg ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0;
-      s_wt[i] = w | (tx << 16);
       // packed items carry the depth field: trimmed depth bits, or the
       // position in depth order (the unpacking pass looks the bits up)
-      s_dep[i] = !a.packed ? dep : trimmed ? dep - ebase : pos;
-      s_loc[i] = g - s_tab[f].gauss_base;
+      s_info[i] = make_uint4(a.seg ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0,
+                             w | (tx << 16), !a.packed ? dep : trimmed ? dep - ebase : pos,
+                             g - s_tab[f].gauss_base);
     }
     s_off[i] = cnt;
   }
@@ -446,18 +445,24 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         const uint32_t i = static_cast<uint32_t>(s_map[q - cb]) - 1u;
         if (i >= kExpandTile) continue;  // every slot has an owner; kept for safety
         const uint32_t kk = q - s_off[i];
-        const uint32_t wt = s_wt[i];
+        const uint4 gi = s_info[i];
+        const uint32_t org = gi.x, wt = gi.y;
         const uint32_t w = wt & 0xFFFFu;
-        const uint32_t dy = kk / w;
+        // row of pair kk in the w-wide rectangle.  Rectangles of at most
+        // 256 x 256 tiles (kk < 2^16): floor((kk + 1/2) / w) in fp32 is exact,
+        // its true value lying at least 1/512 from an integer while the
+        // rounding errors stay below 256 * 2^-21.
+        const uint32_t dy = a.small_rects ? static_cast<uint32_t>((static_cast<float>(kk) + 0.5f) *
+                                                                  __builtin_amdgcn_rcpf(static_cast<float>(w)))
+                                          : kk / w;
         const uint32_t dx = kk - dy * w;
-        const uint32_t org = s_org[i];
         const uint32_t tile = (a.seg ? org & 0xFFFFu : org) + dy * (wt >> 16) + dx;
         if (a.packed) {
           keys[q] = (static_cast<uint64_t>(tile) << a.pk.tile_shift) |
-                    (static_cast<uint64_t>(s_dep[i]) << a.pk.idx_bits) | s_loc[i];
+                    (static_cast<uint64_t>(gi.z) << a.pk.idx_bits) | gi.w;
         } else {
-          keys[q] = (static_cast<uint64_t>(tile) << 32) | s_dep[i];
-          vals[q] = s_loc[i];
+          keys[q] = (static_cast<uint64_t>(tile) << 32) | gi.z;
+          vals[q] = gi.w;
         }
         uint32_t* h = s_hist;
         if (a.seg) {

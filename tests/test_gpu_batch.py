@@ -131,6 +131,18 @@ def test_batch_frame_tile_limits():
         check_against_oracle(frames, b, m)
 
 
+def test_batch_wide_depth_ranges():
+    """Frames whose depths span 2, 9 and 23 binades, through the segmented
+    and the whole-batch tile passes."""
+    frames = [(1280, 720, synth.make_frame(synth.FrameSpec(1280, 720, 40_000, depth_lo=1e-3, depth_hi=1e4), 81)),
+              (640, 360, synth.make_frame(synth.FrameSpec(640, 360, 20_000, depth_lo=0.5, depth_hi=2.0), 82)),
+              (1920, 1080, synth.make_frame(synth.FrameSpec(1920, 1080, 30_000), 83))]
+    for kw in ({}, {"drop_culled": True}):
+        b, st, m = run_batch(frames, **kw)
+        assert st == 0, kw
+        check_against_oracle(frames, b, m)
+
+
 def test_batch_capacity_error():
     frames = synth.make_batch(3, n_range=(5_000, 9_000))
     total = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)

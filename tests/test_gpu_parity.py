@@ -380,6 +380,41 @@ def test_packed_pairs_both_depth_fields(case):
     assert_same(W, H, rec, gpu_frame(W, H, rec, stages=False), stages=False)
 
 
+def top_byte_span(depths):
+    """How many top-byte values (sign and 7 exponent bits) the depth keys
+    take: 2 binades per value."""
+    top = np.asarray(depths, np.float32).view(np.uint32) >> 24
+    return 0 if len(top) == 0 else int(top.max()) - int(top.min()) + 1
+
+
+# depth ranges from one binade to the whole float range: [2, 2^17) spans
+# top bytes 64..71 (8 values), [1, 2^17) 63..71 (9)
+DEPTH_RANGE_CASES = [(2.0, 131000.0, 8), (1.0, 131000.0, 9), (0.7, 0.71, 1), (1e-30, 1e30, 101)]
+
+
+@pytest.mark.parametrize("case", DEPTH_RANGE_CASES, ids=lambda c: f"{c[0]}-{c[1]}")
+@pytest.mark.parametrize("drop", [False, True])
+def test_depth_ranges_with_and_without_dropping(case, drop):
+    """Depths over one binade up to nearly all of the float range, with a
+    quarter of the Gaussians culled, with and without dropping them in the
+    depth sort: bit-exact pairs and ranges."""
+    lo, hi, span = case
+    W, H, n = 1920, 1080, 300_000
+    rec = synth.make_frame(synth.FrameSpec(W, H, n, depth_lo=lo, depth_hi=hi), 7300 + span)
+    rec["radius"][::4] = 0
+    cnt, _ = oracle.count(W, H, rec)
+    assert top_byte_span(rec["depth"][cnt > 0]) == span
+    print(f"depth [{lo}, {hi}] drop={drop}: top bytes span {span}", flush=True)
+    o = oracle.sort_frame(W, H, rec, stages=False)
+    s = ss.FrameSorter(W, H, n, o.num_pairs, drop_culled=drop)
+    out = s(ss.records_to_device(rec))
+    st, m = out.result()
+    assert st == 0 and m == o.num_pairs
+    assert np.array_equal(u64(out.keys)[:m], o.keys)
+    assert np.array_equal(u32(out.values)[:m], o.values)
+    assert np.array_equal(u32(out.tile_ranges).reshape(-1, 2), o.ranges)
+
+
 def tiny_path_frames():
     """Frames the two-kernel small-frame path takes (at most 256 tiles and
     16,384 Gaussians, no per-Gaussian outputs asked for), with its edges."""

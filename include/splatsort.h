@@ -103,7 +103,21 @@ typedef struct ss_options {
                               and items 8 or 16.  A pass tile holds
                               workgroup_size * items_per_thread pairs. */
   uint32_t algorithm;      /* SS_ALGO_*; all give bit-identical frame results */
+  /* Fields below are read only when struct_size covers them. */
+  uint32_t spin_limit;     /* depth-first path: polls a workgroup makes in a
+                              wait on other workgroups (decoupled look-back,
+                              published digit bases) before it gives up with
+                              SS_ERR_TIMEOUT; 0 = 2^20, far above any
+                              legitimate wait */
+  uint32_t fault;          /* SS_FAULT_* (0 = none): test hook */
 } ss_options;
+
+/* Test hook: the workgroups that publish the digit bases of the first pass
+ * over the pairs publish nothing, so every tile's bounded wait for its bases
+ * ends in SS_ERR_TIMEOUT (after spin_limit polls), while every kernel still
+ * runs to its end.  Depth-first path.  For tests of the timeout path. */
+#define SS_FAULT_NONE 0u
+#define SS_FAULT_WITHHOLD_BASES 1u
 
 /* SS_ALGO_DIRECT: duplicate in index order, then ceil((ceil(log2 T) + 32) /
  * radix_bits) passes over all M pairs.  SS_ALGO_DEPTH_FIRST: sort the N
@@ -154,6 +168,14 @@ typedef struct ss_options {
  * sees all Gaussians); on frames with few culled Gaussians the extra decision
  * costs a few microseconds.  No effect on the other algorithms. */
 #define SS_FLAG_DROP_CULLED 4u
+/* Depth-first path (frames and batches), 512-thread passes: the sort passes
+ * over the pairs run as persistent kernels, one grid of at most as many
+ * workgroups as the GPU holds at once, each taking tickets in order from an
+ * atomic counter (the base-publishing workgroups first, then the tiles)
+ * until none are left.  A ticket is only ever taken by a running workgroup,
+ * so every wait is on a workgroup that runs.  Same output.  Ignored with
+ * 256-thread passes. */
+#define SS_FLAG_PERSISTENT 8u
 
 /* Library identification. */
 uint32_t ss_abi_version(void);

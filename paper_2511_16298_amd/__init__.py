@@ -129,7 +129,8 @@ class FrameSorter:
     def __init__(self, width: int, height: int, num_gaussians: int, pair_capacity: int,
                  radix_bits: int = 0, items_per_thread: int = 0, stages: bool = False,
                  device="cuda", unsorted: bool = False, workgroup_size: int = 0, algorithm: int = 0,
-                 key32: bool = False, drop_culled: bool = False):
+                 key32: bool = False, drop_culled: bool = False, persistent: bool = False,
+                 spin_limit: int = 0, fault: int = 0):
         torch = _torch()
         self.width, self.height = width, height
         self.num_gaussians = num_gaussians
@@ -137,9 +138,11 @@ class FrameSorter:
         self.tiles_x, self.tiles_y, self.key_bits = geometry(width, height)
         self.num_tiles = self.tiles_x * self.tiles_y
         flags = ((_abi.SS_FLAG_UNSORTED if unsorted else 0) | (_abi.SS_FLAG_KEY32_LOSSY if key32 else 0)
-                 | (_abi.SS_FLAG_DROP_CULLED if drop_culled else 0))
+                 | (_abi.SS_FLAG_DROP_CULLED if drop_culled else 0)
+                 | (_abi.SS_FLAG_PERSISTENT if persistent else 0))
         self.options = make_options(radix_bits, items_per_thread, flags=flags,
-                                    workgroup_size=workgroup_size, algorithm=algorithm)
+                                    workgroup_size=workgroup_size, algorithm=algorithm,
+                                    spin_limit=spin_limit, fault=fault)
         probe = ss_frame()
         probe.width, probe.height, probe.tile_px, probe.num_gaussians = width, height, 16, num_gaussians
         probe.gaussians = 16 if num_gaussians else None   # only shape matters here
@@ -187,13 +190,15 @@ class BatchSorter:
     ``[(width, height, num_gaussians), ...]`` (one segmented sort)."""
 
     def __init__(self, shapes, pair_capacity: int, radix_bits: int = 0, items_per_thread: int = 0,
-                 workgroup_size: int = 0, device="cuda", plan_workspace: bool = False, drop_culled: bool = False):
+                 workgroup_size: int = 0, device="cuda", plan_workspace: bool = False, drop_culled: bool = False,
+                 persistent: bool = False, spin_limit: int = 0, fault: int = 0):
         import numpy as np
         torch = _torch()
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
         self.capacity = int(pair_capacity)
+        flags = (_abi.SS_FLAG_DROP_CULLED if drop_culled else 0) | (_abi.SS_FLAG_PERSISTENT if persistent else 0)
         self.options = make_options(radix_bits, items_per_thread, workgroup_size=workgroup_size,
-                                    flags=_abi.SS_FLAG_DROP_CULLED if drop_culled else 0)
+                                    flags=flags, spin_limit=spin_limit, fault=fault)
         tiles = [geometry(w, h)[0] * geometry(w, h)[1] for (w, h, _) in self.shapes]
         self.tile_base = np.concatenate([[0], np.cumsum(tiles)[:-1]]).astype(np.int64)
         self.num_tiles = int(sum(tiles))
@@ -273,7 +278,8 @@ class Plan:
         st, o, ms = _abi.ss_plan_config(self.handle)
         check(st, "ss_plan_config")
         return {"radix_bits": o.radix_bits, "items_per_thread": o.items_per_thread,
-                "workgroup_size": o.workgroup_size, "candidate_ms": ms}
+                "workgroup_size": o.workgroup_size, "persistent": bool(o.flags & _abi.SS_FLAG_PERSISTENT),
+                "candidate_ms": ms}
 
     def close(self):
         if getattr(self, "handle", None):

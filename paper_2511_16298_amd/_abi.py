@@ -45,6 +45,9 @@ SS_MAX_BATCH_FRAMES = 256
 SS_FLAG_UNSORTED = 1
 SS_FLAG_KEY32_LOSSY = 2
 SS_FLAG_DROP_CULLED = 4
+SS_FLAG_PERSISTENT = 8
+SS_FAULT_NONE = 0
+SS_FAULT_WITHHOLD_BASES = 1
 
 SS_MAX_IMAGE_PX = 1048560
 SS_MAX_PAIR_CAPACITY = (1 << 30) - 1
@@ -69,7 +72,7 @@ class ss_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
                 ("items_per_thread", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("timer", ctypes.c_void_p), ("workgroup_size", ctypes.c_uint32),
-                ("algorithm", ctypes.c_uint32)]
+                ("algorithm", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32), ("fault", ctypes.c_uint32)]
 
 
 class ss_batch_out(ctypes.Structure):
@@ -81,7 +84,7 @@ class ss_batch_out(ctypes.Structure):
 
 
 def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, flags: int = 0,
-                 workgroup_size: int = 0, algorithm: int = 0) -> ss_options:
+                 workgroup_size: int = 0, algorithm: int = 0, spin_limit: int = 0, fault: int = 0) -> ss_options:
     o = ss_options()
     o.struct_size = ctypes.sizeof(ss_options)
     o.radix_bits = radix_bits
@@ -90,6 +93,8 @@ def make_options(radix_bits: int = 0, items_per_thread: int = 0, timer=None, fla
     o.timer = timer
     o.workgroup_size = workgroup_size
     o.algorithm = algorithm
+    o.spin_limit = spin_limit
+    o.fault = fault
     return o
 
 

@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <cstddef>
 #include <new>
 #include <vector>
 
@@ -35,13 +36,22 @@ struct Options {
   uint32_t algorithm = SS_ALGO_AUTO;
   ss_timer* timer = nullptr;
   bool items_default = true;  // items_per_thread left at 0 (the frame size may choose)
+  uint32_t spin_limit = 0;    // 0: the kernels' default
+  uint32_t fault = SS_FAULT_NONE;
 };
 
 ss_status parse_options(const ss_options* o, Options* out) {
   *out = Options{};
   if (o == nullptr) return SS_OK;
-  if (o->struct_size < sizeof(ss_options)) return SS_ERR_INVALID_ARGUMENT;
-  if ((o->flags & ~(SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY | SS_FLAG_DROP_CULLED)) != 0) return SS_ERR_UNSUPPORTED;
+  // callers built before spin_limit and fault existed pass the shorter struct
+  if (o->struct_size < offsetof(ss_options, spin_limit)) return SS_ERR_INVALID_ARGUMENT;
+  if ((o->flags & ~(SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY | SS_FLAG_DROP_CULLED | SS_FLAG_PERSISTENT)) != 0)
+    return SS_ERR_UNSUPPORTED;
+  if (o->struct_size >= sizeof(ss_options)) {
+    if (o->fault > SS_FAULT_WITHHOLD_BASES) return SS_ERR_UNSUPPORTED;
+    out->spin_limit = o->spin_limit;
+    out->fault = o->fault;
+  }
   if (o->algorithm > SS_ALGO_BITONIC) return SS_ERR_UNSUPPORTED;
   // the normalised 32-bit key belongs to the bitonic network and needs the sort
   if ((o->flags & SS_FLAG_KEY32_LOSSY) != 0 &&
@@ -168,7 +178,7 @@ struct DfLayout {
   size_t block_total = 0, block_frame = 0;
   size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
          lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
-         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, total = 0;
+         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, tickets = 0, total = 0;
 };
 
 // Pairs travel through the tile passes as one 64-bit item when the tile id,
@@ -255,6 +265,7 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses + (L.packed ? 1 : 0)) * L.tblocks * L.tbins *
                                             sizeof(uint32_t));
   L.bases_t = off;   off = align_up(off + static_cast<size_t>(hframes) * L.tpasses * L.tbins * sizeof(uint32_t));
+  L.tickets = off;   off = align_up(off + kMaxTilePasses * sizeof(uint32_t));  // persistent tile passes
   L.clear_end = off;
   // written whole by the expansion's totals
   L.seg_base = off;  off = align_up(off + (L.seg ? n_frames + 1u : 0u) * sizeof(uint32_t));
@@ -370,6 +381,11 @@ struct PassChain {
   const uint32_t* seg_wgs;
   const uint32_t* seg_base;
   uint32_t frame_stride;
+  // waits, test hook, persistent 64-bit passes (pass p's zeroed counter at
+  // tickets + p; NULL: one workgroup per tile)
+  uint32_t spin_limit;
+  uint32_t fault;
+  uint32_t* tickets;
 };
 
 ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t s) {
@@ -407,6 +423,9 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
         a.depth_top_out = c.depth_top_out;
         a.hist_top = c.hist_top;
       }
+      a.spin_limit = c.spin_limit;
+      a.fault = c.fault;
+      a.tickets = c.tickets ? c.tickets + p : nullptr;
       a.frame_digit = c.frame_digit;
       a.table = c.table;
       a.n_frames = c.n_frames;
@@ -636,6 +655,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       c.depth_top_out = scal + 5;
       c.hist_top = ck.hist + 3 * 256;
     }
+    c.spin_limit = o.spin_limit;
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
   // segmented: a stable pass by frame, key -> alt (each frame's Gaussians
@@ -653,6 +673,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     c.frame_digit = true;
     c.table = table;
     c.n_frames = lay.n_frames;
+    c.spin_limit = o.spin_limit;
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
   // the Gaussians in (frame-major when segmented) depth order
@@ -700,6 +721,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.lookback = at<uint64_t>(ws, lay.expand_lb);
   e.status = d_status;
   e.nblocks = lay.eblocks;
+  e.spin_limit = o.spin_limit;
   e.packed = lay.packed;
   e.pk = pk;
   e.seg = lay.seg;
@@ -747,6 +769,9 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       c.seg_base = seg_base;
       c.frame_stride = P * lay.tbins;
     }
+    c.spin_limit = o.spin_limit;
+    c.fault = o.fault;
+    if ((o.flags & SS_FLAG_PERSISTENT) != 0 && lay.tcfg.threads == 512) c.tickets = at<uint32_t>(ws, lay.tickets);
     SS_TRY(run_chain(L, SS_KERNEL_SORT_PASS, c, s));
     if (lay.packed) {
       // the digits of the last pass: those of its (possibly narrower)

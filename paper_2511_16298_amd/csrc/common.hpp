@@ -36,6 +36,9 @@ constexpr uint32_t kBasePublished = 1u << 31;
 // but the grid always drains).  Far above any legitimate wait.
 constexpr uint32_t kSpinLimit = 1u << 20;
 
+// The spin limit a launch asked for (0: the default).
+__device__ __forceinline__ uint32_t spin_limit_of(uint32_t asked) { return asked != 0 ? asked : kSpinLimit; }
+
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -109,9 +112,11 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* s_tmp, T& total) {
 constexpr int kLookbackWindow = 8;
 
 // `first`: the chain's first workgroup (0, or a segment's first), which
-// publishes its count as inclusive at once.
+// publishes its count as inclusive at once.  `spin_limit`: polls before
+// giving up (kSpinLimit unless a caller asks for fewer).
 __device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_t stride, uint32_t d, uint32_t own,
-                                               uint32_t* status, uint32_t& excl, uint32_t first = 0) {
+                                               uint32_t* status, uint32_t& excl, uint32_t first = 0,
+                                               uint32_t spin_limit = kSpinLimit) {
   excl = 0;
   if (t == first) return true;
   int32_t kb = static_cast<int32_t>(t) - 1;  // nearest predecessor not yet consumed
@@ -140,7 +145,7 @@ __device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_
     if (inc) break;
     kb -= used;
     if (stall) {
-      if (++spins > kSpinLimit) {
+      if (++spins > spin_limit) {
         if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
         return false;
       }
@@ -166,7 +171,8 @@ __device__ __forceinline__ uint64_t lb_word(uint64_t state, uint32_t count, uint
 
 __device__ __forceinline__ bool lookback_digit_max(uint64_t* lb, uint32_t t, uint32_t stride, uint32_t d,
                                                    uint32_t own, uint32_t own_max, uint32_t* status,
-                                                   uint32_t& excl, uint32_t& excl_max, uint32_t first = 0) {
+                                                   uint32_t& excl, uint32_t& excl_max, uint32_t first = 0,
+                                                   uint32_t spin_limit = kSpinLimit) {
   excl = 0;
   excl_max = 0;
   if (t == first) return true;
@@ -199,7 +205,7 @@ __device__ __forceinline__ bool lookback_digit_max(uint64_t* lb, uint32_t t, uin
     if (inc) break;
     kb -= used;
     if (stall) {
-      if (++spins > kSpinLimit) {
+      if (++spins > spin_limit) {
         if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
         return false;
       }

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       if (state == 0 && tid < first) s_retry = 1;
       __syncthreads();
       if (s_retry) {
-        if (++spins > kSpinLimit) {
+        if (++spins > spin_limit_of(a.spin_limit)) {
           if (tid == 0) s_timeout = 1;
           break;
         }

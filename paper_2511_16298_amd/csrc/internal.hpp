@@ -134,6 +134,15 @@ struct PassArgs {
   // from its value (the Gaussian's global index) and the frames' gauss_base.
   bool frame_digit;
   uint32_t n_frames;
+  // Bounded waits: polls before SS_ERR_TIMEOUT (kSpinLimit when 0).  fault:
+  // SS_FAULT_* test hook (SS_FAULT_WITHHOLD_BASES: the chain's publishing
+  // workgroups publish nothing, so every tile's wait for its bases times out).
+  uint32_t spin_limit;
+  uint32_t fault;
+  // Persistent pass (64-bit keys): a grid of at most the resident workgroups,
+  // each taking tickets (publishing workgroups first, then tiles in order)
+  // from this zeroed counter until none are left.
+  uint32_t* tickets;
 };
 
 struct HistArgs {
@@ -220,6 +229,7 @@ struct ExpandArgs {
   uint64_t* lookback;       // zeroed [nblocks]
   uint32_t* status;
   uint32_t nblocks;
+  uint32_t spin_limit;      // look-back polls before SS_ERR_TIMEOUT (0: kSpinLimit)
   PairTotalsArgs totals;    // finished by workgroup 0
 };
 

@@ -5,6 +5,7 @@
 // so calls that overlap on one GPU race; the array keeps the last call's
 // contents, and the sort clears what it needs with its own fill kernel.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <mutex>
@@ -47,7 +48,7 @@ extern "C" {
 ss_status ss_sort_frame_noalloc(const ss_frame* frame, const ss_frame_out* out, void* stream,
                                 const ss_options* options) {
   // the depth-first path only (the default): the others build host tables
-  if (options != nullptr && options->struct_size >= sizeof(ss_options) &&
+  if (options != nullptr && options->struct_size >= offsetof(ss_options, spin_limit) &&
       ((options->algorithm != SS_ALGO_AUTO && options->algorithm != SS_ALGO_DEPTH_FIRST) ||
        (options->flags & (SS_FLAG_UNSORTED | SS_FLAG_KEY32_LOSSY)) != 0))
     return SS_ERR_UNSUPPORTED;

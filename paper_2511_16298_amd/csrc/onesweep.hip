@@ -52,6 +52,7 @@ struct PassSmem {
   unsigned long long tmp[THREADS / kWave];
   uint32_t timeout;
   uint32_t drop;     // 32-bit keys: this pass drops culled Gaussians
+  uint32_t ticket;   // persistent passes: the workgroup's current ticket
 };
 
 // Where a workgroup's tile sits in a segmented pass (a frame's first tile
@@ -269,8 +270,9 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       // published by workgroup 0 of the chain's first pass, long before any
       // workgroup gets here
       uint32_t w = ld_agent(&sc.bases[tid]), spins = 0;
+      const uint32_t limit = spin_limit_of(a.spin_limit);
       while ((w & kBasePublished) == 0) {
-        if (++spins > kSpinLimit) {
+        if (++spins > limit) {
           sm.timeout = 1;
           if (a.status) st_agent(a.status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
           break;
@@ -283,11 +285,13 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     uint32_t excl = 0;
     if constexpr (MODE == kPassUnpack) {
       uint32_t excl_max = 0;
-      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max, sc.first))
+      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max, sc.first,
+                              spin_limit_of(a.spin_limit)))
         sm.timeout = 1;
       sm.lbx[tid] = excl != 0 ? excl_max : 0u;
     } else {
-      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl, sc.first)) sm.timeout = 1;
+      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl, sc.first, spin_limit_of(a.spin_limit)))
+        sm.timeout = 1;
     }
     sm.gofs[tid] = gbase + excl - lexcl;
   }
@@ -411,6 +415,7 @@ template <int RB, int THREADS>
 __device__ __forceinline__ void publish_bases(const PassArgs& a, uint32_t* s_tmp) {
   constexpr int BINS = 1 << RB;
   const int tid = threadIdx.x;
+  if (a.fault == SS_FAULT_WITHHOLD_BASES) return;
   for (uint32_t q = 0; q < a.publish_passes; ++q) {
     uint32_t tot = 0;
     if (tid < BINS) {
@@ -452,7 +457,8 @@ __device__ __forceinline__ void store_depth_top(const PassArgs& a, uint32_t* s2)
 }
 
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
-__device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm);
+__device__ __forceinline__ bool onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm,
+                                              uint32_t t);
 
 // Segmented: publishing workgroup f computes frame f's digit bases for
 // publish_passes passes (from the frame's histograms) and offsets them by the
@@ -461,6 +467,7 @@ template <int RB, int THREADS>
 __device__ __forceinline__ void publish_bases_seg(const PassArgs& a, uint32_t f, uint32_t* s_tmp) {
   constexpr int BINS = 1 << RB;
   const int tid = threadIdx.x;
+  if (a.fault == SS_FAULT_WITHHOLD_BASES) return;
   const uint32_t first = a.seg_base[f];
   const size_t fo = static_cast<size_t>(f) * a.bases_frame_stride;
   for (uint32_t q = 0; q < a.publish_passes; ++q) {
@@ -477,19 +484,43 @@ __device__ __forceinline__ void publish_bases_seg(const PassArgs& a, uint32_t f,
 }
 
 // DROP (32-bit keys, the depth sort's first pass): may drop the culled
-// Gaussians (the decision is known only after the loads).
+// Gaussians (the decision is known only after the loads).  Workgroup b is
+// tile b (after the publishing workgroups).
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
 __global__ __launch_bounds__(THREADS) void k_onesweep(PassArgs a) {
   __shared__ PassSmem<K, RB, ITEMS, THREADS, MODE> sm;
   if (a.status && *a.status != SS_OK) return;
-  onesweep_body<K, RB, ITEMS, THREADS, MODE, DROP>(a, sm);
+  onesweep_body<K, RB, ITEMS, THREADS, MODE, DROP>(a, sm, blockIdx.x);
   if constexpr (sizeof(K) == 4) {
     if (a.depth_top_out != nullptr && blockIdx.x == 0) store_depth_top<THREADS>(a, sm.dstart);
   }
 }
 
+// Persistent form (64-bit keys, 512 threads, a.tickets): tickets in order
+// until one lies past the last tile.  A ticket is taken only by a running
+// workgroup, so every ticket a tile waits on (publishers, earlier tiles) is
+// held by one that runs too.  The loop would keep more registers live than
+// the one-tile kernel's; the bounds hold it to the waves per SIMD that the
+// tile's LDS allows anyway (4 with 16 items, 6 with 8).
+template <typename K, int RB, int ITEMS, int THREADS, int MODE>
+__global__ __launch_bounds__(THREADS, ITEMS >= 16 ? 4 : 6) void k_onesweep_persistent(PassArgs a) {
+  __shared__ PassSmem<K, RB, ITEMS, THREADS, MODE> sm;
+  if (a.status && *a.status != SS_OK) return;
+  while (true) {
+    if (threadIdx.x == 0)
+      sm.ticket = a.status && ld_agent(a.status) != SS_OK ? 0xFFFFFFFFu : atomicAdd(a.tickets, 1u);
+    __syncthreads();
+    const uint32_t t = sm.ticket;
+    if (t == 0xFFFFFFFFu || !onesweep_body<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t)) break;
+    __syncthreads();  // every thread is done with this ticket's LDS
+  }
+}
+
+// Workgroup (or ticket) t.  Returns false when t lies past the pass's last
+// tile (a persistent workgroup then stops taking tickets).
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool DROP>
-__device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm) {
+__device__ __forceinline__ bool onesweep_body(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm,
+                                              uint32_t t) {
   constexpr int TILE = THREADS * ITEMS;
   const uint32_t n = a.num_pairs ? *a.num_pairs : a.n_fixed;
   const int tid = threadIdx.x;
@@ -500,7 +531,6 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
   // bases (dispatched first, it has them out before any tile needs them, and
   // no tile's look-back waits on it); tile b is then workgroup b + 1.  A
   // segmented chain has one publishing workgroup per frame.
-  uint32_t t = blockIdx.x;
   SegCtx sc{0u, a.bases, 0u};
   uint32_t base = 0, end = n;
   if constexpr (sizeof(K) == 8) {
@@ -510,14 +540,14 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
         publish_bases_seg<RB, THREADS>(a, t, reinterpret_cast<uint32_t*>(sm.tmp));
       else
         publish_bases<RB, THREADS>(a, reinterpret_cast<uint32_t*>(sm.tmp));
-      return;
+      return true;
     }
     t -= publishers;
     if (a.seg_wgs != nullptr) {
       // this workgroup's frame, and its tile inside the frame's pairs
       for (uint32_t i = tid; i <= a.seg_frames; i += THREADS) sm.aux[i] = a.seg_wgs[i];
       __syncthreads();
-      if (t >= sm.aux[a.seg_frames]) return;   // more workgroups than the frames' tiles
+      if (t >= sm.aux[a.seg_frames]) return false;   // more workgroups than the frames' tiles
       const uint32_t f = segment_of(sm.aux, a.seg_frames, t);
       sc.first = sm.aux[f];
       sc.bases = a.bases + static_cast<size_t>(f) * a.bases_frame_stride;
@@ -535,7 +565,7 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
       __syncthreads();
     }
   }
-  if (base >= end) return;  // uniform over the workgroup
+  if (base >= end) return false;  // uniform over the workgroup
   if constexpr (!DROP) {
     const uint32_t dropped = sizeof(K) == 4 && a.n_total != 0 ? a.n_total - n : 0u;
     if (end - base >= static_cast<uint32_t>(TILE))
@@ -570,17 +600,45 @@ __device__ __forceinline__ void onesweep_body(const PassArgs& a, PassSmem<K, RB,
     if constexpr (ITEMS <= 12) {
       if (n - base >= static_cast<uint32_t>(TILE) && !sm.drop) {
         pass_rest<K, RB, ITEMS, THREADS, MODE, true>(a, sm, t, base, n, k, v, dg, sc);
-        return;
+        return true;
       }
     }
     pass_rest<K, RB, ITEMS, THREADS, MODE, false>(a, sm, t, base, n, k, v, dg, sc);
   }
+  return true;
+}
+
+// Workgroups of this kernel that the device holds at once (persistent
+// passes), from its occupancy and the device's CU count; 0 if unknown.
+template <typename K, int RB, int ITEMS, int THREADS, int MODE>
+uint32_t resident_workgroups() {
+  static const uint32_t n = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_onesweep_persistent<K, RB, ITEMS, THREADS, MODE>), THREADS,
+            0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0u;
+    return static_cast<uint32_t>(per_cu > 0 && cus > 0 ? per_cu * cus : 0);
+  }();
+  return n;
 }
 
 template <typename K, int RB, int ITEMS, int THREADS, int MODE>
 hipError_t pass_launch(const PassArgs& a, uint32_t nblocks, hipStream_t s) {
   const uint32_t publishers = a.publish_passes == 0 ? 0u : a.seg_wgs != nullptr ? a.seg_frames : 1u;
-  const uint32_t grid = nblocks + (sizeof(K) == 8 ? publishers : 0u);
+  uint32_t grid = nblocks + (sizeof(K) == 8 ? publishers : 0u);
+  if constexpr (sizeof(K) == 8 && THREADS == 512) {
+    if (a.tickets != nullptr) {
+      const uint32_t r = resident_workgroups<K, RB, ITEMS, THREADS, MODE>();
+      if (r == 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_onesweep_persistent<K, RB, ITEMS, THREADS, MODE>), dim3(grid < r ? grid : r),
+                         dim3(THREADS), 0, s, a);
+      return hipGetLastError();
+    }
+  }
+  if (a.tickets != nullptr) return hipErrorInvalidValue;  // persistent: 512-thread 64-bit passes only
   if constexpr (sizeof(K) == 4) {
     if (a.culled != nullptr) {
       hipLaunchKernelGGL((k_onesweep<K, RB, ITEMS, THREADS, MODE, true>), dim3(grid), dim3(THREADS), 0, s, a);

@@ -24,13 +24,15 @@ struct ss_plan {
 namespace {
 
 struct Candidate {
-  uint32_t radix_bits, items, threads;
+  uint32_t radix_bits, items, threads, flags;
 };
 
-// Every pass configuration compiled into the library.
+// Every pass configuration compiled into the library, and the 512-thread
+// ones again as persistent passes.
 const Candidate kCandidates[] = {
-    {8, 16, 512}, {8, 8, 512}, {6, 16, 512}, {6, 8, 512}, {4, 16, 512}, {8, 16, 256}, {8, 12, 256},
-    {8, 8, 256},  {6, 16, 256}, {4, 16, 256},
+    {8, 16, 512, 0}, {8, 8, 512, 0},  {6, 16, 512, 0}, {6, 8, 512, 0},  {4, 16, 512, 0},
+    {8, 16, 256, 0}, {8, 12, 256, 0}, {8, 8, 256, 0},  {6, 16, 256, 0}, {4, 16, 256, 0},
+    {8, 16, 512, SS_FLAG_PERSISTENT}, {8, 8, 512, SS_FLAG_PERSISTENT}, {6, 16, 512, SS_FLAG_PERSISTENT},
 };
 
 ss_options with(const ss_options& base, const Candidate& c) {
@@ -39,7 +41,8 @@ ss_options with(const ss_options& base, const Candidate& c) {
   o.radix_bits = c.radix_bits;
   o.items_per_thread = c.items;
   o.workgroup_size = c.threads;
-  o.timer = nullptr;  // the caller's flags stay
+  o.flags = (base.flags & ~SS_FLAG_PERSISTENT) | c.flags;  // the caller's other flags stay
+  o.timer = nullptr;
   return o;
 }
 

@@ -100,13 +100,20 @@ def test_sort_frame_argument_errors_are_synchronous():
     o = fake_out(cap=_abi.SS_MAX_PAIR_CAPACITY + 1)
     assert _abi.ss_sort_frame(f, o, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
     # options
-    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 8, 0), (0, 0, 0, 128),
+    for rb, it, fl, wg in [(5, 0, 0, 0), (9, 0, 0, 0), (0, 7, 0, 0), (0, 0, 16, 0), (0, 0, 0, 128),
                            (6, 12, 0, 512), (0, 12, 0, 512), (0, 0, 0, 1024)]:
         opt = _abi.make_options(rb, it, flags=fl, workgroup_size=wg)
         assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, opt) == _abi.SS_ERR_UNSUPPORTED
+    assert _abi.ss_sort_frame(f, fake_out(), ws, need, None,
+                              _abi.make_options(fault=_abi.SS_FAULT_WITHHOLD_BASES + 1)) == _abi.SS_ERR_UNSUPPORTED
     bad = _abi.make_options()
     bad.struct_size = 4
     assert _abi.ss_sort_frame(f, fake_out(), ws, need, None, bad) == _abi.SS_ERR_INVALID_ARGUMENT
+    # a caller built before spin_limit and fault existed: the shorter struct is
+    # accepted and the fields it does not cover are not read
+    old = _abi.make_options(fault=99)
+    old.struct_size = _abi.ss_options.spin_limit.offset
+    assert _abi.ss_workspace_bytes(f, 1000, old)[0] == _abi.SS_OK
     # count-only entry point
     assert _abi.ss_count_pairs(f, None, None, None, 1 << 10, ws, need, None) == _abi.SS_ERR_INVALID_ARGUMENT
     assert _abi.ss_count_pairs(f, None, None, 1 << 10, 1 << 11, ws, 16, None) == _abi.SS_ERR_WORKSPACE

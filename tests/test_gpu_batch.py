@@ -143,6 +143,29 @@ def test_batch_wide_depth_ranges():
         check_against_oracle(frames, b, m)
 
 
+@pytest.mark.parametrize("drop", [False, True])
+def test_persistent_passes_batch(drop):
+    """Persistent tile passes (workgroups taking tiles by atomic ticket) over a
+    segmented batch, and over a whole one: the same result."""
+    frames = synth.make_batch(9, seed=321, n_range=(2_000, 60_000))
+    b, st, m = run_batch(frames, persistent=True, drop_culled=drop)
+    assert st == 0
+    check_against_oracle(frames, b, m)
+
+
+def test_timeout_raised_from_the_host():
+    """With the digit bases withheld and a short spin limit every tile's wait
+    ends in SS_ERR_TIMEOUT and every kernel still finishes; without the hook
+    the same frames sort exactly."""
+    frames = synth.make_batch(4, seed=322, n_range=(20_000, 60_000))
+    for persistent in (False, True):
+        b, st, m = run_batch(frames, persistent=persistent, spin_limit=32, fault=ss._abi.SS_FAULT_WITHHOLD_BASES)
+        assert st == ss._abi.SS_ERR_TIMEOUT, persistent
+        b, st, m = run_batch(frames, persistent=persistent, spin_limit=32)
+        assert st == 0
+        check_against_oracle(frames, b, m)
+
+
 def test_batch_capacity_error():
     frames = synth.make_batch(3, n_range=(5_000, 9_000))
     total = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)

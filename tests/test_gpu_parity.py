@@ -415,6 +415,46 @@ def test_depth_ranges_with_and_without_dropping(case, drop):
     assert np.array_equal(u32(out.tile_ranges).reshape(-1, 2), o.ranges)
 
 
+@pytest.mark.parametrize("name", ["fullhd-1m", "large-6m", "one-pass", "capacity-tail"])
+def test_persistent_passes_frame(name):
+    """Persistent tile passes on single frames: several tiles per workgroup at
+    full size, one tile pass (at most 256 tiles), and a capacity far above
+    the pairs (tickets past the last tile end the loop)."""
+    if name in synth.FRAME_WORKLOADS:
+        spec, seed = synth.FRAME_WORKLOADS[name]
+        W, H, rec = spec.width, spec.height, synth.make_frame(spec, seed)
+    elif name == "one-pass":
+        W, H, rec = 256, 256, synth.make_frame(synth.FrameSpec(256, 256, 40_000), 91)
+    else:
+        W, H, rec = 640, 360, synth.make_frame(synth.FrameSpec(640, 360, 30_000), 92)
+    o = oracle.sort_frame(W, H, rec, stages=False)
+    cap = o.num_pairs * (4 if name == "capacity-tail" else 1)
+    s = ss.FrameSorter(W, H, len(rec), cap, persistent=True)
+    out = s(ss.records_to_device(rec))
+    st, m = out.result()
+    assert st == 0 and m == o.num_pairs
+    assert np.array_equal(u64(out.keys)[:m], o.keys)
+    assert np.array_equal(u32(out.values)[:m], o.values)
+    assert np.array_equal(u32(out.tile_ranges).reshape(-1, 2), o.ranges)
+
+
+def test_timeout_raised_from_the_host_frame():
+    """A single frame with its digit bases withheld: SS_ERR_TIMEOUT, every
+    kernel finishing; then the hook off, exact."""
+    W, H = 1920, 1080
+    rec = synth.make_frame(synth.FrameSpec(W, H, 200_000), 93)
+    o = oracle.sort_frame(W, H, rec, stages=False)
+    d = ss.records_to_device(rec)
+    bad = ss.FrameSorter(W, H, len(rec), o.num_pairs, spin_limit=32, fault=_abi.SS_FAULT_WITHHOLD_BASES)
+    st, _ = bad(d).result()
+    assert st == _abi.SS_ERR_TIMEOUT
+    good = ss.FrameSorter(W, H, len(rec), o.num_pairs, spin_limit=32)
+    out = good(d)
+    st, m = out.result()
+    assert st == 0 and m == o.num_pairs
+    assert np.array_equal(u64(out.keys)[:m], o.keys)
+
+
 def tiny_path_frames():
     """Frames the two-kernel small-frame path takes (at most 256 tiles and
     16,384 Gaussians, no per-Gaussian outputs asked for), with its edges."""

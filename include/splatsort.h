@@ -264,7 +264,14 @@ ss_status ss_batch_count_pairs(const ss_frame* frames, uint32_t n_frames, uint32
  * thread, workgroup size) on the given data and keeps the fastest; the
  * results are identical whichever is chosen.  Creation synchronises the
  * stream; the workspace must hold ss_plan_workspace_bytes.  Graph capture
- * runs on a stream the plan owns. */
+ * runs on a stream the plan owns.  With tune_cache (a file path), the choice
+ * is looked up first under (device architecture, HIP runtime version, ABI
+ * version, and the ceil(log2) of the frame count, Gaussians, pair capacity,
+ * total and largest frame's tiles); a hit skips the timing (ss_plan_config
+ * then reports no candidate times), a miss times the candidates and records
+ * the winner in the file (one text line per key, replaced in place; written
+ * through a temporary file and a rename).  A file that cannot be read or
+ * written only costs the timing. */
 typedef struct ss_plan ss_plan;
 typedef struct ss_plan_desc {
   uint32_t struct_size;      /* sizeof(ss_plan_desc) */
@@ -276,6 +283,8 @@ typedef struct ss_plan_desc {
   uint32_t autotune;         /* 0: use options; 1: time the candidates, keep the fastest */
   uint32_t tune_repeats;     /* launches timed per candidate (0 = 5) */
   ss_options options;        /* starting / fixed configuration (timer ignored) */
+  const char* tune_cache;    /* autotune cache file, or NULL; read only when
+                                struct_size covers it */
 } ss_plan_desc;
 
 ss_status ss_plan_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uint32_t pair_capacity,

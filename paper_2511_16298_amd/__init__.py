@@ -258,15 +258,17 @@ class BatchSorter:
 class Plan:
     """A BatchSorter's pipeline captured into a HIP graph (``ss_plan_*``) for
     fixed record tensors; ``autotune`` times every compiled pass configuration
-    first.  The sorter must have been made with ``plan_workspace=True``."""
+    first.  The sorter must have been made with ``plan_workspace=True``.
+    ``tune_cache``: a file that keeps the autotuned choice per device and
+    batch size (a later plan of the same size skips the timing)."""
 
     def __init__(self, sorter: BatchSorter, records_list, autotune: bool = True, tune_repeats: int = 0,
-                 stream=None):
+                 stream=None, tune_cache=None):
         self.sorter = sorter
         self.records = list(records_list)   # keep the captured inputs alive
         st, h = _abi.ss_plan_create(sorter.frames_for(self.records), sorter._cout, sorter.workspace.data_ptr(),
                                     sorter.workspace_bytes, _stream_handle(stream), int(autotune), tune_repeats,
-                                    sorter.options)
+                                    sorter.options, tune_cache=tune_cache)
         check(st, "ss_plan_create")
         self.handle = h
 

@@ -131,7 +131,7 @@ class ss_plan_desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("n_frames", ctypes.c_uint32),
                 ("frames", ctypes.c_void_p), ("out", ss_batch_out), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("autotune", ctypes.c_uint32),
-                ("tune_repeats", ctypes.c_uint32), ("options", ss_options)]
+                ("tune_repeats", ctypes.c_uint32), ("options", ss_options), ("tune_cache", ctypes.c_char_p)]
 
 class ss_render_desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
@@ -296,7 +296,7 @@ def ss_plan_workspace_bytes(frames, pair_capacity: int):
 
 
 def ss_plan_create(frames, out: ss_batch_out, workspace, workspace_bytes, stream, autotune=0, tune_repeats=0,
-                   options=None):
+                   options=None, tune_cache=None):
     arr = _frames_array(frames)
     d = ss_plan_desc()
     d.struct_size = ctypes.sizeof(ss_plan_desc)
@@ -308,6 +308,7 @@ def ss_plan_create(frames, out: ss_batch_out, workspace, workspace_bytes, stream
     d.autotune = autotune
     d.tune_repeats = tune_repeats
     d.options = options if options is not None else make_options()
+    d.tune_cache = os.fsencode(tune_cache) if tune_cache is not None else None
     h = _P()
     st = lib().ss_plan_create(ctypes.byref(h), ctypes.byref(d), stream)
     return st, h.value

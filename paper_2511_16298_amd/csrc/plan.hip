@@ -4,10 +4,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stddef.h>
+
 #include <new>
+#include <string>
 #include <vector>
 
 #include "splatsort.h"
+#include "tunecache.hpp"
 
 struct ss_plan {
   std::vector<ss_frame> frames;
@@ -18,7 +22,7 @@ struct ss_plan {
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<double> candidate_ms;
+  std::vector<double> candidate_ms;   // empty when the choice came from the tune cache
 };
 
 namespace {
@@ -93,6 +97,45 @@ ss_status time_candidate(ss_plan* p, const ss_options& o, uint32_t repeats, hipS
   return st;
 }
 
+uint32_t log2_ceil(uint64_t x) {
+  uint32_t b = 0;
+  while ((1ull << b) < x && b < 63) ++b;
+  return b;
+}
+
+// The tune-cache key of a plan's batch on the stream's device.
+bool plan_tune_key(const ss_plan* p, hipStream_t s, ss::TuneKey* k) {
+  int dev = 0;
+  if (s != nullptr) {
+    hipDevice_t d = 0;
+    if (hipStreamGetDevice(s, &d) != hipSuccess) return false;
+    dev = static_cast<int>(d);
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return false;
+  }
+  hipDeviceProp_t prop;
+  int runtime = 0;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess || hipRuntimeGetVersion(&runtime) != hipSuccess) return false;
+  uint64_t n = 0, tiles = 0, max_tiles = 0;
+  for (const ss_frame& f : p->frames) {
+    uint32_t tx = 0, ty = 0, kb = 0;
+    if (ss_frame_geometry(&f, &tx, &ty, &kb) != SS_OK) return false;
+    const uint64_t t = static_cast<uint64_t>(tx) * ty;
+    n += f.num_gaussians;
+    tiles += t;
+    if (t > max_tiles) max_tiles = t;
+  }
+  k->arch = ss::tune_arch_token(prop.gcnArchName);
+  k->runtime = runtime;
+  k->abi = ss_abi_version();
+  k->frames_log2 = log2_ceil(p->frames.size());
+  k->gaussians_log2 = log2_ceil(n);
+  k->pairs_log2 = log2_ceil(p->out.pair_capacity);
+  k->tile_bits = log2_ceil(tiles);
+  k->frame_tile_bits = log2_ceil(max_tiles);
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -115,7 +158,10 @@ ss_status ss_plan_workspace_bytes(const ss_frame* frames, uint32_t n_frames, uin
 }
 
 ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream) {
-  if (plan == nullptr || desc == nullptr || desc->struct_size < sizeof(ss_plan_desc)) return SS_ERR_INVALID_ARGUMENT;
+  // callers built before tune_cache existed pass the shorter struct
+  if (plan == nullptr || desc == nullptr || desc->struct_size < offsetof(ss_plan_desc, tune_cache))
+    return SS_ERR_INVALID_ARGUMENT;
+  const char* cache = desc->struct_size >= sizeof(ss_plan_desc) ? desc->tune_cache : nullptr;
   if (desc->frames == nullptr || desc->n_frames == 0) return SS_ERR_INVALID_ARGUMENT;
   ss_plan* p = new (std::nothrow) ss_plan;
   if (p == nullptr) return SS_ERR_HIP;
@@ -133,7 +179,23 @@ ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream)
   ss_status st = ss_batch_workspace_bytes(p->frames.data(), desc->n_frames, p->out.pair_capacity, &p->options,
                                           &need);
   if (st == SS_OK && desc->workspace_bytes < need) st = SS_ERR_WORKSPACE;
-  if (st == SS_OK && desc->autotune) {
+  // a cached choice for this device, runtime and batch size skips the timing
+  ss::TuneKey key;
+  const bool keyed = st == SS_OK && desc->autotune && cache != nullptr && plan_tune_key(p, s, &key);
+  bool tuned = false;
+  if (keyed) {
+    ss::TuneChoice c;
+    if (ss::tune_cache_lookup(cache, key, &c)) {
+      const ss_options o = with(p->options, Candidate{c.radix_bits, c.items, c.threads, c.flags});
+      size_t b = 0;
+      if (ss_batch_workspace_bytes(p->frames.data(), desc->n_frames, p->out.pair_capacity, &o, &b) == SS_OK &&
+          b <= desc->workspace_bytes) {
+        p->options = o;
+        tuned = true;
+      }
+    }
+  }
+  if (st == SS_OK && desc->autotune && !tuned) {
     const uint32_t repeats = desc->tune_repeats ? desc->tune_repeats : 5;
     double best = 1e30;
     ss_options chosen = p->options;
@@ -160,6 +222,10 @@ ss_status ss_plan_create(ss_plan** plan, const ss_plan_desc* desc, void* stream)
       }
     }
     p->options = chosen;
+    if (st == SS_OK && keyed && best < 1e30)
+      (void)ss::tune_cache_store(cache, key, ss::TuneChoice{chosen.radix_bits, chosen.items_per_thread,
+                                                            chosen.workgroup_size,
+                                                            chosen.flags & SS_FLAG_PERSISTENT, best});
   }
   if (st == SS_OK && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
     st = SS_ERR_HIP;

@@ -254,3 +254,40 @@ def test_plan_graph_replays_match_eager():
     assert np.array_equal(u64(sorter.keys)[:m3], ref2.keys)
     assert np.array_equal(u32(sorter.values)[:m3], ref2.values)
     plan.close()
+
+
+def test_plan_tune_cache(tmp_path):
+    """The autotune cache: the first plan times the candidates and records the
+    winner; a second plan of the same batch size takes it from the file
+    without timing and sorts exactly; a batch of another size is timed and
+    recorded beside it."""
+    path = str(tmp_path / "tune.txt")
+
+    def plan_for(frames):
+        capacity = sum(int(oracle.count(w, h, r)[0].astype(np.uint64).sum()) for (w, h, r) in frames)
+        shapes = [(w, h, len(r)) for (w, h, r) in frames]
+        recs = [ss.records_to_device(r) for (_, _, r) in frames]
+        sorter = ss.BatchSorter(shapes, capacity, plan_workspace=True)
+        return sorter, ss.Plan(sorter, recs, autotune=True, tune_repeats=1, tune_cache=path)
+
+    frames = synth.make_batch(5, seed=93, n_range=(10_000, 30_000))
+    _, p1 = plan_for(frames)
+    c1 = p1.config()
+    assert len(c1["candidate_ms"]) >= 5
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("ss-tune 1 gfx")
+    p1.close()
+    sorter, p2 = plan_for(frames)
+    c2 = p2.config()
+    assert c2["candidate_ms"] == []
+    assert {k: c2[k] for k in ("radix_bits", "items_per_thread", "workgroup_size", "persistent")} == \
+        {k: c1[k] for k in ("radix_bits", "items_per_thread", "workgroup_size", "persistent")}
+    p2.launch()
+    st, m = sorter.result()
+    assert st == 0
+    check_against_oracle(frames, sorter, m)
+    p2.close()
+    _, p3 = plan_for(synth.make_batch(9, seed=94, n_range=(10_000, 30_000)))
+    assert len(p3.config()["candidate_ms"]) >= 5
+    assert len(open(path).read().splitlines()) == 2
+    p3.close()

@@ -1,7 +1,7 @@
 """Host code under sanitizers, on the CPU: the server's arena allocator and
 admission rule (a C++ driver against a reference model and a fake clock),
-and the oracle's pin suite against an AddressSanitizer + UBSan build of the
-oracle."""
+the plans' autotune cache file, and the oracle's pin suite against an
+AddressSanitizer + UBSan build of the oracle."""
 import os
 import subprocess
 import sys
@@ -23,6 +23,15 @@ def test_arena_and_admission_under_sanitizers(tmp_path):
     subprocess.check_call(["g++", "-std=c++17", "-O1", *SAN, "-I", os.path.join(ROOT, "paper_2511_16298_amd", "csrc"),
                            os.path.join(HERE, "native", "arena_test.cpp"), "-o", exe])
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert r.stdout.strip() == "OK"
+
+
+def test_tune_cache_under_sanitizers(tmp_path):
+    exe = str(tmp_path / "tunecache_test")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", *SAN, "-I", os.path.join(ROOT, "paper_2511_16298_amd", "csrc"),
+                           os.path.join(HERE, "native", "tunecache_test.cpp"), "-o", exe])
+    r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-4000:]
     assert r.stdout.strip() == "OK"
 

@@ -344,11 +344,12 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     }
     return;
   }
-  // 64-bit keys in 16-item tiles (the shape for 2^23 pairs and more, which
+  // Packed pairs in 16-item tiles (the shape for 2^23 pairs and more, which
   // outgrow the caches before the next pass reads them back): non-temporal
   // stores, measured faster there (large-6m passes 293 -> 285 us) and slower
-  // on smaller frames, whose outputs the next pass still finds in cache
-  constexpr bool kStreamStores = sizeof(K) == 8 && ITEMS == 16;
+  // on smaller frames, whose outputs the next pass still finds in cache, and
+  // in key + value passes, whose values would stay cached without their keys
+  constexpr bool kStreamStores = MODE == kPassItems && ITEMS == 16;
   uint32_t dst[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {

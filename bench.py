@@ -707,7 +707,7 @@ def bench_preprocess(args):
     print(json.dumps(line), flush=True)
 
 def bench_sweep(args):
-    """Sort alone (step a4 through ss_sort_pairs) over random 45-bit keys, the
+    """Sort alone (through ss_sort_pairs) over random 45-bit keys, the
     paper's random key-value sweep extended to 10^8 pairs."""
     import torch
     import paper_2511_16298_amd as ss

@@ -142,7 +142,7 @@ typedef struct ss_options {
  * the padded size. */
 #define SS_ALGO_BITONIC 3u
 
-/* Stop after step a3: keys/values receive the duplicated pairs in
+/* Stop after duplication: keys/values receive the duplicated pairs in
  * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no
  * ranges.  For stage-by-stage verification. */
 #define SS_FLAG_UNSORTED 1u
@@ -192,7 +192,7 @@ ss_status ss_frame_geometry(const ss_frame* frame, uint32_t* tiles_x, uint32_t* 
 ss_status ss_workspace_bytes(const ss_frame* frame, uint32_t pair_capacity,
                              const ss_options* options, size_t* bytes);
 
-/* Steps a1-a2 only: per-Gaussian tile counts, their exclusive prefix sum and
+/* Counting and scan only: per-Gaussian tile counts, their exclusive prefix sum and
  * the total M, so a caller can size the pair buffers (one 4-byte read back).
  * Any of d_tiles_touched, d_offsets may be NULL; d_num_pairs and d_status
  * are required.  Uses the same workspace as ss_sort_frame with capacity 0. */
@@ -200,9 +200,14 @@ ss_status ss_count_pairs(const ss_frame* frame, uint32_t* d_tiles_touched, uint3
                          uint32_t* d_num_pairs, uint32_t* d_status,
                          void* workspace, size_t workspace_bytes, void* stream);
 
-/* The whole hot path a1-a5 for one frame: tile-overlap counting fused with a
- * single-pass exclusive scan and the duplication into (key, value) pairs;
- * a stable LSD radix sort of the pairs over key bits [0, b); tile ranges. */
+/* The whole path for one frame: count, scan, duplicate, sort, and identify
+ * the tile ranges (Background, "Duplication with Tiles" and "Sorting"; the
+ * Evaluation's stage table lists the same steps).  By default (depth-first)
+ * the Gaussians are sorted by depth, their pairs written in depth order and
+ * then sorted stably by tile id alone; frames of at most 256 tiles and
+ * 16,384 Gaussians (without tiles_touched / offsets outputs) take a
+ * two-kernel path; SS_ALGO_DIRECT counts, scans and duplicates in index
+ * order and sorts key bits [0, b).  Every path gives the same output. */
 ss_status ss_sort_frame(const ss_frame* frame, const ss_frame_out* out,
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
@@ -247,7 +252,7 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
                         void* workspace, size_t workspace_bytes, void* stream,
                         const ss_options* options);
 
-/* Batched sizing (steps a1-a2 for many frames): the pair count of every
+/* Batched sizing (counting and scan for many frames): the pair count of every
  * frame, written to d_frame_pairs[n_frames] (saturated at 2^32 - 1), their
  * sum to *d_num_pairs, and SS_OK / SS_ERR_OVERFLOW / SS_ERR_INVALID_INPUT to
  * *d_status.  Nothing else is written. */
@@ -345,7 +350,7 @@ ss_status ss_server_stats(ss_server* server, ss_server_counters* out);
 /* Drains every submitted request, then stops the scheduler. */
 void ss_server_destroy(ss_server* server);
 
-/* Step a4 alone on caller data (the paper's random key-value sort benchmark,
+/* The sort alone on caller data (the paper's random key-value sort benchmark,
  * Evaluation, "Datasets"): stable sort of n pairs by key bits [0, key_bits);
  * keys must be < 2^key_bits.  keys_in/values_in are not modified; they may
  * not alias the outputs.  Workspace: ss_sort_pairs_workspace_bytes. */
@@ -458,9 +463,9 @@ ss_status ss_preprocess(const ss_camera* camera, const ss_preprocess_desc* desc,
 
 typedef enum ss_kernel_kind {
   SS_KERNEL_CLEAR = 0,      /* zeroes counters and look-back state */
-  SS_KERNEL_COUNT_DUP = 1,  /* direct: a1+a2+a3 fused; depth-first: a1 (counts, keys) */
-  SS_KERNEL_SORT_PASS = 2,  /* one a4 digit pass */
-  SS_KERNEL_RANGES = 3,     /* a5 */
+  SS_KERNEL_COUNT_DUP = 1,  /* direct: count, scan and duplicate fused; depth-first: count and keys */
+  SS_KERNEL_SORT_PASS = 2,  /* one digit pass of the sort over the pairs */
+  SS_KERNEL_RANGES = 3,     /* tile ranges */
   SS_KERNEL_COPY = 4,       /* ss_copy_bytes */
   SS_KERNEL_HIST = 5,       /* digit histograms of caller keys (ss_sort_pairs) */
   SS_KERNEL_DIGIT_BASES = 6, /* pair totals of ss_batch_count_pairs (sort passes derive

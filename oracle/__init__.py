@@ -140,7 +140,7 @@ def tile_grid(width: int, height: int, tile_px: int = 16):
 
 
 def count(width: int, height: int, records: np.ndarray, tile_px: int = 16):
-    """Step a1 alone: (tiles_touched[N], rects[N,4] = x0, x1, y0, y1)."""
+    """Counting alone: (tiles_touched[N], rects[N,4] = x0, x1, y0, y1)."""
     fr, rec = _frame(width, height, records, tile_px)
     n = len(rec)
     cnt = np.zeros(n, np.uint32)
@@ -152,7 +152,7 @@ def count(width: int, height: int, records: np.ndarray, tile_px: int = 16):
 
 
 def scan(counts: np.ndarray):
-    """Step a2 alone: (offsets[N] uint64, total)."""
+    """The scan alone: (offsets[N] uint64, total)."""
     c = np.ascontiguousarray(counts, dtype=np.uint32)
     off = np.zeros(len(c), np.uint64)
     tot = ctypes.c_uint64()
@@ -163,7 +163,7 @@ def scan(counts: np.ndarray):
 
 def duplicate(width: int, height: int, records: np.ndarray, offsets: np.ndarray, num_pairs: int,
               tile_px: int = 16):
-    """Step a3 alone: the unsorted (keys, values) from the a2 offsets."""
+    """Duplication alone: the unsorted (keys, values) from the scan's offsets."""
     fr, rec = _frame(width, height, records, tile_px)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     k = np.zeros(num_pairs, np.uint64)
@@ -175,7 +175,7 @@ def duplicate(width: int, height: int, records: np.ndarray, offsets: np.ndarray,
 
 
 def sort_pairs(keys: np.ndarray, values: np.ndarray):
-    """Step a4 alone on copies: stable sort by the 64-bit key."""
+    """The sort alone on copies: stable sort by the 64-bit key."""
     k = np.array(keys, dtype=np.uint64, copy=True)
     v = np.array(values, dtype=np.uint32, copy=True)
     assert lib().oracle_sort(_ptr(k), _ptr(v), len(k)) == OK
@@ -183,7 +183,7 @@ def sort_pairs(keys: np.ndarray, values: np.ndarray):
 
 
 def ranges(sorted_keys: np.ndarray, num_tiles: int) -> np.ndarray:
-    """Step a5 alone: (T, 2) start/end."""
+    """Range identification alone: (T, 2) start/end."""
     k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
     r = np.zeros((num_tiles, 2), np.uint32)
     st = lib().oracle_ranges(_ptr(k), len(k), num_tiles, _ptr(r))
@@ -194,9 +194,9 @@ def ranges(sorted_keys: np.ndarray, num_tiles: int) -> np.ndarray:
 
 def sort_frame(width: int, height: int, records: np.ndarray, tile_px: int = 16,
                capacity: Optional[int] = None, stages: bool = True) -> FrameResult:
-    """Whole frame, a1..a5.  With ``capacity=None`` the pair buffers are sized
+    """Whole frame: count, scan, duplicate, sort, ranges.  With ``capacity=None`` the pair buffers are sized
     to the exact M (a first call counts).  ``stages`` also returns the
-    per-Gaussian counts, offsets and the unsorted a3 order."""
+    per-Gaussian counts, offsets and the unsorted duplication order."""
     fr, rec = _frame(width, height, records, tile_px)
     n = len(rec)
     if tile_px != 16 or width < 1 or height < 1:

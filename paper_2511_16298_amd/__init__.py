@@ -357,7 +357,7 @@ class Server:
 
 
 def count_pairs(records, width: int, height: int, stream=None):
-    """Steps a1-a2: (tiles_touched, offsets, num_pairs, status) device tensors."""
+    """Counting and scan: (tiles_touched, offsets, num_pairs, status) device tensors."""
     torch = _torch()
     dev = records.device
     f = _frame(records, width, height)
@@ -395,7 +395,7 @@ def sort_frame(records, width: int, height: int, capacity: Optional[int] = None,
 
 def sort_pairs(keys, values, key_bits: int, stream=None, radix_bits: int = 0, items_per_thread: int = 0,
                timer: Optional[Timer] = None, workgroup_size: int = 0, algorithm: int = 0):
-    """Step a4 alone: stable sort of (int64 keys, int32 values) by key bits
+    """The sort alone: stable sort of (int64 keys, int32 values) by key bits
     [0, key_bits) (``SS_ALGO_BITONIC``: by (key bits, value)).  Returns new
     (keys, values) tensors."""
     torch = _torch()

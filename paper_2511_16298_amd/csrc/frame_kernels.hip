@@ -45,12 +45,12 @@ __global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, s
 
 // Workgroup b takes the 1024 consecutive Gaussians of tile b (look-back order
 // as described in common.hpp).
-//  a1: overlap rectangle of each Gaussian's open bounding box with the tile
+//  count: overlap rectangle of each Gaussian's open bounding box with the tile
 //      grid, in 1/16-px integers: x0 = floor((X - 16 r) / 256),
 //      x1 = ceil((X + 16 r) / 256), clamped to [0, tiles_x]; radius 0 culls.
-//  a2: workgroup scan of the counts, then a decoupled look-back over earlier
+//  scan: workgroup scan of the counts, then a decoupled look-back over earlier
 //      workgroups' aggregates gives the global exclusive offset.
-//  a3: the workgroup's pairs are spread evenly over its threads: thread t
+//  duplicate: the workgroup's pairs are spread evenly over its threads: thread t
 //      writes local pairs t, t + 256, ...; each finds its Gaussian by a
 //      10-step search of the local offsets in LDS, so a Gaussian covering a
 //      thousand tiles costs no more than a thousand small ones.  Keys are
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_dup(CountDupArgs a) {
   const uint32_t ticket = blockIdx.x;
   const uint64_t gbase = static_cast<uint64_t>(ticket) * kCountTile;
 
-  // ---- a1 (striped, coalesced 16-byte loads) ----
+  // ---- count (striped, coalesced 16-byte loads) ----
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < kCountItems; ++j) {
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_dup(CountDupArgs a) {
   }
   const bool any_bad = __syncthreads_or(bad);
 
-  // ---- a2: workgroup scan (blocked: thread t owns Gaussians 4t .. 4t+3) ----
+  // ---- scan: workgroup scan (blocked: thread t owns Gaussians 4t .. 4t+3) ----
   uint32_t c[kCountItems];
   uint64_t tsum = 0;
 #pragma unroll
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_dup(CountDupArgs a) {
     }
   }
 
-  // ---- a2: decoupled look-back over earlier workgroups (wave 0) ----
+  // ---- scan: decoupled look-back over earlier workgroups (wave 0) ----
   if (tid < kWave) {
     const uint32_t lane = tid;
     const uint64_t mine = (btotal > kCountSat ? kCountSat : btotal) | (any_bad ? kLbBad64 : 0);
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_dup(CountDupArgs a) {
   }
   if (!DUP) return;
 
-  // ---- a3: duplicate, spread evenly over the workgroup ----
+  // ---- duplicate, spread evenly over the workgroup ----
   uint32_t q_end = 0;
   if (prefix < a.capacity) {
     const uint64_t room = a.capacity - prefix;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
 
 // Exclusive prefix over digits of the global digit totals of every pass
 // (the histogram copies summed).  One workgroup of 256 threads per pass.
-// a5: thread i compares the tile of pair i - 1 with the tile of pair i
+// Tile ranges: thread i compares the tile of pair i - 1 with the tile of pair i
 // (tile -1 before the first pair, tile T after the last).  At a change from
 // a to b it closes a at i, gives every tile strictly between a and b the
 // empty range [i, i), and opens b at i.  Every range word is written by

@@ -103,7 +103,7 @@ def check_brute_force(cases: int = 150, seed: int = 7):
         assert np.array_equal(res.keys, k), (W, H)
         assert np.array_equal(res.values, v), (W, H)
         assert np.array_equal(res.ranges, rng), (W, H)
-        # stage outputs: per-Gaussian counts and the a3 order (row-major tiles)
+        # stage outputs: per-Gaussian counts and the duplication order (row-major tiles)
         cnt = np.array([len(t) for t in per_g], np.uint32)
         assert np.array_equal(res.tiles_touched, cnt)
         for g, tiles in enumerate(per_g):

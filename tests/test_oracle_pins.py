@@ -32,7 +32,7 @@ def test_invariants_large_scaled_down():
 
 
 def test_stage_functions_compose():
-    """a1..a5 called one by one give the whole-frame result."""
+    """Count, scan, duplicate, sort and ranges called one by one give the whole-frame result."""
     spec, seed = synth.FRAME_WORKLOADS["small-256x256"]
     rec = synth.make_frame(spec, seed)
     res = oracle.sort_frame(spec.width, spec.height, rec)

@@ -102,6 +102,24 @@ def test_segmented_batch_frames_smaller_than_a_workgroup():
         check_against_oracle(frames, b, m)
 
 
+def test_batch_of_256_frames():
+    """The most frames a batch takes (256): the per-frame tables in LDS, one
+    publishing workgroup and one range fix-up workgroup per frame; frames of
+    0 to 3,000 Gaussians on grids of 1 to 8,160 tiles, some sharing an
+    expansion workgroup with a dozen others."""
+    rs = np.random.default_rng(256)
+    sizes = [(16, 16), (64, 48), (320, 180), (640, 360), (1920, 1080), (1000, 16)]
+    frames = []
+    for f in range(256):
+        w, h = sizes[int(rs.integers(len(sizes)))]
+        n = int(rs.choice([0, 1, 17, 150, 600, 3000]))
+        frames.append((w, h, synth.make_frame(synth.FrameSpec(w, h, n), 9000 + f)))
+    for kw in ({}, {"persistent": True}):
+        b, st, m = run_batch(frames, **kw)
+        assert st == 0, kw
+        check_against_oracle(frames, b, m)
+
+
 def test_segmented_and_whole_batch_agree():
     """The same frames through the segmented tile passes (default) and the
     whole-batch ones (dropping culled Gaussians keeps the batch whole, as do

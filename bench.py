@@ -69,7 +69,8 @@ def parse():
     p.add_argument("--radix-bits", type=int, default=0)
     p.add_argument("--items", type=int, default=0)
     p.add_argument("--wg", type=int, default=0, help="sort-pass workgroup size")
-    p.add_argument("--algorithm", default="depth-first", choices=["depth-first", "direct", "bitonic", "bitonic-key32"],
+    p.add_argument("--algorithm", default="depth-first",
+                   choices=["depth-first", "direct", "bitonic", "bitonic-key32", "tile-first"],
                    help="frame sort algorithm (frames, sweep); bitonic-key32 = the paper's normalised "
                         "32-bit float key (lossy within a tile, frames only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -814,7 +815,8 @@ def time_frame(args, workload: str, steps: int, warmup: int, dev, stream, kernel
     assert int(s_t.item()) == 0
     M = int(m_t.item()) & 0xFFFFFFFF
     algo = {"depth-first": ss.SS_ALGO_DEPTH_FIRST, "direct": ss.SS_ALGO_DIRECT,
-            "bitonic": ss.SS_ALGO_BITONIC, "bitonic-key32": ss.SS_ALGO_BITONIC}[args.algorithm]
+            "bitonic": ss.SS_ALGO_BITONIC, "bitonic-key32": ss.SS_ALGO_BITONIC,
+            "tile-first": ss.SS_ALGO_TILE_FIRST}[args.algorithm]
     key32 = args.algorithm == "bitonic-key32"
     sorter = ss.FrameSorter(spec.width, spec.height, len(rec), M, args.radix_bits, args.items, device=dev,
                             workgroup_size=args.wg, algorithm=algo, key32=key32)
@@ -852,7 +854,7 @@ def time_frame(args, workload: str, steps: int, warmup: int, dev, stream, kernel
         for name, kind in (("clear", _abi.SS_KERNEL_CLEAR), ("count", _abi.SS_KERNEL_COUNT_DUP),
                            ("digit_bases", _abi.SS_KERNEL_DIGIT_BASES), ("depth_pass", _abi.SS_KERNEL_DEPTH_PASS),
                            ("expand", _abi.SS_KERNEL_EXPAND), ("sort_pass", _abi.SS_KERNEL_SORT_PASS),
-                           ("ranges", _abi.SS_KERNEL_RANGES)):
+                           ("ranges", _abi.SS_KERNEL_RANGES), ("tile_sort", _abi.SS_KERNEL_TILE_SORT)):
             ms, n = timer.read(kind)
             if n:
                 kern[name] = {"launches": n, "avg_us": 1e3 * ms / n, "us_per_step": 1e3 * ms / steps}

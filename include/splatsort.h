@@ -141,6 +141,12 @@ typedef struct ss_options {
  * when the values of equal keys increase in input order.  Workspace grows to
  * the padded size. */
 #define SS_ALGO_BITONIC 3u
+/* SS_ALGO_TILE_FIRST (frames only): duplicate in index order, sort the pairs
+ * stably by tile id alone (as depth-first does), then sort each tile's run
+ * stably by depth, one workgroup per tile: in LDS up to 8,192 pairs, longer
+ * runs in chunks through the workspace.  The depth sort of the Gaussians is
+ * not needed.  Same output as the other algorithms. */
+#define SS_ALGO_TILE_FIRST 4u
 
 /* Stop after duplication: keys/values receive the duplicated pairs in
  * duplication order (Gaussian by Gaussian, tiles row-major); no sort and no
@@ -474,7 +480,8 @@ typedef enum ss_kernel_kind {
   SS_KERNEL_EXPAND = 8,     /* depth-first: pairs in depth order */
   SS_KERNEL_RENDER = 9,     /* ss_render_frame */
   SS_KERNEL_PREPROCESS = 10, /* ss_preprocess */
-  SS_KERNEL_KINDS = 11
+  SS_KERNEL_TILE_SORT = 11, /* tile-first: each tile's run sorted by depth */
+  SS_KERNEL_KINDS = 12
 } ss_kernel_kind;
 
 /* Event pool for per-kernel timing.  Create once (host), pass in

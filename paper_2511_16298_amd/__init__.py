@@ -15,14 +15,15 @@ import dataclasses
 from typing import Optional
 
 from . import _abi
-from ._abi import (SS_ALGO_AUTO, SS_ALGO_BITONIC, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_OK, SplatSortError, check,
+from ._abi import (SS_ALGO_AUTO, SS_ALGO_BITONIC, SS_ALGO_DEPTH_FIRST, SS_ALGO_DIRECT, SS_ALGO_TILE_FIRST, SS_OK,
+                   SplatSortError, check,
                    make_options, ss_batch_out, ss_frame, ss_frame_out)
 
 __all__ = ["FrameSorter", "BatchSorter", "Plan", "Server", "Renderer", "render_attrs_to_device",
            "Preprocessor", "PreprocessOutput", "camera", "sort_frame",
            "count_pairs", "sort_pairs", "copy_bytes", "Timer",
            "records_to_device", "SplatSortError", "geometry", "SS_ALGO_AUTO", "SS_ALGO_DEPTH_FIRST",
-           "SS_ALGO_DIRECT", "SS_ALGO_BITONIC"]
+           "SS_ALGO_DIRECT", "SS_ALGO_BITONIC", "SS_ALGO_TILE_FIRST"]
 
 
 def _torch():

@@ -34,12 +34,14 @@ SS_KERNEL_DEPTH_PASS = 7
 SS_KERNEL_EXPAND = 8
 SS_KERNEL_RENDER = 9
 SS_KERNEL_PREPROCESS = 10
+SS_KERNEL_TILE_SORT = 11
 SS_RENDER_EXACT = 1
 
 SS_ALGO_AUTO = 0
 SS_ALGO_DEPTH_FIRST = 1
 SS_ALGO_DIRECT = 2
 SS_ALGO_BITONIC = 3
+SS_ALGO_TILE_FIRST = 4
 SS_MAX_BATCH_FRAMES = 256
 
 SS_FLAG_UNSORTED = 1

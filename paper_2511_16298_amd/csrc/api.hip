@@ -52,7 +52,7 @@ ss_status parse_options(const ss_options* o, Options* out) {
     out->spin_limit = o->spin_limit;
     out->fault = o->fault;
   }
-  if (o->algorithm > SS_ALGO_BITONIC) return SS_ERR_UNSUPPORTED;
+  if (o->algorithm > SS_ALGO_TILE_FIRST) return SS_ERR_UNSUPPORTED;
   // the normalised 32-bit key belongs to the bitonic network and needs the sort
   if ((o->flags & SS_FLAG_KEY32_LOSSY) != 0 &&
       (o->algorithm != SS_ALGO_BITONIC || (o->flags & SS_FLAG_UNSORTED) != 0))
@@ -579,6 +579,14 @@ struct DfIO {
   uint32_t* frame_pair_base;    // batch only, may be NULL
 };
 
+// Tile-first: every tile's run (index order, after the tile passes) sorted
+// stably by depth; runs too long for LDS use the alternate pair buffer.
+ss_status sort_tile_runs(Launcher& L, const DfLayout& lay, const DfIO& io, void* ws, uint32_t* d_status,
+                         hipStream_t s) {
+  TileSortArgs t{io.keys, io.values, io.ranges, lay.total_tiles, at<uint64_t>(ws, lay.alt_keys), d_status};
+  return L.run(SS_KERNEL_TILE_SORT, [&] { return launch_tile_sort(t, s); });
+}
+
 ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, const DfIO& io, void* ws,
                           hipStream_t s) {
   uint32_t* scal = at<uint32_t>(ws, lay.scalars);
@@ -633,14 +641,18 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   ck.block_total = at<unsigned long long>(ws, lay.block_total);
   ck.block_frame = at<uint32_t>(ws, lay.block_frame);
   ck.bad = at<uint32_t>(ws, lay.bad);
+  // Tile-first (frames): no depth sort; the pairs are written in index
+  // order, partitioned stably by tile, and each tile's run is sorted by
+  // depth at the end.
+  const bool tile_first = o.algorithm == SS_ALGO_TILE_FIRST;
   // with SS_FLAG_DROP_CULLED: Gaussians the depth sort keeps, stored by its first pass
-  uint32_t* live = (o.flags & SS_FLAG_DROP_CULLED) != 0 ? scal + 4 : nullptr;
+  uint32_t* live = (o.flags & SS_FLAG_DROP_CULLED) != 0 && !tile_first ? scal + 4 : nullptr;
   SS_TRY(L.run(SS_KERNEL_COUNT_DUP, [&] { return launch_count_keys(ck, s); }));
 
   // stable sort of the Gaussians by depth: key -> alt -> key -> alt -> key;
   // culled ones (no pairs) sort last, or, with SS_FLAG_DROP_CULLED and when
   // they are many, the first pass drops them and the others sort the rest
-  {
+  if (!tile_first) {
     const void* ks[4] = {key, key_alt, key, key_alt};
     const uint32_t* vs[4] = {val, val_alt, val, val_alt};
     void* kd[4] = {key_alt, key, key_alt, key};
@@ -676,7 +688,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
     c.spin_limit = o.spin_limit;
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
-  // the Gaussians in (frame-major when segmented) depth order
+  // the Gaussians in (frame-major when segmented) depth order; tile-first:
+  // in index order, as the count kernel wrote them
   const uint32_t* skey = lay.seg ? key_alt : key;
   const uint32_t* sval = lay.seg ? val_alt : val;
   const uint32_t* srect32 = lay.seg ? rect32_alt : rect32;
@@ -722,6 +735,11 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.status = d_status;
   e.nblocks = lay.eblocks;
   e.spin_limit = o.spin_limit;
+  if (tile_first && lay.packed) {
+    e.top_hist = ck.hist + 3 * 256;
+    e.top_hist_stride = 4 * 256;
+    e.depth_top_out = scal + 5;
+  }
   e.packed = lay.packed;
   e.pk = pk;
   e.seg = lay.seg;
@@ -787,15 +805,17 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
           return launch_ranges_fix_seg(io.keys, d_status, bases_t + static_cast<size_t>(P - 1) * lay.tbins,
                                        1u << last_rb, P * lay.tbins, seg_base, table, lay.n_frames, io.ranges, s);
         });
-      return L.run(SS_KERNEL_RANGES, [&] {
+      SS_TRY(L.run(SS_KERNEL_RANGES, [&] {
         return launch_ranges_fix(io.keys, d_num_pairs, d_status, bases_t + static_cast<size_t>(P - 1) * lay.tbins,
                                  1u << last_rb, lay.total_tiles, io.ranges, s);
-      });
+      }));
+      return tile_first ? sort_tile_runs(L, lay, io, ws, d_status, s) : SS_OK;
     }
   }
-  return L.run(SS_KERNEL_RANGES, [&] {
+  SS_TRY(L.run(SS_KERNEL_RANGES, [&] {
     return launch_ranges(io.keys, d_num_pairs, d_status, lay.capacity, lay.total_tiles, io.ranges, s);
-  });
+  }));
+  return tile_first ? sort_tile_runs(L, lay, io, ws, d_status, s) : SS_OK;
 }
 
 // ----------------------------- small frames --------------------------------
@@ -1086,7 +1106,7 @@ ss_status ss_batch_workspace_bytes(const ss_frame* frames, uint32_t n_frames, ui
   SS_TRY(batch_shape(frames, n_frames, &b));
   Options o;
   SS_TRY(parse_options(options, &o));
-  if (use_direct(o)) return SS_ERR_UNSUPPORTED;
+  if (use_direct(o) || o.algorithm == SS_ALGO_TILE_FIRST) return SS_ERR_UNSUPPORTED;
   *bytes = make_df_layout(static_cast<uint32_t>(b.n), n_frames, pair_capacity, b.tiles, o, b.max_n, b.max_tiles).total;
   return SS_OK;
 }
@@ -1097,7 +1117,7 @@ ss_status ss_sort_batch(const ss_frame* frames, uint32_t n_frames, const ss_batc
   SS_TRY(batch_shape(frames, n_frames, &b));
   Options o;
   SS_TRY(parse_options(options, &o));
-  if (use_direct(o)) return SS_ERR_UNSUPPORTED;
+  if (use_direct(o) || o.algorithm == SS_ALGO_TILE_FIRST) return SS_ERR_UNSUPPORTED;
   if (out == nullptr || out->tile_ranges == nullptr) return SS_ERR_INVALID_ARGUMENT;
   const uint32_t cap = out->pair_capacity;
   if (cap > SS_MAX_PAIR_CAPACITY) return SS_ERR_INVALID_ARGUMENT;

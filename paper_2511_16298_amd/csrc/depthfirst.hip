@@ -290,8 +290,40 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     f_hi = frame_of(s_tab, a.n_frames, min(base + kExpandTile, a.n) - 1);
   }
   const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;  // Gaussians the depth sort kept
+  uint32_t top_max = 0, top_min = 0;
+  if (a.packed) {
+    if (a.top_hist != nullptr) {
+      // the top-byte range of the live depth keys, from the histogram
+      // (bins below 128: positive depths; bin 255 holds the culled)
+      if (tid == 0) {
+        s_first = 0;      // max, reusing the look-back's words before the look-back
+        s_retry = 0xFFu;  // min
+      }
+      __syncthreads();
+      if (tid < 128) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kHistCopies; ++k) c += a.top_hist[static_cast<size_t>(k) * a.top_hist_stride + tid];
+        if (c != 0) {
+          atomicMax(&s_first, tid);
+          atomicMin(&s_retry, tid);
+        }
+      }
+      __syncthreads();
+      top_max = s_first;
+      top_min = s_retry <= s_first ? s_retry : 0u;
+      __syncthreads();
+      if (blockIdx.x == 0 && tid == 0 && a.depth_top_out != nullptr) {
+        a.depth_top_out[0] = top_max;
+        a.depth_top_out[1] = top_min;
+      }
+    } else {
+      top_max = a.pk.depth_top[0];
+      top_min = a.pk.depth_top[1];
+    }
+  }
   uint32_t ebase = 0;
-  const bool trimmed = a.packed && packed_depth_trimmed(a.pk.depth_top[0], a.pk.depth_top[1], a.pk, &ebase);
+  const bool trimmed = a.packed && packed_depth_trimmed(top_max, top_min, a.pk, &ebase);
 
   // ---- Gaussians of this workgroup: striped loads, per-Gaussian info ----
 #pragma unroll

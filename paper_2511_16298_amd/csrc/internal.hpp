@@ -230,6 +230,13 @@ struct ExpandArgs {
   uint32_t* status;
   uint32_t nblocks;
   uint32_t spin_limit;      // look-back polls before SS_ERR_TIMEOUT (0: kSpinLimit)
+  // Gaussians in index order (tile-first): no depth sort ran, so every
+  // workgroup takes the live depth keys' top-byte range from the count
+  // kernel's top-byte histogram (copies top_hist_stride apart), and
+  // workgroup 0 stores it at depth_top_out for the tile passes
+  const uint32_t* top_hist;
+  uint32_t top_hist_stride;
+  uint32_t* depth_top_out;
   PairTotalsArgs totals;    // finished by workgroup 0
 };
 
@@ -270,6 +277,19 @@ hipError_t launch_ranges_fix_seg(const uint64_t* keys, const uint32_t* status, c
 // The compiled digit width (>= bits) that a pass of this shape can use when
 // its digit has only `bits` significant bits, or 0 (use radix_bits).
 int narrow_pass_bits(int bits, int key_bytes, int radix_bits, int items, int threads);
+
+// Tile-first ordering (see tilesort.hip): every tile's run of pairs, in
+// Gaussian index order, sorted stably by depth, one workgroup per tile.
+constexpr uint32_t kTileSortCap = 8192;   // pairs of a run sorted in LDS
+struct TileSortArgs {
+  uint64_t* keys;           // [M] tile << 32 | depth bits, runs by tile
+  uint32_t* values;         // [M] Gaussian index
+  const uint32_t* ranges;   // [2 num_tiles] each tile's run
+  uint32_t num_tiles;
+  uint64_t* alt;            // [M] scratch for runs longer than kTileSortCap
+  const uint32_t* status;   // or NULL
+};
+hipError_t launch_tile_sort(const TileSortArgs& a, hipStream_t s);
 
 // Small frames in two kernels (see tiny.hip): at most kTinyMaxTiles tiles
 // and kTinyMaxGaussians Gaussians, one frame.

@@ -174,7 +174,11 @@ def test_batch_argument_errors():
 
 def test_algorithm_option_validated():
     f = frame(n=10, ptr=1 << 12)
-    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=4))[0] == _abi.SS_ERR_UNSUPPORTED
+    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=5))[0] == _abi.SS_ERR_UNSUPPORTED
+    # tile-first: frames only
+    assert _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=_abi.SS_ALGO_TILE_FIRST))[0] == _abi.SS_OK
+    assert _abi.ss_batch_workspace_bytes([f, f], 100, _abi.make_options(algorithm=_abi.SS_ALGO_TILE_FIRST))[0] == \
+        _abi.SS_ERR_UNSUPPORTED
     a = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=1))
     b = _abi.ss_workspace_bytes(f, 100, _abi.make_options(algorithm=2))
     assert a[0] == b[0] == _abi.SS_OK and a[1] != b[1]

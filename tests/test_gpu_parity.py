@@ -29,7 +29,7 @@ def u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT, ss.SS_ALGO_BITONIC]
+ALGOS = [ss.SS_ALGO_DEPTH_FIRST, ss.SS_ALGO_DIRECT, ss.SS_ALGO_BITONIC, ss.SS_ALGO_TILE_FIRST]
 
 
 def gpu_frame(W, H, rec, capacity=None, radix_bits=0, items=0, stages=True, unsorted=False, algorithm=0,
@@ -453,6 +453,29 @@ def test_timeout_raised_from_the_host_frame():
     st, m = out.result()
     assert st == 0 and m == o.num_pairs
     assert np.array_equal(u64(out.keys)[:m], o.keys)
+
+
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 20_000])
+@pytest.mark.parametrize("depths", ["random", "low-byte", "ties"])
+def test_tile_first_long_runs(n, depths):
+    """Tile-first runs around and above what LDS holds (8,192 pairs), the
+    longer ones sorted through the workspace chunk by chunk: one tile of a
+    4 x 4 grid gets n pairs, every tile gets the 500 Gaussians that cover the
+    grid.  Depths random, differing only in their low byte (one pass), or
+    from a few values (index order decides)."""
+    rs = np.random.default_rng(n + len(depths))
+    rec = blank(n + 500)
+    rec["mean_x"][:n] = rec["mean_y"][:n] = 16 * 24     # centre of tile (1, 1)
+    rec["radius"][:n] = 1
+    rec["mean_x"][n:] = rec["mean_y"][n:] = 16 * 32
+    rec["radius"][n:] = 40                               # the whole 64 x 64 frame
+    if depths == "random":
+        rec["depth"] = rs.uniform(0.5, 300.0, n + 500).astype(np.float32)
+    elif depths == "low-byte":
+        rec["depth"] = (np.uint32(0x3F800000) + rs.integers(0, 256, n + 500).astype(np.uint32)).view(np.float32)
+    else:
+        rec["depth"] = rs.choice(np.float32([1.0, 2.0, 4.5]), n + 500)
+    assert_same(64, 64, rec, gpu_frame(64, 64, rec, stages=False, algorithm=ss.SS_ALGO_TILE_FIRST), stages=False)
 
 
 def tiny_path_frames():

@@ -778,21 +778,20 @@ def packed_pairs(n: int, max_frame_n: int, tile_bits: int, tile_passes: int) -> 
 def step_bytes_model(n: int, m: int, tiles_x: int, tiles_y: int, key_bits: int, rb: int = 8) -> tuple:
     """(depth-first step bytes, direct-path bytes, tile passes, packed) of one frame.
 
-    Depth-first, frames of at most 256 tiles per axis and at most 2^23
-    Gaussians: count 16N read + 12N write (packed rectangle, depth key,
-    index), four depth passes 24N each (the rectangle rides with the index),
-    expand 12N read.  Then, with packed 64-bit pairs: expand writes 8M, the
+    Depth-first, frames of at most 256 tiles per axis: count 16N read + 12N
+    write (packed rectangle, depth key, index), four depth passes 24N each
+    (the rectangle rides with the index), expand 12N read.  Then, with packed 64-bit pairs: expand writes 8M, the
     Pt - 1 first tile passes 16M each, the last one reads 8M and writes the
     12-byte pairs and the ranges (8T) -- 136 N + (12 + 16 Pt) M + 8 T;
     otherwise expand writes 12M, each tile pass moves 24M and the ranges
-    kernel reads 8M and writes 8T -- 136 N + (20 + 24 Pt) M + 8 T.  Larger
-    frames: 16N count write, 16N per depth pass, expand 8N read + 8N
-    rectangle gather -- 112 N + ....  The direct path would move
+    kernel reads 8M and writes 8T -- 136 N + (20 + 24 Pt) M + 8 T.  Frames
+    wider or taller than 256 tiles: 16N count write, 16N per depth pass,
+    expand 8N read + 8N rectangle gather -- 112 N + ....  The direct path would move
     48 N + (28 + 24 P) M + 8 T."""
     tile_bits = key_bits - 32
     tile_passes = -(-tile_bits // rb)
     passes = -(-key_bits // rb)
-    per_gaussian = 136.0 if tiles_x <= 256 and tiles_y <= 256 and n <= (1 << 23) else 112.0
+    per_gaussian = 136.0 if tiles_x <= 256 and tiles_y <= 256 else 112.0
     packed = packed_pairs(n, n, tile_bits, tile_passes)
     per_pair = (12.0 + 16.0 * tile_passes) if packed else (20.0 + 24.0 * tile_passes)
     step = per_gaussian * n + per_pair * m + 8.0 * tiles_x * tiles_y

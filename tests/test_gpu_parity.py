@@ -478,6 +478,19 @@ def test_tile_first_long_runs(n, depths):
     assert_same(64, 64, rec, gpu_frame(64, 64, rec, stages=False, algorithm=ss.SS_ALGO_TILE_FIRST), stages=False)
 
 
+def test_frame_above_2_23_gaussians():
+    """A single frame of more than 2^23 Gaussians (9M, of which 2% touch the
+    image): the depth sort carries the packed rectangles past the size where
+    batches stop doing so."""
+    W, H, n = 1920, 1080, 9_000_000
+    rec = synth.make_frame(synth.FrameSpec(W, H, 180_000), 9100)
+    big = np.zeros(n, dtype=synth.RECORD_DTYPE)
+    idx = np.random.default_rng(9101).choice(n, 180_000, replace=False)
+    big[idx] = rec
+    big["depth"][big["radius"] == 0] = 1.0
+    assert_same(W, H, big, gpu_frame(W, H, big, stages=False), stages=False)
+
+
 def tiny_path_frames():
     """Frames the two-kernel small-frame path takes (at most 256 tiles and
     16,384 Gaussians, no per-Gaussian outputs asked for), with its edges."""

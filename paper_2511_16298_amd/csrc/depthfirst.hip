@@ -19,7 +19,7 @@
 namespace ss {
 namespace {
 
-constexpr uint32_t kCountKeysThreads = 256;
+constexpr uint32_t kCountKeysThreads = 512;
 constexpr uint32_t kCountKeysItems = kCountKeysTile / kCountKeysThreads;
 constexpr unsigned long long kCulledOne = 1ull << 48;  // culled count, above the pair count
 constexpr uint32_t kExpandThreads = 512;
@@ -47,9 +47,9 @@ __global__ void k_put_table(TableChunk c, FrameInfo* __restrict__ table) {
   if (threadIdx.x < c.count) table[c.first + threadIdx.x] = c.f[threadIdx.x];
 }
 
-// Step 1.  1024 Gaussians per workgroup, loaded striped (coalesced 16-byte
-// loads).  No scan here: only totals (all pairs and per frame) by atomics,
-// and the four depth-digit histograms of the Gaussian sort.
+// Step 1.  2048 Gaussians per workgroup of 512 threads, loaded striped
+// (coalesced 16-byte loads).  No scan here: only totals (all pairs and per
+// frame) by atomics, and the four depth-digit histograms of the Gaussian sort.
 __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs a) {
   __shared__ FrameInfo s_tab[kMaxFrames];
   __shared__ uint32_t s_hist[4 * 256];
@@ -120,8 +120,8 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
     tsum += cnt;
   }
   const bool any_bad = __syncthreads_or(bad);
-  // one scan sums the pairs (below 2^42: 1,024 Gaussians of at most 2^32
-  // tiles) and, from bit 48, the culled Gaussians (at most 1,024)
+  // one scan sums the pairs (below 2^43: 2,048 Gaussians of at most 2^32
+  // tiles) and, from bit 48, the culled Gaussians (at most 2,048)
   unsigned long long both;
   block_exclusive_scan<unsigned long long, kCountKeysThreads>(tsum, s_tmp, both);
   const unsigned long long btotal = both & (kCulledOne - 1);

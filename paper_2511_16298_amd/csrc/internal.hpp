@@ -244,7 +244,7 @@ hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s
 hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s);
 hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
-constexpr uint32_t kCountKeysTile = 1024;   // Gaussians per count workgroup
+constexpr uint32_t kCountKeysTile = 2048;   // Gaussians per count workgroup
 constexpr uint32_t kExpandTile = 2048;      // Gaussians per expand workgroup
 
 // Zeroes `bytes` (a multiple of 16) at p and, if not NULL, the word `extra`;

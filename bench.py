@@ -82,6 +82,8 @@ def parse():
                    help="run one streaming copy of this size first (traffic-counter calibration)")
     p.add_argument("--summarize-profiles", metavar="DIR",
                    help="summarise rocprofv3 output under DIR/{stats,fetch,write} into profiles/ and exit")
+    p.add_argument("--profiled-args", default="--steps 20 --warmup 5 --no-cpu-baseline --no-extras",
+                   help="with --summarize-profiles: the bench arguments of the profiled kernel-trace run")
     return p.parse_args()
 
 
@@ -117,13 +119,14 @@ def _rows(pattern: str):
         return list(csv.DictReader(f))
 
 
-def summarize_profiles(d: str, workload: str, copy_mib: int = 512):
+def summarize_profiles(d: str, workload: str, copy_mib: int = 512,
+                       profiled_args: str = "--steps 20 --warmup 5 --no-cpu-baseline --no-extras"):
     """Write the kernel-time and HBM-traffic summaries of the pass kernel."""
     os.makedirs(PROFILES, exist_ok=True)
     stats = _rows(os.path.join(d, "stats", "*kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics, workload {workload}",
              "command: rocprofv3 --kernel-trace --stats --output-format csv -d DIR/stats -o run -- "
-             f"python3 bench.py --workload {workload} --steps 20 --warmup 5 --no-cpu-baseline --no-extras",
+             f"python3 bench.py --workload {workload} {profiled_args}",
              f"{dominant_kernel(workload)[0]} sources (kernel, launch shapes) sha256[:16]: {source_hash(dominant_kernel(workload)[2])}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -964,7 +967,7 @@ def bench_batch(args):
 def main():
     args = parse()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.workload)
+        summarize_profiles(args.summarize_profiles, args.workload, profiled_args=args.profiled_args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs on a single GPU (the sort of one frame runs "

@@ -51,6 +51,28 @@ __device__ __forceinline__ uint32_t popc_below(uint64_t mask) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// The lanes among `lanes` whose RB-bit digit equals this lane's (stable
+// ranking inside a wave: this lane's rank is the number of them below it).
+// For every digit bit b: t = 0 or ~0 (this lane's bit, sign-extended), m =
+// the ballot of that bit; keep m where t is set and ~m elsewhere, i.e.
+// mask & ~(m ^ t), which is one 3-input bitwise op per 32-lane half
+// (truth table 0x90 over (mask, m, t)).  The empty asm keeps t opaque, so
+// that the ballot is one compare of t rather than a fresh extraction of
+// the bit from d.  Four VALU instructions per digit bit.
+template <int RB>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t lanes) {
+  uint32_t lo = static_cast<uint32_t>(lanes), hi = static_cast<uint32_t>(lanes >> 32);
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    uint32_t t = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(d), b, 1));
+    asm("" : "+v"(t));
+    const uint64_t m = ballot(t != 0);
+    lo = __builtin_amdgcn_bitop3_b32(lo, static_cast<uint32_t>(m), t, 0x90);
+    hi = __builtin_amdgcn_bitop3_b32(hi, static_cast<uint32_t>(m >> 32), t, 0x90);
+  }
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Cross-workgroup words are read and written with device-scope atomics so
 // they are coherent across the XCDs' separate L2 caches.
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {

@@ -158,28 +158,13 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   }
 
   // ---- stable rank inside the wave ----
-  // peers = lanes whose digit equals this lane's: for every digit bit b,
-  // keep the ballot of b where this lane's bit is set, its complement
-  // elsewhere (t = 0 or ~0 from a signed one-bit field extract).
+  // peers = valid lanes whose digit equals this lane's
   uint32_t* wc = sm.wcnt + wave * BINS;
   uint32_t pos[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const bool valid = FULL || dg[j] < BINS;
-    uint32_t plo = ~0u, phi = ~0u;
-    if (!FULL) {
-      const uint64_t vm = ballot(valid);
-      plo = static_cast<uint32_t>(vm);
-      phi = static_cast<uint32_t>(vm >> 32);
-    }
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const uint32_t tb = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(dg[j]), b, 1));
-      const uint64_t m = ballot(tb != 0);
-      plo &= ~(static_cast<uint32_t>(m) ^ tb);
-      phi &= ~(static_cast<uint32_t>(m >> 32) ^ tb);
-    }
-    const uint64_t peers = (static_cast<uint64_t>(phi) << 32) | plo;
+    const uint64_t peers = match_digit<RB>(dg[j], FULL ? ~0ull : ballot(valid));
     uint32_t r = 0;
     if (valid) {
       const uint32_t old = wc[dg[j]];

@@ -45,16 +45,7 @@ __device__ __forceinline__ void rank_chunk(const uint64_t (&it)[kItems], uint32_
     const uint32_t q = wave * (kWave * J) + j * kWave + lane;
     const bool valid = q < n;
     dg[j] = valid ? item_digit(it[j], p) : 256u;
-    const uint64_t vm = ballot(valid);
-    uint32_t plo = static_cast<uint32_t>(vm), phi = static_cast<uint32_t>(vm >> 32);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint32_t tb = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(dg[j]), b, 1));
-      const uint64_t mb = ballot(tb != 0);
-      plo &= ~(static_cast<uint32_t>(mb) ^ tb);
-      phi &= ~(static_cast<uint32_t>(mb >> 32) ^ tb);
-    }
-    const uint64_t peers = (static_cast<uint64_t>(phi) << 32) | plo;
+    const uint64_t peers = match_digit<8>(dg[j], ballot(valid));
     uint32_t r = 0;
     if (valid) {
       const uint32_t old = wc[dg[j]];

@@ -250,6 +250,10 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_
 // tiles and the histograms are per frame.  LDS holds those of the frames of
 // the workgroup's first and last Gaussian; pairs of a frame between them
 // (frames smaller than a workgroup) count straight into global memory.
+//
+// SMALL (a.small_rects) and SEG (a.seg) are template parameters so that each
+// instantiation carries only its own row division and histogram target.
+template <bool SMALL, bool SEG>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   FrameInfo* s_tab = reinterpret_cast<FrameInfo*>(s_dyn);  // [n_frames]
@@ -278,14 +282,14 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   const uint32_t rb = a.radix_bits;
   const uint32_t bins = 1u << rb;
   const uint32_t hframe = a.npasses * bins;  // one frame's histograms
-  const uint32_t hwords = a.seg ? 2 * hframe : hframe;
+  const uint32_t hwords = SEG ? 2 * hframe : hframe;
   for (uint32_t i = tid; i < hwords; i += kExpandThreads) s_hist[i] = 0;
   __syncthreads();
   const uint32_t ticket = blockIdx.x;   // look-back order (see common.hpp)
   const uint32_t base = ticket * kExpandTile;
   // segmented: the frames whose histograms live in LDS
   uint32_t f_lo = 0, f_hi = 0;
-  if (a.seg && a.n != 0) {
+  if (SEG && a.n != 0) {
     f_lo = frame_of(s_tab, a.n_frames, min(base, a.n - 1));
     f_hi = frame_of(s_tab, a.n_frames, min(base + kExpandTile, a.n) - 1);
   }
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       cnt = w * h;
       // packed items carry the depth field: trimmed depth bits, or the
       // position in depth order (the unpacking pass looks the bits up)
-      s_info[i] = make_uint4(a.seg ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0,
+      s_info[i] = make_uint4(SEG ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0,
                              w | (tx << 16), !a.packed ? dep : trimmed ? dep - ebase : pos,
                              g - s_tab[f].gauss_base);
     }
@@ -484,11 +488,12 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         // 256 x 256 tiles (kk < 2^16): floor((kk + 1/2) / w) in fp32 is exact,
         // its true value lying at least 1/512 from an integer while the
         // rounding errors stay below 256 * 2^-21.
-        const uint32_t dy = a.small_rects ? static_cast<uint32_t>((static_cast<float>(kk) + 0.5f) *
+        const uint32_t dy = SMALL ? static_cast<uint32_t>((static_cast<float>(kk) + 0.5f) *
                                                                   __builtin_amdgcn_rcpf(static_cast<float>(w)))
                                           : kk / w;
-        const uint32_t dx = kk - dy * w;
-        const uint32_t tile = (a.seg ? org & 0xFFFFu : org) + dy * (wt >> 16) + dx;
+        // every factor is below 2^24 (w, dy, tiles_x < 2^16): 24-bit products
+        const uint32_t dx = kk - __umul24(dy, w);
+        const uint32_t tile = (SEG ? org & 0xFFFFu : org) + __umul24(dy, wt >> 16) + dx;
         if (a.packed) {
           keys[q] = (static_cast<uint64_t>(tile) << a.pk.tile_shift) |
                     (static_cast<uint64_t>(gi.z) << a.pk.idx_bits) | gi.w;
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
           vals[q] = gi.w;
         }
         uint32_t* h = s_hist;
-        if (a.seg) {
+        if (SEG) {
           const uint32_t f = org >> 16;
           h = f == f_lo ? s_hist
               : f == f_hi ? s_hist + hframe
@@ -510,11 +515,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   }
   // histogram copy ticket % kHistCopies: [npasses][bins], or, segmented,
   // [frame][npasses][bins]
-  const size_t copy = static_cast<size_t>(ticket % kHistCopies) * (a.seg ? a.n_frames : 1u) * hframe;
+  const size_t copy = static_cast<size_t>(ticket % kHistCopies) * (SEG ? a.n_frames : 1u) * hframe;
   for (uint32_t i = tid; i < hwords; i += kExpandThreads) {
     const uint32_t v = s_hist[i];
     const uint32_t f = i < hframe ? f_lo : f_hi;
-    if (v) atomicAdd(&a.hist[copy + (a.seg ? static_cast<size_t>(f) * hframe : 0u) + i % hframe], v);
+    if (v) atomicAdd(&a.hist[copy + (SEG ? static_cast<size_t>(f) * hframe : 0u) + i % hframe], v);
   }
 }
 
@@ -541,7 +546,13 @@ hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
   if (a.nblocks == 0) return hipSuccess;
   const size_t dyn = a.n_frames * sizeof(FrameInfo) + (static_cast<size_t>(a.npasses) << a.radix_bits) * 4 *
                                                          (a.seg ? 2u : 1u);
-  hipLaunchKernelGGL(k_expand, dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
+  if (a.small_rects) {
+    if (a.seg) hipLaunchKernelGGL((k_expand<true, true>), dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
+    else hipLaunchKernelGGL((k_expand<true, false>), dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
+  } else {
+    if (a.seg) hipLaunchKernelGGL((k_expand<false, true>), dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
+    else hipLaunchKernelGGL((k_expand<false, false>), dim3(a.nblocks), dim3(kExpandThreads), dyn, s, a);
+  }
   return hipGetLastError();
 }
 

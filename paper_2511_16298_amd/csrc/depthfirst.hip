@@ -262,7 +262,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
   __shared__ uint32_t s_off[kExpandTile];
   // per Gaussian, read as one 16-byte word per pair: x = global tile of
   // (x0, y0) (segmented: frame-local | frame << 16), y = w | tiles_x << 16,
-  // z = depth field, w = frame-local index
+  // z = depth bits, w = frame-local index; packed items instead hold in
+  // (z, w) the low and high words of their bits below the tile field
+  // (depth field << idx_bits | index)
   __shared__ uint4 s_info[kExpandTile];
   __shared__ __align__(16) uint16_t s_map[kChunk];
   __shared__ uint32_t s_incl[kExpandThreads];
@@ -359,9 +361,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       cnt = w * h;
       // packed items carry the depth field: trimmed depth bits, or the
       // position in depth order (the unpacking pass looks the bits up)
+      const uint32_t local = g - s_tab[f].gauss_base;
+      uint64_t low = (static_cast<uint64_t>(trimmed ? dep - ebase : pos) << a.pk.idx_bits) | local;
+      if (!a.packed) low = (static_cast<uint64_t>(local) << 32) | dep;
       s_info[i] = make_uint4(SEG ? (y0 * tx + x0) | (f << 16) : s_tab[f].tile_base + y0 * tx + x0,
-                             w | (tx << 16), !a.packed ? dep : trimmed ? dep - ebase : pos,
-                             g - s_tab[f].gauss_base);
+                             w | (tx << 16), static_cast<uint32_t>(low), static_cast<uint32_t>(low >> 32));
     }
     s_off[i] = cnt;
   }
@@ -495,8 +499,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         const uint32_t dx = kk - __umul24(dy, w);
         const uint32_t tile = (SEG ? org & 0xFFFFu : org) + __umul24(dy, wt >> 16) + dx;
         if (a.packed) {
-          keys[q] = (static_cast<uint64_t>(tile) << a.pk.tile_shift) |
-                    (static_cast<uint64_t>(gi.z) << a.pk.idx_bits) | gi.w;
+          // the tile field lies in the high word (tile_shift >= 32)
+          keys[q] = (static_cast<uint64_t>((tile << (a.pk.tile_shift - 32)) | gi.w) << 32) | gi.z;
         } else {
           keys[q] = (static_cast<uint64_t>(tile) << 32) | gi.z;
           vals[q] = gi.w;
@@ -508,7 +512,12 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
               : f == f_hi ? s_hist + hframe
                           : a.hist + (static_cast<size_t>(ticket % kHistCopies) * a.n_frames + f) * hframe;
         }
-        for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&h[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+        if (a.npasses == 2) {  // the usual count (up to 16 tile bits), without loop control
+          atomicAdd(&h[tile & (bins - 1)], 1u);
+          atomicAdd(&h[bins + ((tile >> rb) & (bins - 1))], 1u);
+        } else {
+          for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&h[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+        }
       }
     }
     __syncthreads();

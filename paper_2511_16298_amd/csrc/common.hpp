@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "splatsort.h"
@@ -88,15 +89,45 @@ __device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Inclusive scans over the 64 lanes of a wave with DPP lane moves instead of
+// LDS permutes.  Inside each row of 16 lanes, four steps (row_shr:1, 2, 4, 8)
+// add the value d lanes below; lanes below the row's start read 0 (bound_ctrl),
+// the identity of both operations.  Then row_bcast:15 adds lane 15's prefix to
+// rows 1 and 3, and row_bcast:31 lane 31's to rows 2 and 3.  Lanes outside a
+// step's row or bank mask receive 0.
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROWS, BANKS, true));
+}
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ uint64_t dpp0(uint64_t v) {
+  return (static_cast<uint64_t>(dpp0<CTRL, ROWS, BANKS>(static_cast<uint32_t>(v >> 32))) << 32) |
+         dpp0<CTRL, ROWS, BANKS>(static_cast<uint32_t>(v));
+}
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T o = __shfl_up(v, d, kWave);
-    if (lane >= static_cast<uint32_t>(d)) v += o;
-  }
-  return v;
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+  using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+  U x = static_cast<U>(v);
+  x += dpp0<kDppRowShr | 1, 0xF, 0xF>(x);
+  x += dpp0<kDppRowShr | 2, 0xF, 0xF>(x);
+  x += dpp0<kDppRowShr | 4, 0xF, 0xF>(x);
+  x += dpp0<kDppRowShr | 8, 0xF, 0xF>(x);
+  x += dpp0<kDppRowBcast15, 0xA, 0xF>(x);
+  x += dpp0<kDppRowBcast31, 0xC, 0xF>(x);
+  return static_cast<T>(x);
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+  x = max(x, dpp0<kDppRowShr | 1, 0xF, 0xF>(x));
+  x = max(x, dpp0<kDppRowShr | 2, 0xF, 0xF>(x));
+  x = max(x, dpp0<kDppRowShr | 4, 0xF, 0xF>(x));
+  x = max(x, dpp0<kDppRowShr | 8, 0xF, 0xF>(x));
+  x = max(x, dpp0<kDppRowBcast15, 0xA, 0xF>(x));
+  x = max(x, dpp0<kDppRowBcast31, 0xC, 0xF>(x));
+  return x;
 }
 
 // Exclusive scan over a whole workgroup of THREADS threads (one value each).

@@ -218,11 +218,7 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_
   constexpr int kWaves = THREADS / kWave;
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= static_cast<uint32_t>(d)) v = max(v, o);
-  }
+  v = wave_inclusive_max(v);
   if (lane == kWave - 1) s_tmp[wave] = v;
   __syncthreads();
   uint32_t before = 0;

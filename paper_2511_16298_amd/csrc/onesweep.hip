@@ -75,6 +75,17 @@ __device__ __forceinline__ uint32_t segment_of(const uint32_t* first, uint32_t n
   return lo;
 }
 
+// The digit of key k at bit `shift`.  Packed items keep their tile field in
+// the high word (shift >= 32): one 32-bit field extract instead of a 64-bit
+// shift and a mask.
+template <typename K, int MODE, int RB>
+__device__ __forceinline__ uint32_t key_digit(K k, uint32_t shift) {
+  if constexpr (sizeof(K) == 8 && MODE != kPassKV)
+    return __builtin_amdgcn_ubfe(static_cast<uint32_t>(k >> 32), shift - 32, RB);
+  else
+    return static_cast<uint32_t>(k >> shift) & ((1u << RB) - 1u);
+}
+
 // The tile body, in two parts: the loads, then ranking and scatter.  FULL:
 // every one of the TILE slots holds a pair (all tiles but the last, unless
 // items are dropped), so no per-item bounds tests are needed.  `dropped`
@@ -84,7 +95,6 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
                                           uint32_t base, uint32_t n, uint32_t dropped, K (&k)[ITEMS],
                                           uint32_t (&v)[ITEMS], uint32_t (&dg)[ITEMS]) {
   constexpr int BINS = 1 << RB;
-  constexpr uint32_t DMASK = BINS - 1;
   const int tid = threadIdx.x;
   // 32-bit keys: global total of digit tid (summed over the histogram
   // copies), whose exclusive prefix over the digits is the digit's first
@@ -118,7 +128,7 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
       k[j] = kin[idx];
       v[j] = MODE == kPassKV ? a.vin[idx] : 0u;
       dg[j] = sizeof(K) == 4 && a.frame_digit ? segment_of(sm.aux, a.n_frames, v[j])
-                                              : static_cast<uint32_t>(k[j] >> a.shift) & DMASK;
+                                              : key_digit<K, MODE, RB>(k[j], a.shift);
     } else {
       k[j] = 0;
       v[j] = 0;
@@ -145,7 +155,6 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
                                           uint32_t (&dg)[ITEMS], const SegCtx& sc) {
   constexpr int WAVES = THREADS / kWave;
   constexpr int BINS = 1 << RB;
-  constexpr uint32_t DMASK = BINS - 1;
   constexpr int TILE = THREADS * ITEMS;
   const int tid = threadIdx.x;
   const uint32_t wave = tid / kWave;
@@ -302,10 +311,10 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
       const uint32_t i = j * THREADS + tid;
       if (FULL || i < valid_n) {
         const uint64_t item = sm.buf[i];
-        const uint32_t d = static_cast<uint32_t>(item >> a.shift) & DMASK;
+        const uint32_t d = key_digit<K, MODE, RB>(item, a.shift);
         const uint32_t o = sm.gofs[d] + i;
         if (o < n) {
-          const uint32_t tile = sc.tile_base + static_cast<uint32_t>(item >> S);
+          const uint32_t tile = sc.tile_base + (static_cast<uint32_t>(item >> 32) >> (S - 32));
           const uint64_t payload = item & pmask;
           const uint32_t hi = static_cast<uint32_t>(payload >> ib);
           const uint32_t dbits = trimmed ? hi + ebase : a.packed.depth_sorted[hi];
@@ -317,7 +326,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
           int64_t tp = -1;
           bool known = true;
           if (i > sm.dstart[d]) {
-            tp = static_cast<int64_t>(sc.tile_base + static_cast<uint32_t>(sm.buf[i - 1] >> S));
+            tp = static_cast<int64_t>(sc.tile_base + (static_cast<uint32_t>(sm.buf[i - 1] >> 32) >> (S - 32)));
           } else {
             const uint32_t lx = sm.lbx[d];
             known = lx != 0;
@@ -342,7 +351,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     dst[j] = 0xFFFFFFFFu;
     if (FULL || i < valid_n) {
       const K key = sm.buf[i];
-      uint32_t d = static_cast<uint32_t>(key >> (frame_digit ? 0u : a.shift)) & DMASK;
+      uint32_t d = frame_digit ? 0u : key_digit<K, MODE, RB>(key, a.shift);
       if constexpr (sizeof(K) == 4) {
         if (frame_digit) d = static_cast<uint32_t>(sm.buf[TILE + i]);
       }

@@ -153,66 +153,25 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* s_tmp, T& total) {
   return before + inc - v;
 }
 
-// Decoupled look-back for one digit (one calling thread per digit): adds up
-// the digit's counts in workgroups 0 .. t-1 of `lb` ([workgroup][stride]
-// words, this workgroup's aggregate already published) and publishes this
-// workgroup's inclusive count.  Each round reads the words of
-// kLookbackWindow predecessors at once (independent loads, so one memory
-// latency per round) and consumes them nearest first, up to the first
-// inclusive word; a word not yet published ends the round there.  Returns
-// false after kSpinLimit fruitless rounds, having raised SS_ERR_TIMEOUT in
-// *status (when not NULL).
+// Decoupled look-back for one digit by a group of G consecutive lanes of one
+// wave (one group per digit): adds up the digit's counts in workgroups
+// first .. t-1 of `lb` ([workgroup][stride] words, this workgroup's aggregate
+// already published).  Each round, lane s of the group reads the words of
+// predecessors kb - 8s - j (j < 8) at once, independent loads, so a round
+// costs one memory latency and covers 8G predecessors.  Every lane sums its
+// words nearest first, up to the first inclusive or not yet published one;
+// the group then takes its lanes in order up to the first that stopped.  An
+// inclusive word ends the look-back; an unpublished one ends the round there
+// (the round after restarts at it).  `first`: the chain's first workgroup,
+// which published its count as inclusive at once; words before it read as
+// inclusive zeros.  Returns the exclusive count (and, with 64-bit words, the
+// largest carried maximum) in every lane of the group; returns false after
+// spin_limit fruitless rounds, having raised SS_ERR_TIMEOUT in *status (when
+// not NULL).  The caller publishes the inclusive word.
 constexpr int kLookbackWindow = 8;
 
-// `first`: the chain's first workgroup (0, or a segment's first), which
-// publishes its count as inclusive at once.  `spin_limit`: polls before
-// giving up (kSpinLimit unless a caller asks for fewer).
-__device__ __forceinline__ bool lookback_digit(uint32_t* lb, uint32_t t, uint32_t stride, uint32_t d, uint32_t own,
-                                               uint32_t* status, uint32_t& excl, uint32_t first = 0,
-                                               uint32_t spin_limit = kSpinLimit) {
-  excl = 0;
-  if (t == first) return true;
-  int32_t kb = static_cast<int32_t>(t) - 1;  // nearest predecessor not yet consumed
-  const int32_t lo = static_cast<int32_t>(first);
-  uint32_t spins = 0;
-  while (true) {
-    uint32_t w[kLookbackWindow];
-#pragma unroll
-    for (int j = 0; j < kLookbackWindow; ++j)
-      w[j] = kb - j >= lo ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbInc32;
-    uint32_t add = 0;
-    int32_t used = 0;
-    bool inc = false, stall = false;
-#pragma unroll
-    for (int j = 0; j < kLookbackWindow; ++j) {
-      if (inc || stall) continue;
-      if ((w[j] & ~kLbMask32) == 0) {
-        stall = true;
-      } else {
-        add += w[j] & kLbMask32;
-        ++used;
-        inc = (w[j] & kLbInc32) != 0;
-      }
-    }
-    excl += add;
-    if (inc) break;
-    kb -= used;
-    if (stall) {
-      if (++spins > spin_limit) {
-        if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  st_agent(&lb[static_cast<size_t>(t) * stride + d], kLbInc32 | (excl + own));
-  return true;
-}
-
-// The look-back above with 64-bit words that also carry a maximum: bits 0-29
-// the count, bits 30-61 a value combined by max (0 = none), bits 62-63 the
-// state.  Returns the exclusive count and maximum, and publishes this
-// workgroup's inclusive word (own count and maximum `own_max`).
+// 64-bit look-back words that also carry a maximum: bits 0-29 the count,
+// bits 30-61 a value combined by max (0 = none), bits 62-63 the state.
 constexpr uint64_t kLbAggW = 1ull << 62;
 constexpr uint64_t kLbIncW = 2ull << 62;
 constexpr uint64_t kLbCountW = (1ull << 30) - 1;
@@ -222,51 +181,88 @@ __device__ __forceinline__ uint64_t lb_word(uint64_t state, uint32_t count, uint
   return state | (static_cast<uint64_t>(mx) << 30) | count;
 }
 
-__device__ __forceinline__ bool lookback_digit_max(uint64_t* lb, uint32_t t, uint32_t stride, uint32_t d,
-                                                   uint32_t own, uint32_t own_max, uint32_t* status,
-                                                   uint32_t& excl, uint32_t& excl_max, uint32_t first = 0,
-                                                   uint32_t spin_limit = kSpinLimit) {
+struct LbWords32 {
+  using W = uint32_t;
+  static constexpr bool kMax = false;
+  static constexpr W kBefore = kLbInc32;
+  __device__ static bool published(W w) { return (w & ~kLbMask32) != 0; }
+  __device__ static bool inclusive(W w) { return (w & kLbInc32) != 0; }
+  __device__ static uint32_t count(W w) { return w & kLbMask32; }
+  __device__ static uint32_t maximum(W) { return 0; }
+};
+struct LbWords64 {
+  using W = uint64_t;
+  static constexpr bool kMax = true;
+  static constexpr W kBefore = kLbIncW;
+  __device__ static bool published(W w) { return (w >> 62) != 0; }
+  __device__ static bool inclusive(W w) { return (w >> 62) == 2; }
+  __device__ static uint32_t count(W w) { return static_cast<uint32_t>(w & kLbCountW); }
+  __device__ static uint32_t maximum(W w) { return static_cast<uint32_t>((w >> 30) & kLbMaxW); }
+};
+
+template <int G, typename P>
+__device__ __forceinline__ bool lookback_group(typename P::W* lb, uint32_t t, uint32_t stride, uint32_t d,
+                                               uint32_t* status, uint32_t& excl, uint32_t& excl_max,
+                                               uint32_t first, uint32_t spin_limit) {
+  static_assert(G >= 1 && G <= kWave && kWave % G == 0, "a group lies inside one wave");
+  constexpr int W = kLookbackWindow;
+  const uint32_t lane = lane_id();
+  const uint32_t s = lane % G;
+  const uint32_t base = lane - s;
   excl = 0;
   excl_max = 0;
   if (t == first) return true;
-  int32_t kb = static_cast<int32_t>(t) - 1;
+  int32_t kb = static_cast<int32_t>(t) - 1;  // nearest predecessor not yet consumed
   const int32_t lo = static_cast<int32_t>(first);
   uint32_t spins = 0;
   while (true) {
-    uint64_t w[kLookbackWindow];
+    typename P::W w[W];
 #pragma unroll
-    for (int j = 0; j < kLookbackWindow; ++j)
-      w[j] = kb - j >= lo ? ld_agent(&lb[static_cast<size_t>(kb - j) * stride + d]) : kLbIncW;
-    uint32_t add = 0, mx = 0;
-    int32_t used = 0;
-    bool inc = false, stall = false;
+    for (int j = 0; j < W; ++j) {
+      const int32_t k = kb - static_cast<int32_t>(s) * W - j;
+      w[j] = k >= lo ? ld_agent(&lb[static_cast<size_t>(k) * stride + d]) : P::kBefore;
+    }
+    uint32_t sum = 0, mx = 0, used = 0, st = 0;  // st: 0 all consumed, 1 inclusive met, 2 unpublished met
 #pragma unroll
-    for (int j = 0; j < kLookbackWindow; ++j) {
-      if (inc || stall) continue;
-      if ((w[j] >> 62) == 0) {
-        stall = true;
+    for (int j = 0; j < W; ++j) {
+      if (st != 0) continue;
+      if (!P::published(w[j])) {
+        st = 2;
       } else {
-        add += static_cast<uint32_t>(w[j] & kLbCountW);
-        const uint32_t m = static_cast<uint32_t>((w[j] >> 30) & kLbMaxW);
-        mx = m > mx ? m : mx;
+        sum += P::count(w[j]);
+        if (P::kMax) mx = max(mx, P::maximum(w[j]));
         ++used;
-        inc = (w[j] >> 62) == 2;
+        if (P::inclusive(w[j])) st = 1;
+      }
+    }
+    // the group's lanes in order, up to the first that stopped
+    uint32_t add = 0, amx = 0, taken = 0, stop = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const uint32_t sk = G == 1 ? sum : static_cast<uint32_t>(__shfl(static_cast<int>(sum), base + k, kWave));
+      const uint32_t pk = G == 1 ? (used | st << 8)
+                                 : static_cast<uint32_t>(__shfl(static_cast<int>(used | st << 8), base + k, kWave));
+      uint32_t mk = 0;
+      if (P::kMax) mk = G == 1 ? mx : static_cast<uint32_t>(__shfl(static_cast<int>(mx), base + k, kWave));
+      if (stop == 0) {
+        add += sk;
+        amx = max(amx, mk);
+        taken += pk & 0xFFu;
+        stop = pk >> 8;
       }
     }
     excl += add;
-    excl_max = mx > excl_max ? mx : excl_max;
-    if (inc) break;
-    kb -= used;
-    if (stall) {
+    excl_max = max(excl_max, amx);
+    if (stop == 1) break;
+    kb -= static_cast<int32_t>(taken);
+    if (stop == 2) {
       if (++spins > spin_limit) {
-        if (status) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
+        if (status && s == 0) st_agent(status, static_cast<uint32_t>(SS_ERR_TIMEOUT));
         return false;
       }
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  st_agent(&lb[static_cast<size_t>(t) * stride + d],
-           lb_word(kLbIncW, excl + own, own_max > excl_max ? own_max : excl_max));
   return true;
 }
 

@@ -42,6 +42,7 @@ struct PassSmem {
   K buf[THREADS * ITEMS * (sizeof(K) == 4 ? 2 : 1)];
   uint32_t wcnt[(THREADS / kWave) << RB];
   uint32_t dstart[1 << RB];
+  uint32_t cnt[1 << RB];    // the tile's count of each digit
   uint32_t gofs[1 << RB];
   // kPassUnpack: per digit, 1 + the largest tile part below the digit among
   // the pairs of earlier workgroups (0: none)
@@ -215,9 +216,13 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   } else {
     uint32_t total;
     lexcl = block_exclusive_scan<uint32_t, THREADS>(bcnt, reinterpret_cast<uint32_t*>(sm.tmp), total);
-    gbase = 0;  // read next to the look-back (below), where its temporaries are free
+    gbase = 0;  // 64-bit keys: published digit bases, read at the look-back
   }
-  if (tid < BINS) sm.dstart[tid] = lexcl;
+  if (tid < BINS) {
+    sm.dstart[tid] = lexcl;
+    sm.cnt[tid] = bcnt;
+    if constexpr (sizeof(K) == 4) sm.gofs[tid] = gbase;
+  }
   __syncthreads();
 
   // ---- permute the keys into digit order in LDS ----
@@ -245,26 +250,35 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     }
   }
   // kPassUnpack: the digit's largest tile part in this workgroup is that of
-  // its last slot (the input is in order of the lower tile bits)
-  uint32_t own_max = 0;
+  // its last slot (the input is in order of the lower tile bits); 1 + it,
+  // or 0 for a digit without pairs here
+  const uint32_t lowmask = a.low_bits >= 32 ? ~0u : (1u << a.low_bits) - 1u;
+  auto own_max_of = [&](uint32_t start, uint32_t count) -> uint32_t {
+    return count == 0 ? 0u
+                      : 1u + (static_cast<uint32_t>(sm.buf[start + count - 1] >> a.packed.tile_shift) & lowmask);
+  };
   if constexpr (MODE == kPassUnpack) {
     __syncthreads();
-    if (tid < BINS && bcnt != 0) {
-      const uint32_t lowmask = a.low_bits >= 32 ? ~0u : (1u << a.low_bits) - 1u;
-      own_max = 1u + (static_cast<uint32_t>(sm.buf[lexcl + bcnt - 1] >> a.packed.tile_shift) & lowmask);
-    }
     if (tid < BINS)
       st_agent(&a.lookback64[static_cast<size_t>(t) * BINS + tid],
-               lb_word(t == sc.first ? kLbIncW : kLbAggW, bcnt, own_max));
+               lb_word(t == sc.first ? kLbIncW : kLbAggW, bcnt, own_max_of(lexcl, bcnt)));
   }
 
   // ---- decoupled look-back: pairs of digit d in earlier workgroups ----
-  if (tid < BINS) {
+  // G consecutive lanes per digit: two where the workgroup has the threads
+  // (16 predecessors per round), except in 16-item passes over pairs, whose
+  // long chains of tiles measured faster with one; more lanes spread each
+  // load over more rows of the look-back words and measured slower
+  constexpr int G = sizeof(K) == 8 && ITEMS >= 16 ? 1 : THREADS / BINS > 2 ? 2 : THREADS / BINS;
+  static_assert(G >= 1 && THREADS % BINS == 0, "whole lane groups per digit");
+  if (tid < BINS * G) {
+    const uint32_t d = static_cast<uint32_t>(tid) / G;
+    const uint32_t limit = spin_limit_of(a.spin_limit);
+    uint32_t gb;
     if constexpr (sizeof(K) == 8) {
       // published by workgroup 0 of the chain's first pass, long before any
       // workgroup gets here
-      uint32_t w = ld_agent(&sc.bases[tid]), spins = 0;
-      const uint32_t limit = spin_limit_of(a.spin_limit);
+      uint32_t w = ld_agent(&sc.bases[d]), spins = 0;
       while ((w & kBasePublished) == 0) {
         if (++spins > limit) {
           sm.timeout = 1;
@@ -272,22 +286,36 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        w = ld_agent(&sc.bases[tid]);
+        w = ld_agent(&sc.bases[d]);
       }
-      gbase = w & ~kBasePublished;
-    }
-    uint32_t excl = 0;
-    if constexpr (MODE == kPassUnpack) {
-      uint32_t excl_max = 0;
-      if (!lookback_digit_max(a.lookback64, t, BINS, tid, bcnt, own_max, a.status, excl, excl_max, sc.first,
-                              spin_limit_of(a.spin_limit)))
-        sm.timeout = 1;
-      sm.lbx[tid] = excl != 0 ? excl_max : 0u;
+      gb = w & ~kBasePublished;
     } else {
-      if (!lookback_digit(a.lookback, t, BINS, tid, bcnt, a.status, excl, sc.first, spin_limit_of(a.spin_limit)))
-        sm.timeout = 1;
+      gb = sm.gofs[d];  // the digit's global base, from the scan
     }
-    sm.gofs[tid] = gbase + excl - lexcl;
+    const uint32_t count = sm.cnt[d], start = sm.dstart[d];
+    uint32_t excl = 0, excl_max = 0;
+    bool ok;
+    if constexpr (MODE == kPassUnpack)
+      ok = lookback_group<G, LbWords64>(a.lookback64, t, BINS, d, a.status, excl, excl_max, sc.first, limit);
+    else
+      ok = lookback_group<G, LbWords32>(a.lookback, t, BINS, d, a.status, excl, excl_max, sc.first, limit);
+    if (!ok) {
+      sm.timeout = 1;
+    } else if (static_cast<uint32_t>(tid) % G == 0) {
+      // the group's first lane publishes the inclusive word (the chain's
+      // first workgroup published its count as inclusive already)
+      if (t != sc.first) {
+        if constexpr (MODE == kPassUnpack) {
+          const uint32_t om = own_max_of(start, count);
+          st_agent(&a.lookback64[static_cast<size_t>(t) * BINS + d],
+                   lb_word(kLbIncW, excl + count, om > excl_max ? om : excl_max));
+        } else {
+          st_agent(&a.lookback[static_cast<size_t>(t) * BINS + d], kLbInc32 | (excl + count));
+        }
+      }
+      if constexpr (MODE == kPassUnpack) sm.lbx[d] = excl != 0 ? excl_max : 0u;
+      sm.gofs[d] = gb + excl - start;
+    }
   }
   __syncthreads();
   if (sm.timeout) return;

@@ -43,6 +43,14 @@ __device__ __forceinline__ uint32_t frame_of(const FrameInfo* tab, uint32_t n_fr
   return lo;
 }
 
+// One 16-byte record read through a global-memory pointer (four adjacent
+// words, which the compiler merges into one load).
+__device__ __forceinline__ int4 load_record(const ss_gaussian2d* p) {
+  typedef const int __attribute__((address_space(1))) GlobalWord;
+  const GlobalWord* q = (const GlobalWord*)p;
+  return make_int4(q[0], q[1], q[2], q[3]);
+}
+
 __global__ void k_put_table(TableChunk c, FrameInfo* __restrict__ table) {
   if (threadIdx.x < c.count) table[c.first + threadIdx.x] = c.f[threadIdx.x];
 }
@@ -66,15 +74,27 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
   const uint32_t last = min(base + kCountKeysTile, a.n) - 1;
   const bool one_frame = a.n_frames == 1 || frame_of(s_tab, a.n_frames, base) == frame_of(s_tab, a.n_frames, last);
 
+  // all records first, unconditionally (slots past n reread the last
+  // record) and through a global-memory pointer: the table's pointers would
+  // otherwise be read as generic ones, split around the radius test, and
+  // each item would wait for its own loads
+  int4 rec[kCountKeysItems];
+  uint32_t fr[kCountKeysItems];
+#pragma unroll
+  for (uint32_t j = 0; j < kCountKeysItems; ++j) {
+    const uint32_t g = min(base + j * kCountKeysThreads + tid, a.n - 1);
+    fr[j] = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
+    rec[j] = load_record(s_tab[fr[j]].gaussians + (g - s_tab[fr[j]].gauss_base));
+  }
   bool bad = false;
   uint64_t tsum = 0;
 #pragma unroll
   for (uint32_t j = 0; j < kCountKeysItems; ++j) {
     const uint32_t g = base + j * kCountKeysThreads + tid;
     if (g >= a.n) continue;
-    const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
+    const uint32_t f = fr[j];
     const FrameInfo& F = s_tab[f];
-    const int4 r = reinterpret_cast<const int4*>(F.gaussians)[g - F.gauss_base];
+    const int4 r = rec[j];
     const uint32_t radius = static_cast<uint32_t>(r.w);
     const uint32_t dbits = static_cast<uint32_t>(r.z);
     uint32_t cnt = 0;

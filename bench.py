@@ -354,6 +354,7 @@ def bench_serve(args):
 
         def collect():
             i = 0
+            last = time.perf_counter()
             while True:
                 with lock:
                     while i >= len(tickets) and not done_submitting[0]:
@@ -366,6 +367,9 @@ def bench_serve(args):
                 sampler.take(r, k)
                 srv.release(t)
                 i += 1
+                if time.perf_counter() - last > 10.0:  # a backlog can take minutes to drain
+                    last = time.perf_counter()
+                    print(f"# serve at {int(rate)}/s: {i} of {len(arr)} requests completed", file=sys.stderr, flush=True)
         th = threading.Thread(target=collect)
         th.start()
         t0 = time.perf_counter()

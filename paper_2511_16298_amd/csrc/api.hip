@@ -178,7 +178,8 @@ struct DfLayout {
   size_t block_total = 0, block_frame = 0;
   size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
          lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
-         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, tickets = 0, total = 0;
+         key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, tickets = 0, wg_totals = 0,
+         total = 0;
 };
 
 // Pairs travel through the tile passes as one 64-bit item when the tile id,
@@ -270,6 +271,7 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   // written whole by the expansion's totals
   L.seg_base = off;  off = align_up(off + (L.seg ? n_frames + 1u : 0u) * sizeof(uint32_t));
   L.seg_wgs = off;   off = align_up(off + (L.seg ? n_frames + 1u : 0u) * sizeof(uint32_t));
+  L.wg_totals = off; off = align_up(off + static_cast<size_t>(L.eblocks) * sizeof(uint64_t));  // expand's
   L.table = off;     off = align_up(off + static_cast<size_t>(n_frames) * sizeof(FrameInfo));
   L.rect = off;      off = align_up(off + static_cast<size_t>(n) * sizeof(uint64_t));
   L.key = off;       off = align_up(off + static_cast<size_t>(n) * sizeof(uint32_t));
@@ -754,7 +756,15 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.totals.seg_base = seg_base;
   e.totals.seg_wgs = seg_wgs;
   e.totals.seg_tile = lay.tcfg.tile();
-  SS_TRY(L.run(SS_KERNEL_EXPAND, [&] { return launch_expand(e, s); }));
+  // a single frame whose rectangles travel with the depth sort: each expand
+  // workgroup's pair count is counted first, so expand needs no look-back
+  const bool wg_totals = pack && !lay.seg && !tile_first;
+  unsigned long long* d_wg_totals = at<unsigned long long>(ws, lay.wg_totals);
+  e.wg_totals = wg_totals ? d_wg_totals : nullptr;
+  SS_TRY(L.run_group(SS_KERNEL_EXPAND, wg_totals ? 2u : 1u, [&]() -> ss_status {
+    if (wg_totals && launch_expand_totals(e, d_wg_totals, s) != hipSuccess) return SS_ERR_HIP;
+    return launch_expand(e, s) == hipSuccess ? SS_OK : SS_ERR_HIP;
+  }));
   if (P > 0) {
     uint32_t* bases_t = at<uint32_t>(ws, lay.bases_t);
     // fixed arrays: the frame path allocates nothing on the host either

@@ -249,6 +249,28 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* s_
   return max(before, v);
 }
 
+// The pair count of each expand workgroup's Gaussians, counted as k_expand
+// counts them (packed rectangles in depth order, culled ones without pairs),
+// so that expand needs no look-back: all totals exist before it starts.
+__global__ __launch_bounds__(kExpandThreads) void k_expand_totals(ExpandArgs a, unsigned long long* wg_totals) {
+  __shared__ unsigned long long s_tmp64[kExpandThreads / kWave];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t base = blockIdx.x * kExpandTile;
+  const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;
+  unsigned long long v = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kExpandPer; ++j) {
+    const uint32_t pos = base + j * kExpandThreads + tid;
+    if (pos < n_sorted) {
+      const uint32_t r = a.rect32[pos];
+      const uint32_t w = a.key[pos] != 0xFFFFFFFFu ? ((r >> 16) & 0xFFu) + 1u : 0u;
+      v += w * (((r >> 24) & 0xFFu) + 1u);
+    }
+  }
+  const unsigned long long total = block_reduce_sum<unsigned long long, kExpandThreads>(v, s_tmp64);
+  if (tid == 0) wg_totals[blockIdx.x] = total;
+}
+
 // Step 3.  2048 Gaussians (in depth order) per workgroup of 512 threads.
 // Counts come from the rectangles; a workgroup scan plus a decoupled
 // look-back whose window is the whole workgroup (512 earlier workgroups per
@@ -405,10 +427,16 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     }
   }
 
-  // ---- decoupled look-back, window = the whole workgroup ----
+  // ---- pairs of earlier workgroups: their totals, or a decoupled look-back
+  // whose window is the whole workgroup ----
   const unsigned long long mine = btotal > kSat ? kSat : btotal;
   unsigned long long excl = 0;
-  if (ticket == 0) {
+  if (a.wg_totals != nullptr) {
+    unsigned long long v = 0;
+    for (uint32_t k = tid; k < ticket; k += kExpandThreads) v += a.wg_totals[k];
+    excl = block_reduce_sum<unsigned long long, kExpandThreads>(v, s_tmp64);
+    if (excl > kSat) excl = kSat;
+  } else if (ticket == 0) {
     if (tid == 0) st_agent(&a.lookback[0], kLbInc64 | mine);
   } else {
     if (tid == 0) st_agent(&a.lookback[ticket], kLbAgg64 | mine);
@@ -564,6 +592,12 @@ hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s) {
 
 hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_totals(const ExpandArgs& a, unsigned long long* wg_totals, hipStream_t s) {
+  if (a.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_totals, dim3(a.nblocks), dim3(kExpandThreads), 0, s, a, wg_totals);
   return hipGetLastError();
 }
 

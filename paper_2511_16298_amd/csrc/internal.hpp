@@ -238,12 +238,18 @@ struct ExpandArgs {
   uint32_t top_hist_stride;
   uint32_t* depth_top_out;
   PairTotalsArgs totals;    // finished by workgroup 0
+  // single frames with packed rectangles: every workgroup's pair count,
+  // written by k_expand_totals beforehand; each workgroup then sums those
+  // before it instead of looking back (NULL: look-back)
+  const unsigned long long* wg_totals;
 };
 
 hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s);
 hipError_t launch_count_keys(const CountKeysArgs& a, hipStream_t s);
 hipError_t launch_pair_totals(const PairTotalsArgs& a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+// Each expand workgroup's pair count into a.wg_totals (single frame, packed rectangles).
+hipError_t launch_expand_totals(const ExpandArgs& a, unsigned long long* wg_totals, hipStream_t s);
 constexpr uint32_t kCountKeysTile = 2048;   // Gaussians per count workgroup
 constexpr uint32_t kExpandTile = 2048;      // Gaussians per expand workgroup
 

@@ -761,6 +761,8 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   const bool wg_totals = pack && !lay.seg && !tile_first;
   unsigned long long* d_wg_totals = at<unsigned long long>(ws, lay.wg_totals);
   e.wg_totals = wg_totals ? d_wg_totals : nullptr;
+  e.culled = ck.hist + 3 * 256 + 255;  // digit 255 of the top byte: culled only
+  e.culled_stride = 4 * 256;
   SS_TRY(L.run_group(SS_KERNEL_EXPAND, wg_totals ? 2u : 1u, [&]() -> ss_status {
     if (wg_totals && launch_expand_totals(e, d_wg_totals, s) != hipSuccess) return SS_ERR_HIP;
     return launch_expand(e, s) == hipSuccess ? SS_OK : SS_ERR_HIP;

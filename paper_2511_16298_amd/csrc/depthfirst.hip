@@ -257,15 +257,23 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_totals(ExpandArgs a, 
   const uint32_t tid = threadIdx.x;
   const uint32_t base = blockIdx.x * kExpandTile;
   const uint32_t n_sorted = a.n_sorted ? *a.n_sorted : a.n;
+  // the culled Gaussians sort last: positions from n minus their count on
+  // have no pairs (the count, digit 255 of the top depth byte, is summed by
+  // the first lanes of every wave while the rectangles load)
+  const uint32_t lane = tid % kWave;
+  const uint32_t c = lane < kHistCopies ? a.culled[static_cast<size_t>(lane) * a.culled_stride] : 0u;
+  uint32_t r[kExpandPer];
+#pragma unroll
+  for (uint32_t j = 0; j < kExpandPer; ++j) {
+    const uint32_t pos = base + j * kExpandThreads + tid;
+    r[j] = pos < n_sorted ? a.rect32[pos] : 0u;
+  }
+  const uint32_t live = a.n - static_cast<uint32_t>(__builtin_amdgcn_readlane(wave_inclusive_scan<uint32_t>(c), kWave - 1));
   unsigned long long v = 0;
 #pragma unroll
   for (uint32_t j = 0; j < kExpandPer; ++j) {
     const uint32_t pos = base + j * kExpandThreads + tid;
-    if (pos < n_sorted) {
-      const uint32_t r = a.rect32[pos];
-      const uint32_t w = a.key[pos] != 0xFFFFFFFFu ? ((r >> 16) & 0xFFu) + 1u : 0u;
-      v += w * (((r >> 24) & 0xFFu) + 1u);
-    }
+    if (pos < n_sorted && pos < live) v += (((r[j] >> 16) & 0xFFu) + 1u) * (((r[j] >> 24) & 0xFFu) + 1u);
   }
   const unsigned long long total = block_reduce_sum<unsigned long long, kExpandThreads>(v, s_tmp64);
   if (tid == 0) wg_totals[blockIdx.x] = total;

@@ -242,6 +242,11 @@ struct ExpandArgs {
   // written by k_expand_totals beforehand; each workgroup then sums those
   // before it instead of looking back (NULL: look-back)
   const unsigned long long* wg_totals;
+  // with wg_totals: the depth histograms' culled words (digit 255 of the top
+  // byte, kHistCopies of them culled_stride apart); the depth-sorted
+  // Gaussians from n minus their sum on are the culled ones
+  const uint32_t* culled;
+  uint32_t culled_stride;
 };
 
 hipError_t launch_put_table(const TableChunk& c, FrameInfo* table, hipStream_t s);

@@ -631,7 +631,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   for (uint32_t f = 0; f < lay.n_frames; ++f)
     small_rects = small_rects && io.host_table[f].tiles_x <= 256 && io.host_table[f].tiles_y <= 256;
   const bool pack = small_rects && (lay.n <= (1u << 23) || lay.n_frames == 1);
-  uint32_t* rect32 = pack ? at<uint32_t>(ws, lay.rect) : nullptr;
+  // not carried but small: packed all the same, by index, so that expand
+  // gathers 4 B per Gaussian and a frame's rectangles stay in cache longer
+  const bool gather32 = small_rects && !pack && o.algorithm != SS_ALGO_TILE_FIRST;
+  uint32_t* rect32 = pack || gather32 ? at<uint32_t>(ws, lay.rect) : nullptr;
   uint32_t* rect32_alt = pack ? rect32 + lay.n : nullptr;
   CountKeysArgs ck{};
   ck.table = table;
@@ -698,7 +701,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   // in index order, as the count kernel wrote them
   const uint32_t* skey = lay.seg ? key_alt : key;
   const uint32_t* sval = lay.seg ? val_alt : val;
-  const uint32_t* srect32 = lay.seg ? rect32_alt : rect32;
+  const uint32_t* srect32 = !pack ? nullptr : lay.seg ? rect32_alt : rect32;
 
   // expand into pairs, then sort them by tile id alone
   const uint32_t P = lay.tpasses;
@@ -730,6 +733,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   e.val = sval;
   e.rect = ck.rect;
   e.rect32 = srect32;
+  e.rect32_idx = gather32 ? rect32 : nullptr;
   e.small_rects = small_rects;
   e.capacity = lay.capacity;
   e.keys = bk[0];

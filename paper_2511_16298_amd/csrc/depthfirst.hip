@@ -388,9 +388,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
       const uint32_t f = a.n_frames == 1 ? 0u : frame_of(s_tab, a.n_frames, g);
       const uint32_t dep = a.key[pos];
       uint32_t w, h, x0, y0;
-      if (a.rect32 != nullptr) {
-        // packed, in depth order: read in sequence instead of gathered by index
-        const uint32_t r = a.rect32[pos];
+      if (a.rect32 != nullptr || a.rect32_idx != nullptr) {
+        // packed, in depth order: read in sequence instead of gathered by
+        // index; else gathered, 4 B instead of 8
+        const uint32_t r = a.rect32 != nullptr ? a.rect32[pos] : a.rect32_idx[g];
         const bool live = dep != 0xFFFFFFFFu;
         x0 = r & 0xFFu;
         y0 = (r >> 8) & 0xFFu;

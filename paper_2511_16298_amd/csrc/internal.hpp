@@ -213,6 +213,8 @@ struct ExpandArgs {
   const uint64_t* rect;     // by global index
   const uint32_t* rect32;   // or packed rectangles in depth order (sorted with the keys; a
                             // culled Gaussian's is ignored: its key is 0xFFFFFFFF)
+  const uint32_t* rect32_idx; // or packed rectangles by global index (gathered; the same
+                              // layout, a culled one's likewise ignored)
   bool small_rects;         // every frame has at most 256 tiles per axis
   uint32_t capacity;
   uint64_t* keys;           // out pairs: global tile << 32 | depth bits (or packed items)

@@ -785,7 +785,7 @@ hipError_t launch_pass(const PassArgs& a, int key_bytes, int radix_bits, int ite
   SS_PASS_CASE(uint64_t, 5, 16, 512) SS_PASS_CASE(uint64_t, 5, 8, 512)
   SS_PASS_CASE(uint64_t, 4, 16, 512) SS_PASS_CASE(uint64_t, 4, 8, 512)
   // the Gaussian depth sort's shapes
-  SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512)
+  SS_PASS_CASE(uint32_t, 8, 16, 512) SS_PASS_CASE(uint32_t, 8, 8, 512) SS_PASS_CASE(uint32_t, 8, 4, 1024)
 #undef SS_PASS_CASE
   // packed pairs: 512-thread shapes, 4..8-bit digits
 #define SS_PACKED_CASE(RB, IT)                                                      \

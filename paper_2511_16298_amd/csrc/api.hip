@@ -177,7 +177,7 @@ struct DfLayout {
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;
   size_t block_total = 0, block_frame = 0;
-  size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_t = 0,
+  size_t scalars = 0, bad = 0, totals = 0, scan_lb = 0, expand_lb = 0, hist_d = 0, hist_f = 0, hist_t = 0,
          lb_d = 0, lb_t = 0, clear_end = 0, table = 0, bases_t = 0, rect = 0, key = 0, val = 0,
          key_alt = 0, val_alt = 0, alt_keys = 0, alt_vals = 0, seg_base = 0, seg_wgs = 0, tickets = 0, wg_totals = 0,
          total = 0;
@@ -229,7 +229,7 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.packed = use_packed(L.tile_bits, L.tpasses, L.idx_bits, n, L.tcfg, L.trb);
   // Segmented batch: frame-local tiles (at most 2^16 per frame, as the
   // expansion's 16-bit tile field holds) in packed pairs, without dropping
-  // culled Gaussians (the frame pass places frame f at its first Gaussian)
+  // culled Gaussians (the segmented depth sort places frame f at its first Gaussian)
   if (n_frames > 1 && (o.flags & SS_FLAG_DROP_CULLED) == 0) {
     const uint32_t lbits = ceil_log2(max_frame_tiles);
     if (lbits >= 1 && lbits <= 16) {
@@ -243,7 +243,9 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
       }
     }
   }
-  // a segmented pass has up to one partial workgroup per frame
+  // a segmented pass has up to one partial workgroup per frame (the depth
+  // sort's too: it sorts every frame's Gaussians apart)
+  if (L.seg) L.dblocks += n_frames;
   L.tblocks = (capacity + L.tcfg.tile() - 1) / L.tcfg.tile() + (L.seg ? n_frames : 0u);
   const uint32_t hframes = L.seg ? n_frames : 1u;  // tile histograms and bases per frame
   L.eblocks = n == 0 ? 1u : (n + kExpandTile - 1) / kExpandTile;  // workgroup 0 also finishes the totals
@@ -259,10 +261,13 @@ DfLayout make_df_layout(uint32_t n, uint32_t n_frames, uint32_t capacity, uint64
   L.scan_lb = off;   off = align_up(off + static_cast<size_t>(L.count_blocks) * sizeof(uint64_t));
   L.expand_lb = off; off = align_up(off + static_cast<size_t>(L.eblocks) * sizeof(uint64_t));
   L.hist_d = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * 4 * 256 * sizeof(uint32_t));
+  // segmented: the depth-digit histograms per frame too
+  L.hist_f = off;    off = align_up(off + (L.seg ? static_cast<size_t>(kHistCopies) * n_frames * 4 * 256 : 0u) *
+                                            sizeof(uint32_t));
   L.hist_t = off;    off = align_up(off + static_cast<size_t>(kHistCopies) * hframes * L.tpasses * L.tbins *
                                             sizeof(uint32_t));
-  // four depth passes, and the frame pass when segmented
-  L.lb_d = off;      off = align_up(off + static_cast<size_t>(L.seg ? 5 : 4) * L.dblocks * 256 * sizeof(uint32_t));
+  // four depth passes
+  L.lb_d = off;      off = align_up(off + static_cast<size_t>(4) * L.dblocks * 256 * sizeof(uint32_t));
   // packed: the last tile pass's look-back words are 64-bit (one more slice)
   L.lb_t = off;      off = align_up(off + static_cast<size_t>(L.tpasses + (L.packed ? 1 : 0)) * L.tblocks * L.tbins *
                                             sizeof(uint32_t));
@@ -375,9 +380,9 @@ struct PassChain {
   // keys with pairs (for packed pairs) at depth_top_out, from hist_top
   uint32_t* depth_top_out;
   const uint32_t* hist_top;
-  // the depth sort's frame pass (32-bit keys): digit = frame of the value
-  bool frame_digit;
-  const FrameInfo* table;     // frame pass, and the segmented unpacking pass
+  // the segmented depth sort (32-bit keys): every frame's Gaussians apart
+  bool depth_seg;
+  const FrameInfo* table;     // the segmented depth sort and unpacking pass
   uint32_t n_frames;
   // segmented 64-bit passes (PassArgs): per-frame workgroups, pairs, and
   // histograms and bases frame_stride apart
@@ -429,7 +434,7 @@ ss_status run_chain(Launcher& L, uint32_t kind, const PassChain& c, hipStream_t 
       a.spin_limit = c.spin_limit;
       a.fault = c.fault;
       a.tickets = c.tickets ? c.tickets + p : nullptr;
-      a.frame_digit = c.frame_digit;
+      a.depth_seg = c.depth_seg;
       a.table = c.table;
       a.n_frames = c.n_frames;
       if (c.seg_wgs != nullptr) {
@@ -647,6 +652,7 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
   ck.val = val;
   ck.tiles_touched = io.tiles_touched;
   ck.hist = at<uint32_t>(ws, lay.hist_d);
+  ck.frame_hist = lay.seg ? at<uint32_t>(ws, lay.hist_f) : nullptr;
   ck.totals = at<unsigned long long>(ws, lay.totals);
   ck.block_total = at<unsigned long long>(ws, lay.block_total);
   ck.block_frame = at<uint32_t>(ws, lay.block_frame);
@@ -661,7 +667,10 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
 
   // stable sort of the Gaussians by depth: key -> alt -> key -> alt -> key;
   // culled ones (no pairs) sort last, or, with SS_FLAG_DROP_CULLED and when
-  // they are many, the first pass drops them and the others sort the rest
+  // they are many, the first pass drops them and the others sort the rest.
+  // Segmented (batches): each frame's Gaussians apart, from its own
+  // histograms, so that they end frame-major, in depth order, culled last,
+  // at the frame's first Gaussian.
   if (!tile_first) {
     const void* ks[4] = {key, key_alt, key, key_alt};
     const uint32_t* vs[4] = {val, val_alt, val, val_alt};
@@ -677,32 +686,21 @@ ss_status run_depth_first(Launcher& L, const DfLayout& lay, const Options& o, co
       c.depth_top_out = scal + 5;
       c.hist_top = ck.hist + 3 * 256;
     }
-    c.spin_limit = o.spin_limit;
-    SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
-  }
-  // segmented: a stable pass by frame, key -> alt (each frame's Gaussians
-  // stay in depth order, culled last, at the frame's first Gaussian)
-  if (lay.seg) {
-    const void* ks[1] = {key};
-    const uint32_t* vs[1] = {val};
-    void* kd[1] = {key_alt};
-    uint32_t* vd[1] = {val_alt};
-    const uint32_t* ps[1] = {rect32};
-    uint32_t* pd[1] = {rect32_alt};
-    PassChain c{1, 4, 0, 8, lay.dcfg, lay.dblocks, ks, vs, kd, vd, nullptr, lay.n, d_status,
-                nullptr, ck.hist, 4 * 256, at<uint32_t>(ws, lay.lb_d) + static_cast<size_t>(4) * lay.dblocks * 256,
-                0, nullptr, nullptr, pack ? ps : nullptr, pack ? pd : nullptr};
-    c.frame_digit = true;
-    c.table = table;
-    c.n_frames = lay.n_frames;
+    if (lay.seg) {
+      c.hist = ck.frame_hist;
+      c.hist_stride = lay.n_frames * 4 * 256;
+      c.depth_seg = true;
+      c.table = table;
+      c.n_frames = lay.n_frames;
+    }
     c.spin_limit = o.spin_limit;
     SS_TRY(run_chain(L, SS_KERNEL_DEPTH_PASS, c, s));
   }
   // the Gaussians in (frame-major when segmented) depth order; tile-first:
   // in index order, as the count kernel wrote them
-  const uint32_t* skey = lay.seg ? key_alt : key;
-  const uint32_t* sval = lay.seg ? val_alt : val;
-  const uint32_t* srect32 = !pack ? nullptr : lay.seg ? rect32_alt : rect32;
+  const uint32_t* skey = key;
+  const uint32_t* sval = val;
+  const uint32_t* srect32 = pack ? rect32 : nullptr;
 
   // expand into pairs, then sort them by tile id alone
   const uint32_t P = lay.tpasses;

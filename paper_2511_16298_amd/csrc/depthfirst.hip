@@ -134,6 +134,14 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
       } else {
         tsum += kCulledOne;
       }
+      // per-frame histograms: a workgroup inside one frame flushes its LDS
+      // copy below; one that spans frames (at most one per frame boundary
+      // for frames of a workgroup or more) adds each Gaussian here
+      if (a.frame_hist != nullptr && !one_frame) {
+        uint32_t* fh = a.frame_hist + (static_cast<size_t>(blockIdx.x % kHistCopies) * a.n_frames + f) * 4 * 256;
+#pragma unroll
+        for (uint32_t p = 0; p < 4; ++p) atomicAdd(&fh[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+      }
     }
     if (a.tiles_touched) a.tiles_touched[g] = cnt;
     if (!one_frame && cnt) atomicAdd(&s_fm[f], static_cast<unsigned long long>(cnt));
@@ -159,9 +167,16 @@ __global__ __launch_bounds__(kCountKeysThreads) void k_count_keys(CountKeysArgs 
     for (uint32_t p = 0; p < 4; ++p) s_hist[p * 256 + 255] += culled;
   __syncthreads();
   uint32_t* gh = a.hist + static_cast<size_t>(blockIdx.x % kHistCopies) * 4 * 256;
+  uint32_t* fh = nullptr;
+  if (a.frame_hist != nullptr && one_frame)
+    fh = a.frame_hist + (static_cast<size_t>(blockIdx.x % kHistCopies) * a.n_frames +
+                         frame_of(s_tab, a.n_frames, base)) * 4 * 256;
   for (uint32_t i = tid; i < 4 * 256; i += kCountKeysThreads) {
     const uint32_t v = s_hist[i];
-    if (v) atomicAdd(&gh[i], v);
+    if (v) {
+      atomicAdd(&gh[i], v);
+      if (fh != nullptr) atomicAdd(&fh[i], v);
+    }
   }
 }
 

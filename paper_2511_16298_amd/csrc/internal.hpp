@@ -120,7 +120,7 @@ struct PassArgs {
   uint32_t low_bits;          // tile bits below this pass's digit
   uint64_t* lookback64;
   // Segmented 64-bit passes (a batch whose pairs are frame-major, after the
-  // depth sort's frame pass): no workgroup's tile straddles two frames, a frame's
+  // segmented depth sort): no workgroup's tile straddles two frames, a frame's
   // workgroups look back only among themselves, digit bases are per frame.
   // The chain's first pass starts with seg_frames publishing workgroups, one
   // per frame.  hist: [copy][frame][pass][bins] (hist_stride between copies),
@@ -130,9 +130,12 @@ struct PassArgs {
   uint32_t seg_frames;
   uint32_t bases_frame_stride;
   const FrameInfo* table;     // kPassUnpack, segmented: tile_base of each frame
-  // The depth sort's frame pass (32-bit keys): an item's digit is its frame,
-  // from its value (the Gaussian's global index) and the frames' gauss_base.
-  bool frame_digit;
+  // Segmented depth sort (32-bit keys, a batch): the Gaussians of every
+  // frame, [gauss_base, gauss_base + n) of the table, are sorted apart, in
+  // tiles of their own with a look-back chain of their own, from the
+  // frame's histograms (hist + frame * 4 * 256) and with digit bases from
+  // the frame's first Gaussian; the workgroups past the frames' tiles exit.
+  bool depth_seg;
   uint32_t n_frames;
   // Bounded waits: polls before SS_ERR_TIMEOUT (kSpinLimit when 0).  fault:
   // SS_FAULT_* test hook (SS_FAULT_WITHHOLD_BASES: the chain's publishing
@@ -175,6 +178,8 @@ struct CountKeysArgs {
   uint32_t* val;            // out [n]: global Gaussian index
   uint32_t* tiles_touched;  // optional [n]
   uint32_t* hist;           // zeroed [kHistCopies][4][256] depth digit histograms
+  uint32_t* frame_hist;     // or NULL; else also zeroed [kHistCopies][n_frames][4][256]: the
+                            // same per frame (the segmented depth sort)
   unsigned long long* totals;  // zeroed [1 + n_frames]: pairs per frame at [1 + f]
                                // (only workgroups that span several frames add here)
   unsigned long long* block_total;  // [nblocks] pairs of a one-frame workgroup, else 0

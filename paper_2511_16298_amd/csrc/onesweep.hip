@@ -47,8 +47,8 @@ struct PassSmem {
   // kPassUnpack: per digit, 1 + the largest tile part below the digit among
   // the pairs of earlier workgroups (0: none)
   uint32_t lbx[MODE == kPassUnpack ? (1 << RB) : 1];
-  // segmented 64-bit passes: each frame's first tile workgroup; the depth
-  // sort's frame pass: each frame's first Gaussian
+  // segmented 64-bit passes: each frame's first tile workgroup; the
+  // segmented depth sort: each frame's first Gaussian
   uint32_t aux[kMaxFrames + 1];
   unsigned long long tmp[THREADS / kWave];
   uint32_t timeout;
@@ -62,7 +62,9 @@ struct PassSmem {
 struct SegCtx {
   uint32_t first;
   const uint32_t* bases;
-  uint32_t tile_base;
+  uint32_t tile_base;  // 64-bit unpacking: the frame's first tile; 32-bit
+                       // segmented: the frame's first Gaussian
+  uint32_t hist_off;   // 32-bit segmented: the frame's histograms
 };
 
 // Largest f < n_frames with first[f] <= x (first[] non-decreasing).
@@ -93,8 +95,8 @@ __device__ __forceinline__ uint32_t key_digit(K k, uint32_t shift) {
 // (32-bit keys): culled items an earlier pass dropped, all of digit 255.
 template <typename K, int RB, int ITEMS, int THREADS, int MODE, bool FULL>
 __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITEMS, THREADS, MODE>& sm,
-                                          uint32_t base, uint32_t n, uint32_t dropped, K (&k)[ITEMS],
-                                          uint32_t (&v)[ITEMS], uint32_t (&dg)[ITEMS]) {
+                                          uint32_t base, uint32_t n, uint32_t dropped, uint32_t hist_off,
+                                          K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t (&dg)[ITEMS]) {
   constexpr int BINS = 1 << RB;
   const int tid = threadIdx.x;
   // 32-bit keys: global total of digit tid (summed over the histogram
@@ -104,15 +106,10 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
   if constexpr (sizeof(K) == 4) {
     if (tid < BINS) {
       uint32_t gtot = 0;
-      if (a.frame_digit) {
-        // the frame pass: digit f holds the frame's Gaussians (none dropped)
-        gtot = static_cast<uint32_t>(tid) < a.n_frames ? sm.aux[tid + 1] - sm.aux[tid] : 0u;
-      } else {
 #pragma unroll
-        for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + tid];
-        // culled Gaussians dropped by an earlier pass (all of digit 255)
-        if (tid == BINS - 1) gtot -= dropped;
-      }
+      for (uint32_t c = 0; c < kHistCopies; ++c) gtot += a.hist[static_cast<size_t>(c) * a.hist_stride + hist_off + tid];
+      // culled Gaussians dropped by an earlier pass (all of digit 255)
+      if (tid == BINS - 1) gtot -= dropped;
       sm.gofs[tid] = gtot;
     }
   }
@@ -128,8 +125,7 @@ __device__ __forceinline__ void pass_load(const PassArgs& a, PassSmem<K, RB, ITE
     if (FULL || idx < n) {
       k[j] = kin[idx];
       v[j] = MODE == kPassKV ? a.vin[idx] : 0u;
-      dg[j] = sizeof(K) == 4 && a.frame_digit ? segment_of(sm.aux, a.n_frames, v[j])
-                                              : key_digit<K, MODE, RB>(k[j], a.shift);
+      dg[j] = key_digit<K, MODE, RB>(k[j], a.shift);
     } else {
       k[j] = 0;
       v[j] = 0;
@@ -221,22 +217,16 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
   if (tid < BINS) {
     sm.dstart[tid] = lexcl;
     sm.cnt[tid] = bcnt;
-    if constexpr (sizeof(K) == 4) sm.gofs[tid] = gbase;
+    if constexpr (sizeof(K) == 4) sm.gofs[tid] = gbase + sc.tile_base;
   }
   __syncthreads();
 
   // ---- permute the keys into digit order in LDS ----
-  // (the frame pass's digit is not in the key: it parks each slot's digit
-  // in the buffer's second half, free until the values go through it)
-  const bool frame_digit = sizeof(K) == 4 && a.frame_digit;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (FULL || dg[j] < BINS) {
       pos[j] += sm.dstart[dg[j]] + wc[dg[j]];
       sm.buf[pos[j]] = k[j];
-      if constexpr (sizeof(K) == 4) {
-        if (frame_digit) sm.buf[TILE + pos[j]] = static_cast<K>(dg[j]);
-      }
     }
   }
   // 32-bit keys: the second value, loaded now (into the registers the keys
@@ -379,10 +369,7 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     dst[j] = 0xFFFFFFFFu;
     if (FULL || i < valid_n) {
       const K key = sm.buf[i];
-      uint32_t d = frame_digit ? 0u : key_digit<K, MODE, RB>(key, a.shift);
-      if constexpr (sizeof(K) == 4) {
-        if (frame_digit) d = static_cast<uint32_t>(sm.buf[TILE + i]);
-      }
+      const uint32_t d = key_digit<K, MODE, RB>(key, a.shift);
       const uint32_t o = sm.gofs[d] + i;
       if (o < n) {
         if constexpr (kStreamStores) __builtin_nontemporal_store(key, &kout[o]);
@@ -433,7 +420,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, PassSmem<K, RB, ITE
   K k[ITEMS];
   uint32_t v[ITEMS];
   uint32_t dg[ITEMS];
-  pass_load<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, base, n, dropped, k, v, dg);
+  pass_load<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, base, n, dropped, sc.hist_off, k, v, dg);
   pass_rest<K, RB, ITEMS, THREADS, MODE, FULL>(a, sm, t, base, n, k, v, dg, sc);
 }
 
@@ -560,7 +547,7 @@ __device__ __forceinline__ bool onesweep_body(const PassArgs& a, PassSmem<K, RB,
   // bases (dispatched first, it has them out before any tile needs them, and
   // no tile's look-back waits on it); tile b is then workgroup b + 1.  A
   // segmented chain has one publishing workgroup per frame.
-  SegCtx sc{0u, a.bases, 0u};
+  SegCtx sc{0u, a.bases, 0u, 0u};
   uint32_t base = 0, end = n;
   if constexpr (sizeof(K) == 8) {
     const uint32_t publishers = a.publish_passes == 0 ? 0u : a.seg_wgs != nullptr ? a.seg_frames : 1u;
@@ -588,10 +575,28 @@ __device__ __forceinline__ bool onesweep_body(const PassArgs& a, PassSmem<K, RB,
     }
   } else {
     base = t * TILE;
-    if (a.frame_digit) {
-      // frames' first Gaussians, then all of them
+    if (a.depth_seg) {
+      // this workgroup's frame and its tile inside the frame's Gaussians:
+      // the frames' first tile workgroups by a scan of their tile counts
+      // (parked in the permute buffer, free until the tile is ranked)
+      static_assert(THREADS >= kMaxFrames, "one frame per thread in the scan");
+      uint32_t* s_wgs = reinterpret_cast<uint32_t*>(sm.buf);
       for (uint32_t i = tid; i <= a.n_frames; i += THREADS) sm.aux[i] = i < a.n_frames ? a.table[i].gauss_base : n;
       __syncthreads();
+      const uint32_t nf = static_cast<uint32_t>(tid) < a.n_frames ? sm.aux[tid + 1] - sm.aux[tid] : 0u;
+      uint32_t tiles_all;
+      const uint32_t first_wg = block_exclusive_scan<uint32_t, THREADS>(
+          (nf + TILE - 1) / TILE, reinterpret_cast<uint32_t*>(sm.tmp), tiles_all);
+      if (static_cast<uint32_t>(tid) <= a.n_frames) s_wgs[tid] = static_cast<uint32_t>(tid) < a.n_frames ? first_wg : tiles_all;
+      __syncthreads();
+      if (t >= tiles_all) return false;  // more workgroups than the frames' tiles (uniform)
+      const uint32_t f = segment_of(s_wgs, a.n_frames, t);
+      sc.first = s_wgs[f];
+      sc.tile_base = sm.aux[f];
+      sc.hist_off = f * 4u * 256u;
+      base = sm.aux[f] + (t - s_wgs[f]) * TILE;
+      end = sm.aux[f + 1];
+      __syncthreads();  // s_wgs is the permute buffer
     }
   }
   if (base >= end) return false;  // uniform over the workgroup
@@ -607,7 +612,7 @@ __device__ __forceinline__ bool onesweep_body(const PassArgs& a, PassSmem<K, RB,
     K k[ITEMS];
     uint32_t v[ITEMS];
     uint32_t dg[ITEMS];
-    pass_load<K, RB, ITEMS, THREADS, MODE, false>(a, sm, base, n, 0u, k, v, dg);
+    pass_load<K, RB, ITEMS, THREADS, MODE, false>(a, sm, base, n, 0u, 0u, k, v, dg);
     if (tid == 0) {
       // drop when the culled are more than n / 16 (the same decision in
       // every workgroup)

@@ -546,47 +546,59 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
 #pragma unroll
     for (uint32_t k = 0; k < kChunkPer; ++k) s_map[kChunkPer * tid + k] = static_cast<uint16_t>(max(m[k], prev));
     __syncthreads();
+    // one loop per (packed items, two tile passes), so that neither test is
+    // taken per pair
+    auto write_round = [&](auto packed_tag, auto two_tag) {
+      constexpr bool kPacked = decltype(packed_tag)::value, kTwo = decltype(two_tag)::value;
 #pragma unroll
-    for (uint32_t k = 0; k < kChunkPer; ++k) {
-      const uint32_t q = cb + k * kExpandThreads + tid;
-      if (q < total) {
-        const uint32_t i = static_cast<uint32_t>(s_map[q - cb]) - 1u;
-        if (i >= kExpandTile) continue;  // every slot has an owner; kept for safety
-        const uint32_t kk = q - s_off[i];
-        const uint4 gi = s_info[i];
-        const uint32_t org = gi.x, wt = gi.y;
-        const uint32_t w = wt & 0xFFFFu;
-        // row of pair kk in the w-wide rectangle.  Rectangles of at most
-        // 256 x 256 tiles (kk < 2^16): floor((kk + 1/2) / w) in fp32 is exact,
-        // its true value lying at least 1/512 from an integer while the
-        // rounding errors stay below 256 * 2^-21.
-        const uint32_t dy = SMALL ? static_cast<uint32_t>((static_cast<float>(kk) + 0.5f) *
-                                                                  __builtin_amdgcn_rcpf(static_cast<float>(w)))
-                                          : kk / w;
-        // every factor is below 2^24 (w, dy, tiles_x < 2^16): 24-bit products
-        const uint32_t dx = kk - __umul24(dy, w);
-        const uint32_t tile = (SEG ? org & 0xFFFFu : org) + __umul24(dy, wt >> 16) + dx;
-        if (a.packed) {
-          // the tile field lies in the high word (tile_shift >= 32)
-          keys[q] = (static_cast<uint64_t>((tile << (a.pk.tile_shift - 32)) | gi.w) << 32) | gi.z;
-        } else {
-          keys[q] = (static_cast<uint64_t>(tile) << 32) | gi.z;
-          vals[q] = gi.w;
-        }
-        uint32_t* h = s_hist;
-        if (SEG) {
-          const uint32_t f = org >> 16;
-          h = f == f_lo ? s_hist
-              : f == f_hi ? s_hist + hframe
-                          : a.hist + (static_cast<size_t>(ticket % kHistCopies) * a.n_frames + f) * hframe;
-        }
-        if (a.npasses == 2) {  // the usual count (up to 16 tile bits), without loop control
-          atomicAdd(&h[tile & (bins - 1)], 1u);
-          atomicAdd(&h[bins + ((tile >> rb) & (bins - 1))], 1u);
-        } else {
-          for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&h[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+      for (uint32_t k = 0; k < kChunkPer; ++k) {
+        const uint32_t q = cb + k * kExpandThreads + tid;
+        if (q < total) {
+          const uint32_t i = static_cast<uint32_t>(s_map[q - cb]) - 1u;
+          if (i >= kExpandTile) continue;  // every slot has an owner; kept for safety
+          const uint32_t kk = q - s_off[i];
+          const uint4 gi = s_info[i];
+          const uint32_t org = gi.x, wt = gi.y;
+          const uint32_t w = wt & 0xFFFFu;
+          // row of pair kk in the w-wide rectangle.  Rectangles of at most
+          // 256 x 256 tiles (kk < 2^16): floor((kk + 1/2) / w) in fp32 is exact,
+          // its true value lying at least 1/512 from an integer while the
+          // rounding errors stay below 256 * 2^-21.
+          const uint32_t dy = SMALL ? static_cast<uint32_t>((static_cast<float>(kk) + 0.5f) *
+                                                                    __builtin_amdgcn_rcpf(static_cast<float>(w)))
+                                            : kk / w;
+          // every factor is below 2^24 (w, dy, tiles_x < 2^16): 24-bit products
+          const uint32_t dx = kk - __umul24(dy, w);
+          const uint32_t tile = (SEG ? org & 0xFFFFu : org) + __umul24(dy, wt >> 16) + dx;
+          if (kPacked) {
+            // the tile field lies in the high word (tile_shift >= 32)
+            keys[q] = (static_cast<uint64_t>((tile << (a.pk.tile_shift - 32)) | gi.w) << 32) | gi.z;
+          } else {
+            keys[q] = (static_cast<uint64_t>(tile) << 32) | gi.z;
+            vals[q] = gi.w;
+          }
+          uint32_t* h = s_hist;
+          if (SEG) {
+            const uint32_t f = org >> 16;
+            h = f == f_lo ? s_hist
+                : f == f_hi ? s_hist + hframe
+                            : a.hist + (static_cast<size_t>(ticket % kHistCopies) * a.n_frames + f) * hframe;
+          }
+          if (kTwo) {  // the usual count (up to 16 tile bits), without loop control
+            atomicAdd(&h[tile & (bins - 1)], 1u);
+            atomicAdd(&h[bins + ((tile >> rb) & (bins - 1))], 1u);
+          } else {
+            for (uint32_t p = 0; p < a.npasses; ++p) atomicAdd(&h[p * bins + ((tile >> (rb * p)) & (bins - 1))], 1u);
+          }
         }
       }
+    };
+    if (a.packed) {
+      if (a.npasses == 2) write_round(std::true_type{}, std::true_type{});
+      else write_round(std::true_type{}, std::false_type{});
+    } else {
+      if (a.npasses == 2) write_round(std::false_type{}, std::true_type{});
+      else write_round(std::false_type{}, std::false_type{});
     }
     __syncthreads();
   }

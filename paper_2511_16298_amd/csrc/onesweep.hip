@@ -324,36 +324,43 @@ __device__ __forceinline__ void pass_rest(const PassArgs& a, PassSmem<K, RB, ITE
     const bool trimmed = packed_depth_trimmed(top_max, top_min, a.packed, &ebase);
     const uint64_t pmask = (1ull << S) - 1;
     const uint32_t imask = ib >= 32 ? ~0u : (1u << ib) - 1u;
+    // one loop per form of the depth field, so that neither carries the
+    // other's test per item
+    auto write_all = [&](auto trim) {
+      constexpr bool kTrimmed = decltype(trim)::value;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const uint32_t i = j * THREADS + tid;
-      if (FULL || i < valid_n) {
-        const uint64_t item = sm.buf[i];
-        const uint32_t d = key_digit<K, MODE, RB>(item, a.shift);
-        const uint32_t o = sm.gofs[d] + i;
-        if (o < n) {
-          const uint32_t tile = sc.tile_base + (static_cast<uint32_t>(item >> 32) >> (S - 32));
-          const uint64_t payload = item & pmask;
-          const uint32_t hi = static_cast<uint32_t>(payload >> ib);
-          const uint32_t dbits = trimmed ? hi + ebase : a.packed.depth_sorted[hi];
-          kout[o] = (static_cast<uint64_t>(tile) << 32) | dbits;
-          a.vout[o] = static_cast<uint32_t>(payload) & imask;
-          // predecessor: the slot before, inside this digit's run; else the
-          // last pair of the digit in earlier workgroups; else (the digit's
-          // first pair overall) left to k_ranges_fix
-          int64_t tp = -1;
-          bool known = true;
-          if (i > sm.dstart[d]) {
-            tp = static_cast<int64_t>(sc.tile_base + (static_cast<uint32_t>(sm.buf[i - 1] >> 32) >> (S - 32)));
-          } else {
-            const uint32_t lx = sm.lbx[d];
-            known = lx != 0;
-            tp = sc.tile_base + ((static_cast<int64_t>(d) << a.low_bits) | static_cast<int64_t>(lx - 1u));
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t i = j * THREADS + tid;
+        if (FULL || i < valid_n) {
+          const uint64_t item = sm.buf[i];
+          const uint32_t d = key_digit<K, MODE, RB>(item, a.shift);
+          const uint32_t o = sm.gofs[d] + i;
+          if (o < n) {
+            const uint32_t tile = sc.tile_base + (static_cast<uint32_t>(item >> 32) >> (S - 32));
+            const uint64_t payload = item & pmask;
+            const uint32_t hi = static_cast<uint32_t>(payload >> ib);
+            const uint32_t dbits = kTrimmed ? hi + ebase : a.packed.depth_sorted[hi];
+            kout[o] = (static_cast<uint64_t>(tile) << 32) | dbits;
+            a.vout[o] = static_cast<uint32_t>(payload) & imask;
+            // predecessor: the slot before, inside this digit's run; else the
+            // last pair of the digit in earlier workgroups; else (the digit's
+            // first pair overall) left to k_ranges_fix
+            int64_t tp = -1;
+            bool known = true;
+            if (i > sm.dstart[d]) {
+              tp = static_cast<int64_t>(sc.tile_base + (static_cast<uint32_t>(sm.buf[i - 1] >> 32) >> (S - 32)));
+            } else {
+              const uint32_t lx = sm.lbx[d];
+              known = lx != 0;
+              tp = sc.tile_base + ((static_cast<int64_t>(d) << a.low_bits) | static_cast<int64_t>(lx - 1u));
+            }
+            if (known && tp != static_cast<int64_t>(tile)) range_boundary(a.ranges, tp, tile, o);
           }
-          if (known && tp != static_cast<int64_t>(tile)) range_boundary(a.ranges, tp, tile, o);
         }
       }
-    }
+    };
+    if (trimmed) write_all(std::true_type{});
+    else write_all(std::false_type{});
     return;
   }
   // Packed pairs in 16-item tiles (the shape for 2^23 pairs and more, which

@@ -28,12 +28,20 @@ def outputs(w, h, n, capacity, dev):
     return o, c
 
 
-@pytest.mark.parametrize("order", [("fullhd-1m", "small-256x256")])
+# the second case keeps both calls on the multi-kernel path (a full-HD
+# frame of 3x10^5 Gaussians after one of 10^6), so the smaller call runs in
+# the array the larger one left behind
+WORKLOADS = dict(synth.FRAME_WORKLOADS)
+WORKLOADS["fullhd-300k"] = (synth.scaled(synth.FRAME_WORKLOADS["fullhd-1m"][0], 300_000),
+                            synth.FRAME_WORKLOADS["fullhd-1m"][1] + 17)
+
+
+@pytest.mark.parametrize("order", [("fullhd-1m", "small-256x256"), ("fullhd-1m", "fullhd-300k")])
 def test_noalloc_equals_sort_frame_twice(order):
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
     for name in order:
-        spec, seed = synth.FRAME_WORKLOADS[name]
+        spec, seed = WORKLOADS[name]
         rec = synth.make_frame(spec, seed)
         d = ss.records_to_device(rec, dev)
         _, _, m_t, s_t = ss.count_pairs(d, spec.width, spec.height)

@@ -169,10 +169,11 @@ struct DfLayout {
   // bits) | depth field << idx_bits | index
   bool packed = false;
   uint32_t idx_bits = 0;
-  // Segmented batch (several frames): after the depth sort a stable pass by
-  // frame makes the Gaussians frame-major, so each frame's pairs come out
-  // contiguous and the tile passes sort every frame on its own, on
-  // frame-local tile ids (tile_bits then counts the largest frame's tiles).
+  // Segmented batch (several frames): the depth sort orders every frame's
+  // Gaussians apart, inside the frame's own index range, so each frame's
+  // pairs come out contiguous and the tile passes sort every frame on its
+  // own, on frame-local tile ids (tile_bits then counts the largest frame's
+  // tiles).
   bool seg = false;
   PassCfg dcfg, tcfg;
   uint32_t dblocks = 0, tblocks = 0, eblocks = 0, count_blocks = 0, ck_blocks = 0;

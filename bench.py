@@ -56,9 +56,8 @@ def parse():
     p.add_argument("--bands", type=int, default=8, help="tile-row bands = GPUs of the sharded frame (shard-*)")
     p.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per rate (serve)")
     p.add_argument("--serve-rates", default="200,1000,3000,6000,12000", help="requests per second (serve)")
-    p.add_argument("--serve-closed-seconds", type=float, default=0.0,
-                   help="closed-loop run per mode (serve; 0: skip).  Off by default: with the current "
-                        "kernels the batched closed loop's last rounds end in SS_ERR_TIMEOUT (cause open)")
+    p.add_argument("--serve-closed-seconds", type=float, default=10.0,
+                   help="closed-loop run per mode (serve; 0: skip)")
     p.add_argument("--serve-outstanding", type=int, default=48,
                    help="requests kept in flight by the closed loop (serve)")
     p.add_argument("--arena-gib", type=float, default=64.0, help="HBM budget of the server (serve)")

@@ -22,6 +22,13 @@
  *    keys, values and ranges are unspecified.
  *  - No call blocks on the GPU unless documented.  No exceptions cross the
  *    ABI.  Calls that share a workspace must not overlap in time.
+ *  - The sort passes wait on earlier workgroups of their own launch
+ *    (decoupled look-back), and the GPU's XCDs dispatch their share of each
+ *    grid independently.  Two sorting calls whose kernels run at the same time
+ *    on one GPU (different streams) can therefore wait on each other in a
+ *    cycle, which the bounded wait ends with SS_ERR_TIMEOUT: issue a GPU's
+ *    sorting calls on one stream, or order them with events.  Kernels without
+ *    such waits (other work, the server's sizing counts) may overlap freely.
  */
 #ifndef SPLATSORT_H
 #define SPLATSORT_H
@@ -311,9 +318,11 @@ void ss_plan_destroy(ss_plan* plan);
  * host thread).  A scheduler thread owned by the server sizes the waiting
  * requests with one batched count, admits the longest FIFO prefix whose
  * round (workspace + outputs) fits the caller's arena now, and launches it
- * as one segmented sort (ss_sort_batch) on one of n_streams streams, so a
- * round can run while the next is being sized and launched (continuous
- * batching).  A request that could not fit even an empty arena completes
+ * as one segmented sort (ss_sort_batch).  Up to n_streams rounds are in
+ * flight at once, queued back to back on one stream the server owns (never
+ * side by side, see the conventions above); the sizing counts run on a second
+ * stream, so a round runs while the next is being sized and launched
+ * (continuous batching).  A request that could not fit even an empty arena completes
  * with SS_ERR_BUDGET; others wait for space.  Outputs stay in the arena until
  * ss_server_release; workspace is freed when the round completes.  With
  * max_batch_frames = 1 and n_streams = 1 the server is a one-request-at-a-

@@ -1,9 +1,20 @@
 // Serving: frame-sort requests arrive over time; a scheduler thread admits
 // them against an HBM budget (a caller-owned arena), packs the admitted ones
 // into one segmented sort per round (continuous batching: requests that
-// arrive while others run join the next round), runs rounds on several
-// streams so they overlap, and completes each request when its round's
-// event fires.  Results stay in the arena until the caller releases them.
+// arrive while others run join the next round), keeps up to n_streams
+// rounds in flight, and completes each request when its round's event
+// fires.  Results stay in the arena until the caller releases them.
+//
+// Rounds in flight are queued back to back on ONE in-order stream, never run
+// side by side: their passes wait on earlier workgroups (decoupled
+// look-back), and the eight XCDs dispatch their share of each grid on their
+// own, so two such kernels running at once can fill one XCD with waiting
+// workgroups of the first whose predecessor is queued on an XCD full of
+// waiting workgroups of the second, and the other way round: a circular
+// wait that only the bounded spin (SS_ERR_TIMEOUT) ends.  The sizing counts
+// (no inter-workgroup waits) run on their own stream and overlap the rounds;
+// results are read back on a third stream, so that a finished round's
+// read-back does not queue behind the round after it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -53,7 +64,7 @@ struct Round {
   std::vector<Request*> reqs;
   size_t ws_off = 0, ws_bytes = 0, out_off = 0, out_bytes = 0;
   uint32_t capacity = 0, total_tiles = 0;
-  int stream = -1;
+  int stream = -1;                 // the round's slot
   hipEvent_t done_event = nullptr;
   uint32_t unreleased = 0;
   // host copies read back at completion
@@ -75,9 +86,10 @@ struct ss_server {
   char* arena_ptr = nullptr;
   Arena arena;
   ss_server_desc desc{};
-  std::vector<hipStream_t> streams;
-  std::vector<bool> busy;
-  hipStream_t count_stream = nullptr;
+  hipStream_t sort_stream = nullptr;      // every round, in order
+  std::vector<bool> busy;                 // round slots (n_streams)
+  hipStream_t count_stream = nullptr;     // sizing counts
+  hipStream_t readback_stream = nullptr;  // completed rounds' small read-backs
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> pending;
@@ -165,7 +177,8 @@ void complete_round(ss_server* s, const std::shared_ptr<Round>& rd) {
   rd->frame_pairs.assign(n, 0);
   rd->frame_base.assign(n, 0);
   uint32_t sc[2] = {0, SS_ERR_HIP};
-  const hipStream_t st = s->streams[rd->stream];
+  // the round's event has fired: its outputs are complete
+  const hipStream_t st = s->readback_stream;
   bool ok = hipMemcpyAsync(rd->frame_pairs.data(), rd->d_frame_pairs, n * 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
             hipMemcpyAsync(rd->frame_base.data(), rd->d_frame_base, n * 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
             hipMemcpyAsync(sc, rd->d_scalars, 8, hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -332,7 +345,7 @@ void worker_loop(ss_server* s) {
         out.frame_pair_base = rd->d_frame_base;
         out.num_pairs = rd->d_scalars;
         out.status = rd->d_scalars + 1;
-        const hipStream_t st = s->streams[free_stream];
+        const hipStream_t st = s->sort_stream;
         ss_status ls = ss_sort_batch(frames.data(), static_cast<uint32_t>(frames.size()), &out,
                                      s->arena_ptr + ws_off, ws_b, st, &s->desc.options);
         if (ls == SS_OK && hipEventCreateWithFlags(&rd->done_event, hipEventDisableTiming) != hipSuccess)
@@ -390,19 +403,17 @@ ss_status ss_server_create(ss_server** server, void* arena, size_t arena_bytes, 
   s->arena.reset(arena_bytes & ~(kArenaAlign - 1));
   s->desc = *desc;
   s->desc.options = opts;
-  bool ok = hipStreamCreateWithFlags(&s->count_stream, hipStreamNonBlocking) == hipSuccess;
-  for (uint32_t i = 0; ok && i < desc->n_streams; ++i) {
-    hipStream_t st = nullptr;
-    ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
-    if (ok) s->streams.push_back(st);
-  }
+  const bool ok = hipStreamCreateWithFlags(&s->count_stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&s->sort_stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&s->readback_stream, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
-    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    if (s->readback_stream) (void)hipStreamDestroy(s->readback_stream);
+    if (s->sort_stream) (void)hipStreamDestroy(s->sort_stream);
     if (s->count_stream) (void)hipStreamDestroy(s->count_stream);
     delete s;
     return SS_ERR_HIP;
   }
-  s->busy.assign(s->streams.size(), false);
+  s->busy.assign(desc->n_streams, false);
   s->worker = std::thread(worker_loop, s);
   *server = s;
   return SS_OK;
@@ -486,8 +497,9 @@ void ss_server_destroy(ss_server* s) {
     s->cv_work.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
-  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-  if (s->count_stream) (void)hipStreamDestroy(s->count_stream);
+  (void)hipStreamDestroy(s->readback_stream);
+  (void)hipStreamDestroy(s->sort_stream);
+  (void)hipStreamDestroy(s->count_stream);
   delete s;
 }
 

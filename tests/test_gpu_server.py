@@ -50,7 +50,7 @@ def test_results_in_the_mix_equal_alone():
 def test_batch_sized_requests_in_the_mix_equal_alone(batch64):
     """Requests drawn from the batch distribution at full size (50k-2M
     Gaussians per frame, the served workload's frames), several rounds in
-    flight on two streams with up to 16 frames per round: every result equals
+    flight (two) with up to 16 frames per round: every result equals
     the oracle's result for that frame alone, pair for pair."""
     frames, refs = batch64
     sizes = np.array([len(r) for (_, _, r) in frames])

@@ -79,6 +79,40 @@ def test_batch_sized_requests_in_the_mix_equal_alone(batch64):
     srv.close()
 
 
+def test_closed_loop_with_rounds_in_flight_drains_ok(batch64):
+    """A closed loop of batch-sized requests (the served workload's frames,
+    50k-2M Gaussians) with 48 outstanding and two rounds in flight, then the
+    drain once submissions stop: every request ends OK (the drain's last
+    rounds once ended in SS_ERR_TIMEOUT while rounds ran side by side on two
+    streams), and every eighth result equals the oracle's for that frame."""
+    frames, refs = batch64
+    dev = [ss.records_to_device(r) for (_, _, r) in frames]
+    srv = ss.Server(24 << 30, max_batch_frames=64, n_streams=2)
+    order = [int(i) for i in np.random.default_rng(12).integers(0, len(frames), 240)]
+    q = [(srv.submit(dev[i], frames[i][0], frames[i][1]), i) for i in order[:48]]
+    nxt, done, big_rounds = 48, 0, 0
+    while q:
+        t, i = q.pop(0)
+        r = srv.wait(t)
+        assert r.status == 0, (done, _abi.status_string(r.status))
+        big_rounds += r.round_frames >= 8
+        if done % 8 == 0:
+            ref = refs[i]
+            assert r.num_pairs == ref.num_pairs, i
+            k, v, rg = srv.result_arrays(r, ref.num_tiles)
+            assert np.array_equal(k, ref.keys) and np.array_equal(v, ref.values) and np.array_equal(rg, ref.ranges), i
+        srv.release(t)
+        done += 1
+        if nxt < len(order):
+            j = order[nxt]
+            q.append((srv.submit(dev[j], frames[j][0], frames[j][1]), j))
+            nxt += 1
+    st = srv.stats()
+    assert done == len(order) and st["completed"] == len(order) and st["pending"] == 0 and st["arena_used"] == 0
+    assert big_rounds > 0, "no round of eight frames or more"
+    srv.close()
+
+
 def test_budget_rejects_what_can_never_fit_and_waits_otherwise():
     big = synth.make_frame(synth.scaled(synth.FULL_HD, 200_000), 3)
     small = frames_pool(6, 502, n_range=(2_000, 4_000))
